@@ -1,0 +1,161 @@
+"""Test infrastructure: the FP64 CPU oracle for |M|^2 (and its checks).
+
+Only tests, the smoke check and the benchmark's CPU-baseline leg use this
+package.  It shares no code with the GPU library and never imports it.
+
+The C++ source `oracle.cpp` is compiled with the host compiler into
+`liboracle.so` next to it (``build()``); loading builds it when it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+EEMUMU, GGTT, GGTTG, GGTTGG, GGTTGGG, GGGG = 0, 1, 2, 3, 4, 5
+NPAR = {EEMUMU: 4, GGTT: 4, GGTTG: 5, GGTTGG: 6, GGTTGGG: 7, GGGG: 4}
+ORDERED, DRESSED = 0, 1
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (-O2, OpenMP, no FMA contraction)."""
+    cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+           "-o", _LIB + ".tmp", _SRC]
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+            L = ctypes.CDLL(_LIB)
+            dp = ctypes.POINTER(ctypes.c_double)
+            ip = ctypes.POINTER(ctypes.c_int)
+            for name in ("oracle_me2", "oracle_me2_ld"):
+                f = getattr(L, name)
+                f.argtypes = [ctypes.c_int, dp, ctypes.c_double, ctypes.c_int64, dp, dp, ctypes.c_int, ctypes.c_int]
+                f.restype = ctypes.c_int
+            L.oracle_colour_matrix.argtypes = [ctypes.c_int, dp]
+            L.oracle_partial_amps.argtypes = [ctypes.c_int, dp, dp, ip, ctypes.c_int, dp]
+            L.oracle_dressed_amp.argtypes = [ctypes.c_int, dp, dp, ip, ip, ctypes.c_int, ctypes.c_int,
+                                             ctypes.c_int, ctypes.c_int, dp]
+            L.oracle_external.argtypes = [ctypes.c_int, dp, ctypes.c_double, ctypes.c_int, dp]
+            L.oracle_gamma.argtypes = [ctypes.c_int, dp]
+            L.oracle_su3.argtypes = [dp, dp]
+            L.oracle_ew.argtypes = [dp, dp]
+            L.oracle_iden.argtypes = [ctypes.c_int, dp]
+            _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def default_threads() -> int:
+    return max(1, len(os.sched_getaffinity(0)))
+
+
+def me2(process: int, momenta, card, alpha_s: float = 0.118, mode: int = ORDERED,
+        nthreads: int | None = None, extended: bool = False) -> np.ndarray:
+    """|M|^2 averaged over initial spins/colours and divided by the final-state symmetry factor."""
+    mom = np.ascontiguousarray(momenta, dtype=np.float64)
+    if mom.ndim != 3 or mom.shape[1] != NPAR[process] or mom.shape[2] != 4:
+        raise ValueError(f"momenta must be [nevt, {NPAR[process]}, 4]")
+    card = np.ascontiguousarray(card, dtype=np.float64)
+    out = np.empty(mom.shape[0], dtype=np.float64)
+    f = lib().oracle_me2_ld if extended else lib().oracle_me2
+    rc = f(process, _dp(card), float(alpha_s), mom.shape[0], _dp(mom), _dp(out), mode,
+           nthreads or default_threads())
+    if rc != 0:
+        raise ValueError(f"oracle_me2 failed with {rc}")
+    return out
+
+
+def colour_matrix(n: int) -> np.ndarray:
+    import math
+    k = math.factorial(n)
+    out = np.empty(k * k, dtype=np.float64)
+    if lib().oracle_colour_matrix(n, _dp(out)) != 0:
+        raise ValueError("bad n")
+    return out.reshape(k, k)
+
+
+def partial_amps(momentum, card, spins, gauge_leg: int = -1) -> np.ndarray:
+    import math
+    mom = np.ascontiguousarray(momentum, dtype=np.float64)
+    npar = mom.shape[0]
+    card = np.ascontiguousarray(card, dtype=np.float64)
+    sp = np.ascontiguousarray(spins, dtype=np.int32)
+    out = np.empty(2 * math.factorial(npar - 2), dtype=np.float64)
+    if lib().oracle_partial_amps(npar, _dp(card), _dp(mom), _ip(sp), gauge_leg, _dp(out)) != 0:
+        raise ValueError("bad arguments")
+    return out[0::2] + 1j * out[1::2]
+
+
+def dressed_amp(momentum, card, spins, colours, i3: int = 0, j4: int = 0, gauge_leg: int = -1,
+                pure_gluon: bool = False) -> complex:
+    mom = np.ascontiguousarray(momentum, dtype=np.float64)
+    card = np.ascontiguousarray(card, dtype=np.float64)
+    sp = np.ascontiguousarray(spins, dtype=np.int32)
+    col = np.ascontiguousarray(colours, dtype=np.int32)
+    out = np.empty(2, dtype=np.float64)
+    if lib().oracle_dressed_amp(mom.shape[0], _dp(card), _dp(mom), _ip(sp), _ip(col), i3, j4, gauge_leg,
+                                int(pure_gluon), _dp(out)) != 0:
+        raise ValueError("bad arguments")
+    return complex(out[0], out[1])
+
+
+def external(kind: int, p, m: float, lam: int) -> np.ndarray:
+    """kind 0 u, 1 v, 2 ubar, 3 vbar (helicity lam = +-1); 4 linear polarisation lam in {0, 1}."""
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    out = np.empty(8, dtype=np.float64)
+    if lib().oracle_external(kind, _dp(p), float(m), int(lam), _dp(out)) != 0:
+        raise ValueError("bad kind")
+    return out[0::2] + 1j * out[1::2]
+
+
+def gamma(mu: int) -> np.ndarray:
+    out = np.empty(32, dtype=np.float64)
+    if lib().oracle_gamma(mu, _dp(out)) != 0:
+        raise ValueError("bad index")
+    return (out[0::2] + 1j * out[1::2]).reshape(4, 4)
+
+
+def su3():
+    T = np.empty(8 * 9 * 2, dtype=np.float64)
+    f = np.empty(512, dtype=np.float64)
+    lib().oracle_su3(_dp(T), _dp(f))
+    return (T[0::2] + 1j * T[1::2]).reshape(8, 3, 3), f.reshape(8, 8, 8)
+
+
+def ew(card):
+    card = np.ascontiguousarray(card, dtype=np.float64)
+    out = np.empty(3, dtype=np.float64)
+    lib().oracle_ew(_dp(card), _dp(out))
+    return dict(sw2=out[0], cw2=out[1], e=out[2])
+
+
+def iden(process: int) -> float:
+    out = np.empty(1, dtype=np.float64)
+    if lib().oracle_iden(process, _dp(out)) != 0:
+        raise ValueError("bad process")
+    return float(out[0])
