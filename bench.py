@@ -1,0 +1,145 @@
+"""Benchmark: |M|^2 events/s for g g -> t tbar g g on one MI355X, FP64 and mixed precision.
+
+One step is one hme_compute call over the whole batch (1,048,576 RAMBO events at
+sqrt(s) = 2 TeV with dR(g,g) > 0.4, seed 4), momenta already resident in HBM:
+external wavefunctions, propagator denominators, the 123-diagram sequence for
+every good helicity, jamps, colour sum, helicity sum and normalisation, all in
+one kernel launch.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = "|M|^2 events/s on 1 MI355X (gg→tt̄gg, FP64 vs mixed); p50/p99 served latency"
+PEAK_FP64_VALU = 78.6e12  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+PEAK_FP32_VALU_UNPACKED = 78.6e12  # same lanes and rate; packed FP32 is not used
+PEAK_HBM = 8.0e12
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_steps(h, mom, out, steps, warmup, alpha_s=0.118):
+    import torch
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        h.compute(mom, out, alpha_s, stream)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record(stream)
+    for _ in range(steps):
+        h.compute(mom, out, alpha_s, stream)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return start.elapsed_time(stop) / 1e3, wall
+
+
+def cpu_baseline(proc, p, gpu_out, card, target_s=12.0):
+    """The FP64 oracle on the host cores over a bounded sample of the same events."""
+    import oracle
+    threads = oracle.default_threads()
+    n = 256
+    oracle.me2(proc, p[:64], card)  # warm the library and its colour matrix
+    while True:
+        t0 = time.perf_counter()
+        ref = oracle.me2(proc, p[:n], card, nthreads=threads)
+        dt = time.perf_counter() - t0
+        if dt >= target_s or n >= len(p):
+            break
+        n = min(len(p), int(n * max(2.0, min(8.0, target_s / max(dt, 1e-3)))))
+    rel = np.abs(gpu_out[:n] / ref - 1)
+    return dict(value=n / dt, unit="events/s", cores=threads, kind="oracle",
+                sample=f"first {n} events of the same batch, colour-ordered FP64 oracle, {dt:.1f} s",
+                max_rel_diff_vs_gpu=float(rel.max()))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--nevt", type=int, default=None, help="override the batch size (default: the workload's)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); events are independent and "
+              "shard without communication, see the design notes.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2507_21039_amd as hme
+    from workloads import configs
+
+    w = configs.WORKLOADS["ggttgg"]
+    nevt = args.nevt or w.nevt
+    card = configs.card_array()
+    log(f"[bench] generating {nevt} RAMBO events ({w.name})")
+    p = w.momenta(nevt)
+    mom = torch.from_numpy(p).cuda()
+    out = torch.empty(nevt, dtype=torch.float64, device="cuda")
+    results = {}
+    for prec, name in ((hme.FP64, "fp64"), (hme.MIXED, "mixed")):
+        log(f"[bench] {name}: create")
+        h = hme.Handle(hme.GGTTGG, card, prec)
+        info = h.query()
+        log(f"[bench] {name}: {args.warmup} warmup + {args.steps} timed steps")
+        gpu_s, wall_s = time_steps(h, mom, out, args.steps, args.warmup)
+        per_launch = gpu_s / args.steps
+        flops = info["flops_per_event"] * nevt
+        results[name] = dict(value=nevt * args.steps / gpu_s, ms_per_step=per_launch * 1e3, wall_s=wall_s,
+                             flops_per_event=info["flops_per_event"], ngoodhel=info["ngoodhel"],
+                             achieved_tflops=flops / per_launch / 1e12, out=out.cpu().numpy().copy())
+        h.close()
+        log(f"[bench] {name}: {results[name]['value']:.4g} events/s, {per_launch * 1e3:.3f} ms/step")
+
+    f64 = results["fp64"]
+    achieved = f64["flops_per_event"] * nevt / (f64["ms_per_step"] / 1e3)
+    line = {
+        "metric": METRIC,
+        "value": f64["value"],
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": f64["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"gg->ttbar gg, {nevt} RAMBO events at sqrt(s)=2 TeV, dR(g,g)>0.4, seed 4, "
+                               f"alpha_s=0.118, mt=173 GeV",
+                   "process": "gg->ttbar gg", "nevt": nevt, "diagrams": 123, "helicities": 64,
+                   "good_helicities": f64["ngoodhel"], "colour_flows": 24},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": None,
+                     "flops_per_event": f64["flops_per_event"]},
+        "mixed": {"value": results["mixed"]["value"], "ms_per_step": results["mixed"]["ms_per_step"],
+                  "dtype": "f32 vertices/propagators/jamps, f64 externals and sums",
+                  "achieved_tflops": results["mixed"]["achieved_tflops"],
+                  "frac_of_fp32_unpacked_valu": results["mixed"]["achieved_tflops"] * 1e12 / PEAK_FP32_VALU_UNPACKED,
+                  "max_rel_diff_vs_fp64": float(np.max(np.abs(results["mixed"]["out"] / f64["out"] - 1)))},
+        "served": None,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        line["cpu_baseline"] = cpu_baseline(configs.GGTTGG, p, f64["out"], card)
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,104 @@
+/* hme: tree-level squared matrix elements |M|^2 on AMD MI355X (gfx950).
+ *
+ * The operation is the per-event, helicity- and colour-summed squared matrix
+ * element of a fixed parton-level process, evaluated from the external momenta
+ * by helicity amplitudes: external wavefunctions, off-shell currents and
+ * amplitudes per Feynman diagram, summed into colour-flow amplitudes (jamps),
+ * contracted with the constant colour matrix and summed over the non-vanishing
+ * helicities (arXiv:2507.21039, section "Parallel scattering amplitudes"; the
+ * colour inner product and the precision modes, section "Numerical
+ * stability").  The interface follows the paper's Bridge: a handle is created
+ * once per process, executed once per batch of events, and destroyed (section
+ * "Event generation interface").
+ *
+ * Output normalisation: |M|^2 averaged over the initial helicities and colours
+ * and divided by the symmetry factor of identical final-state particles
+ * (IDEN, reported by hme_query): 4 for e+e- -> mu+mu-; 256, 256, 512, 1536 for
+ * g g -> t tbar + 0..3 g.
+ *
+ * Momenta: device memory, double[nevt][npar][4] with components (E, px, py, pz)
+ * in GeV, particles in the order
+ *   e+ e- -> mu+ mu- : e+ (in), e- (in), mu+, mu-
+ *   g g -> t tbar + n g : g (in), g (in), t, tbar, g ...
+ * Physics is not validated: momenta are taken to be on shell and conserving;
+ * NaN in gives NaN out.
+ *
+ * Errors: every call returns HME_OK (0) or a negative code; no exception
+ * crosses the interface.  hme_last_error() returns a message for the calling
+ * thread's last failure.
+ */
+#ifndef HME_H
+#define HME_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hme_handle hme_handle;
+
+/* Standard Model inputs: Z mass and width, 1/alpha, Fermi constant, top mass and width (GeV).
+ * sin^2(thetaW) follows from (mZ, alpha, G_F); internal top propagators use zero width. */
+typedef struct {
+  double mZ, wZ, alpha_inv, Gf, mT, wT;
+} hme_sm_card;
+
+enum hme_process { HME_EEMUMU = 0, HME_GGTT = 1, HME_GGTTG = 2, HME_GGTTGG = 3 };
+
+/* HME_FP64: every step in double precision.
+ * HME_MIXED: vertices, propagators and jamps in single precision; external
+ * wavefunctions, propagator denominators and the helicity/event sums in double. */
+enum hme_precision { HME_FP64 = 0, HME_MIXED = 1 };
+
+enum hme_status {
+  HME_OK = 0,
+  HME_E_ARG = -1,        /* null or misaligned pointer, negative size, unknown process or precision */
+  HME_E_HIP = -2,        /* a HIP runtime call failed (message has the HIP error string) */
+  HME_E_OOM = -3,        /* device allocation failed */
+  HME_E_BUDGET = -4,     /* request larger than the server's memory budget */
+  HME_E_TIMEOUT = -5,    /* wait timed out */
+  HME_E_UNSUPPORTED = -6 /* process or precision not built into this library */
+};
+
+typedef struct {
+  int process, precision, npar, nhel, ngoodhel, ncol, ndiag, namp;
+  double iden;             /* averaging and symmetry factor applied to the output */
+  double flops_per_event;  /* algorithmic floating-point operations per event (all good helicities) */
+  double bytes_per_event;  /* HBM traffic per event: momenta in + |M|^2 out */
+} hme_info;
+
+/* Create a handle for `process` on HIP device `device`.  Uploads nothing but a
+ * small helicity table; finds the helicities whose |M_h|^2 vanishes identically
+ * by evaluating every helicity on a fixed internal sample of 16 events (never on
+ * user data) and keeps the others.  The handle owns its device tables.
+ * On failure *out is NULL. */
+int hme_create(int process, const hme_sm_card* card, int precision, int device, hme_handle** out);
+
+/* Compute |M|^2 for nevt events, asynchronously on `hip_stream` (a hipStream_t,
+ * NULL for the default stream).  `momenta` and `me2` are caller-owned device
+ * pointers, 8-byte aligned, [nevt][npar][4] and [nevt] doubles.  alpha_s is the
+ * strong coupling for this call.  nevt = 0 is a successful no-op; any nevt >= 1
+ * is valid (partial wavefronts are masked).  Not thread-safe per handle. */
+int hme_compute(hme_handle* h, double alpha_s, int64_t nevt, const double* momenta, double* me2, void* hip_stream);
+
+/* Fill `info` with the handle's process constants. */
+int hme_query(const hme_handle* h, hme_info* info);
+
+/* Copy up to `cap` good helicity indices into `out` (bit k of an index, counted
+ * from the most significant of npar bits, is 1 for helicity +1 of particle k);
+ * returns the number of good helicities or a negative code. */
+int hme_good_helicities(const hme_handle* h, int* out, int cap);
+
+/* Release the handle and its device tables (NULL is accepted). */
+int hme_destroy(hme_handle* h);
+
+/* Message describing the calling thread's most recent failure ("" if none). */
+const char* hme_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HME_H */

@@ -1,0 +1,139 @@
+"""Python binding of libhme.so (include/hme.h): argument marshalling only.
+
+Every step of the |M|^2 computation runs in the library's HIP kernels; PyTorch
+supplies device memory and streams.  There is no CPU fallback: if the library
+is missing or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhme.so")
+
+EEMUMU, GGTT, GGTTG, GGTTGG = 0, 1, 2, 3
+FP64, MIXED = 0, 1
+NPAR = {EEMUMU: 4, GGTT: 4, GGTTG: 5, GGTTGG: 6}
+PROCESS_NAMES = {EEMUMU: "e+e- -> mu+mu-", GGTT: "gg -> ttbar", GGTTG: "gg -> ttbar g", GGTTGG: "gg -> ttbar gg"}
+
+HME_OK, HME_E_ARG, HME_E_HIP, HME_E_OOM, HME_E_BUDGET, HME_E_TIMEOUT, HME_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+
+EXPORTED = ("hme_create", "hme_compute", "hme_query", "hme_good_helicities", "hme_destroy", "hme_last_error")
+
+
+class SmCard(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("mZ", "wZ", "alpha_inv", "Gf", "mT", "wT")]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int) for n in ("process", "precision", "npar", "nhel", "ngoodhel", "ncol", "ndiag",
+                                            "namp")] + \
+               [(n, ctypes.c_double) for n in ("iden", "flops_per_event", "bytes_per_event")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class HmeError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libhme.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_2507_21039_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        L.hme_create.argtypes = [ctypes.c_int, ctypes.POINTER(SmCard), ctypes.c_int, ctypes.c_int,
+                                 ctypes.POINTER(vp)]
+        L.hme_compute.argtypes = [vp, ctypes.c_double, ctypes.c_int64, vp, vp, vp]
+        L.hme_query.argtypes = [vp, ctypes.POINTER(Info)]
+        L.hme_good_helicities.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int]
+        L.hme_destroy.argtypes = [vp]
+        L.hme_last_error.restype = ctypes.c_char_p
+        for name in ("hme_create", "hme_compute", "hme_query", "hme_good_helicities", "hme_destroy"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().hme_last_error().decode()
+
+
+def _check(rc: int):
+    if rc < 0:
+        raise HmeError(rc, last_error())
+    return rc
+
+
+def card_struct(card) -> SmCard:
+    """card: sequence (mZ, wZ, 1/alpha, G_F, m_top, w_top) or a dict with those keys."""
+    if isinstance(card, dict):
+        return SmCard(card["mZ"], card["wZ"], card["alpha_inv"], card["Gf"], card["mT"], card["wT"])
+    return SmCard(*[float(x) for x in card])
+
+
+class Handle:
+    """One process on one device (hme_create / hme_compute / hme_destroy)."""
+
+    def __init__(self, process: int, card, precision: int = FP64, device: int = 0):
+        self._h = ctypes.c_void_p()
+        _check(lib().hme_create(process, ctypes.byref(card_struct(card)), precision, device, ctypes.byref(self._h)))
+        self.process, self.precision, self.device = process, precision, device
+
+    def compute_ptr(self, alpha_s: float, nevt: int, momenta_ptr: int, me2_ptr: int, stream_ptr: int = 0):
+        _check(lib().hme_compute(self._h, float(alpha_s), int(nevt), ctypes.c_void_p(momenta_ptr),
+                                 ctypes.c_void_p(me2_ptr), ctypes.c_void_p(stream_ptr)))
+
+    def compute(self, momenta, out=None, alpha_s: float = 0.118, stream=None):
+        """momenta: torch float64 device tensor [nevt, npar, 4]; returns |M|^2 [nevt] (float64, same device)."""
+        import torch
+        if momenta.device.type != "cuda" or momenta.dtype != torch.float64 or not momenta.is_contiguous():
+            raise ValueError("momenta must be a contiguous float64 GPU tensor")
+        if momenta.dim() != 3 or momenta.shape[1] != NPAR[self.process] or momenta.shape[2] != 4:
+            raise ValueError(f"momenta must be [nevt, {NPAR[self.process]}, 4]")
+        n = momenta.shape[0]
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=momenta.device)
+        if out.dtype != torch.float64 or out.device != momenta.device or out.numel() < n or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 tensor on the momenta's device")
+        s = stream if stream is not None else torch.cuda.current_stream(momenta.device)
+        self.compute_ptr(alpha_s, n, momenta.data_ptr(), out.data_ptr(), s.cuda_stream)
+        return out
+
+    def query(self) -> dict:
+        info = Info()
+        _check(lib().hme_query(self._h, ctypes.byref(info)))
+        return info.as_dict()
+
+    def good_helicities(self) -> list:
+        n = _check(lib().hme_good_helicities(self._h, None, 0))
+        buf = (ctypes.c_int * max(n, 1))()
+        _check(lib().hme_good_helicities(self._h, buf, n))
+        return list(buf[:n])
+
+    def close(self):
+        if self._h:
+            _check(lib().hme_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

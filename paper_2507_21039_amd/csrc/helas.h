@@ -1,0 +1,308 @@
+// HELAS-style wavefunction and vertex routines for gfx950, one event and one
+// helicity per lane.
+//
+// These are the building blocks that the paper's section "Parallel scattering
+// amplitudes" describes: external wavefunctions (ixxxxx / oxxxxx / vxxxxx),
+// off-shell currents that merge wavefunctions through a vertex and a propagator,
+// and amplitude routines that close a diagram at a final vertex.  The naming
+// follows the ALOHA scheme in spirit (amplitude = "_amp" where ALOHA writes
+// "_0", off-shell current = "_psi" / "_psibar" / "_vec"), but the formulas below
+// are this project's own, written in the chiral (Weyl) representation
+//   gamma^mu = [[0, sigma^mu], [sigmabar^mu, 0]], psi = (psi_L, psi_R),
+// metric (+,-,-,-), with couplings and factors of i left to the generated code.
+//
+// Every function is __host__ __device__ so the generated call sequences can
+// also be evaluated on the CPU in tests; the product path runs them on the GPU.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#define HME_FN __host__ __device__ __forceinline__
+
+namespace hme {
+
+template <class T> struct cx {
+  T r, i;
+};
+
+template <class T> HME_FN cx<T> operator+(cx<T> a, cx<T> b) { return {a.r + b.r, a.i + b.i}; }
+template <class T> HME_FN cx<T> operator-(cx<T> a, cx<T> b) { return {a.r - b.r, a.i - b.i}; }
+template <class T> HME_FN cx<T> operator-(cx<T> a) { return {-a.r, -a.i}; }
+template <class T> HME_FN cx<T> operator*(cx<T> a, cx<T> b) {
+  return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r};
+}
+template <class T> HME_FN cx<T> operator*(T s, cx<T> a) { return {s * a.r, s * a.i}; }
+template <class T> HME_FN cx<T> mul_i(cx<T> a) { return {-a.i, a.r}; }  // i * a
+template <class T> HME_FN cx<T> conj(cx<T> a) { return {a.r, -a.i}; }
+template <class T, class U> HME_FN cx<T> cast(cx<U> a) { return {T(a.r), T(a.i)}; }
+
+// Dirac spinor (column for "_in" states, row for barred states) and vector wavefunction
+// (contravariant components).
+template <class T> struct sp4 {
+  cx<T> c[4];
+};
+template <class T> struct vw4 {
+  cx<T> c[4];
+};
+
+template <class T, class U> HME_FN sp4<T> cast(const sp4<U>& a) {
+  return {{cast<T>(a.c[0]), cast<T>(a.c[1]), cast<T>(a.c[2]), cast<T>(a.c[3])}};
+}
+template <class T, class U> HME_FN vw4<T> cast(const vw4<U>& a) {
+  return {{cast<T>(a.c[0]), cast<T>(a.c[1]), cast<T>(a.c[2]), cast<T>(a.c[3])}};
+}
+
+// Minkowski product of two complex vectors (bilinear, no conjugation)
+template <class T> HME_FN cx<T> mdot(const vw4<T>& a, const vw4<T>& b) {
+  return a.c[0] * b.c[0] - a.c[1] * b.c[1] - a.c[2] * b.c[2] - a.c[3] * b.c[3];
+}
+// Minkowski product of a real vector with a complex vector
+template <class T> HME_FN cx<T> mdot(const T* q, const vw4<T>& a) {
+  return q[0] * a.c[0] - q[1] * a.c[1] - q[2] * a.c[2] - q[3] * a.c[3];
+}
+
+// ------------------------------------------------------------------ external states
+// Momenta p = (E, px, py, pz).  lam = +1 / -1 is the helicity.
+
+// Two-component helicity states (sigma . p-hat) chi = lam chi, normalised to 1:
+// chi_+ ~ (|p| + pz, px + i py), chi_- ~ (-px + i py, |p| + pz); for p-hat = -z
+// exactly, chi_+ = (0, 1) and chi_- = (-1, 0).  |p| + pz is formed without
+// cancellation.
+HME_FN void helicity_chi(const double* p, int lam, cx<double> chi[2]) {
+  const double pt2 = p[1] * p[1] + p[2] * p[2];
+  const double P = sqrt(pt2 + p[3] * p[3]);
+  const double ppz = p[3] >= 0 ? P + p[3] : pt2 / (P - p[3]);
+  const bool axis = ppz == 0.0;
+  const double nrm = axis ? 0.0 : 1.0 / sqrt(2.0 * P * ppz);
+  if (lam > 0) {
+    chi[0] = {axis ? 0.0 : ppz * nrm, 0.0};
+    chi[1] = {axis ? 1.0 : p[1] * nrm, axis ? 0.0 : p[2] * nrm};
+  } else {
+    chi[0] = {axis ? -1.0 : -p[1] * nrm, axis ? 0.0 : p[2] * nrm};
+    chi[1] = {axis ? 0.0 : ppz * nrm, 0.0};
+  }
+}
+
+// sqrt(E + |p|) and sqrt(E - |p|) = m / sqrt(E + |p|)
+HME_FN void spinor_weights(const double* p, double m, double& wp, double& wm) {
+  const double P = sqrt(p[1] * p[1] + p[2] * p[2] + p[3] * p[3]);
+  wp = sqrt(p[0] + P);
+  wm = m == 0.0 ? 0.0 : m / wp;
+}
+
+// Flowing-in fermion: nsf = +1 gives u(p, lam) (incoming fermion),
+// nsf = -1 gives v(p, lam) (outgoing antifermion).  Chiral basis:
+// u = (sqrt(E - lam P) chi_lam, sqrt(E + lam P) chi_lam),
+// v = (sqrt(E + lam P) chi_-lam, -sqrt(E - lam P) chi_-lam).
+HME_FN sp4<double> ixxxxx(const double* p, double m, int lam, int nsf) {
+  double wp, wm;
+  spinor_weights(p, m, wp, wm);
+  cx<double> chi[2];
+  sp4<double> w;
+  if (nsf > 0) {
+    helicity_chi(p, lam, chi);
+    const double a = lam > 0 ? wm : wp, b = lam > 0 ? wp : wm;
+    w.c[0] = a * chi[0];
+    w.c[1] = a * chi[1];
+    w.c[2] = b * chi[0];
+    w.c[3] = b * chi[1];
+  } else {
+    helicity_chi(p, -lam, chi);
+    const double a = lam > 0 ? wp : wm, b = lam > 0 ? wm : wp;
+    w.c[0] = a * chi[0];
+    w.c[1] = a * chi[1];
+    w.c[2] = -b * chi[0];
+    w.c[3] = -b * chi[1];
+  }
+  return w;
+}
+
+// Flowing-out fermion (row spinor): nsf = +1 gives ubar(p, lam) (outgoing fermion),
+// nsf = -1 gives vbar(p, lam) (incoming antifermion); bar(psi) = psi^dagger gamma^0,
+// which swaps the chiral halves and conjugates.
+HME_FN sp4<double> oxxxxx(const double* p, double m, int lam, int nsf) {
+  double wp, wm;
+  spinor_weights(p, m, wp, wm);
+  cx<double> chi[2];
+  sp4<double> w;
+  if (nsf > 0) {
+    helicity_chi(p, lam, chi);
+    const double a = lam > 0 ? wp : wm, b = lam > 0 ? wm : wp;  // (sqrt(E+lam P), sqrt(E-lam P))
+    w.c[0] = a * conj(chi[0]);
+    w.c[1] = a * conj(chi[1]);
+    w.c[2] = b * conj(chi[0]);
+    w.c[3] = b * conj(chi[1]);
+  } else {
+    helicity_chi(p, -lam, chi);
+    const double a = lam > 0 ? wm : wp, b = lam > 0 ? wp : wm;  // (-sqrt(E-lam P), sqrt(E+lam P))
+    w.c[0] = -a * conj(chi[0]);
+    w.c[1] = -a * conj(chi[1]);
+    w.c[2] = b * conj(chi[0]);
+    w.c[3] = b * conj(chi[1]);
+  }
+  return w;
+}
+
+// Massless vector boson: eps(k, lam) = (-lam e1 - i e2) / sqrt(2) with
+// e1 = (0, cos(th) cos(ph), cos(th) sin(ph), -sin(th)), e2 = (0, -sin(ph), cos(ph), 0);
+// nsv = -1 (incoming) returns eps, nsv = +1 (outgoing) returns conj(eps).
+HME_FN vw4<double> vxxxxx(const double* k, int lam, int nsv) {
+  const double pt2 = k[1] * k[1] + k[2] * k[2];
+  const double pt = sqrt(pt2);
+  const double P = sqrt(pt2 + k[3] * k[3]);
+  const double ct = k[3] / P, st = pt / P;
+  const double cp = pt > 0 ? k[1] / pt : 1.0, sp = pt > 0 ? k[2] / pt : 0.0;
+  const double r = 0.70710678118654752440;  // 1/sqrt(2)
+  const double a = -lam * r;
+  const double b = nsv < 0 ? -r : r;  // imaginary part sign: -i e2 (incoming), +i e2 (outgoing)
+  vw4<double> w;
+  w.c[0] = {0.0, 0.0};
+  w.c[1] = {a * ct * cp, -b * sp};
+  w.c[2] = {a * ct * sp, b * cp};
+  w.c[3] = {-a * st, 0.0};
+  return w;
+}
+
+// ------------------------------------------------------------------ fermion-vector vertices
+// Shorthands for a vector V: vp = V0 + V3, vm = V0 - V3, vt = V1 + i V2, vtb = V1 - i V2, so that
+// sigma.V = [[vm, -vtb], [-vt, vp]] and sigmabar.V = [[vp, vtb], [vt, vm]].
+
+// Amplitude fbar V-slash f (ALOHA-style "FFV1_0").
+template <class T> HME_FN cx<T> ffv_amp(const sp4<T>& fb, const sp4<T>& f, const vw4<T>& V) {
+  const cx<T> vp = V.c[0] + V.c[3], vm = V.c[0] - V.c[3];
+  const cx<T> vt = V.c[1] + mul_i(V.c[2]), vtb = V.c[1] - mul_i(V.c[2]);
+  return fb.c[0] * (vm * f.c[2] - vtb * f.c[3]) + fb.c[1] * (vp * f.c[3] - vt * f.c[2]) +
+         fb.c[2] * (vp * f.c[0] + vtb * f.c[1]) + fb.c[3] * (vt * f.c[0] + vm * f.c[1]);
+}
+
+// Same with chiral couplings gamma^mu (gL P_L + gR P_R).
+template <class T> HME_FN cx<T> ffvlr_amp(const sp4<T>& fb, const sp4<T>& f, const vw4<T>& V, T gL, T gR) {
+  const cx<T> vp = V.c[0] + V.c[3], vm = V.c[0] - V.c[3];
+  const cx<T> vt = V.c[1] + mul_i(V.c[2]), vtb = V.c[1] - mul_i(V.c[2]);
+  return gR * (fb.c[0] * (vm * f.c[2] - vtb * f.c[3]) + fb.c[1] * (vp * f.c[3] - vt * f.c[2])) +
+         gL * (fb.c[2] * (vp * f.c[0] + vtb * f.c[1]) + fb.c[3] * (vt * f.c[0] + vm * f.c[1]));
+}
+
+// Off-shell spinor: (K-slash + m) V-slash f * den, with K the momentum along the
+// fermion arrow after the vertex and den = 1 / (K^2 - m^2).
+template <class T> HME_FN sp4<T> ffv_psi(const sp4<T>& f, const vw4<T>& V, const T* K, T m, T den) {
+  const cx<T> vp = V.c[0] + V.c[3], vm = V.c[0] - V.c[3];
+  const cx<T> vt = V.c[1] + mul_i(V.c[2]), vtb = V.c[1] - mul_i(V.c[2]);
+  const cx<T> g0 = vm * f.c[2] - vtb * f.c[3];
+  const cx<T> g1 = vp * f.c[3] - vt * f.c[2];
+  const cx<T> g2 = vp * f.c[0] + vtb * f.c[1];
+  const cx<T> g3 = vt * f.c[0] + vm * f.c[1];
+  const T kp = K[0] + K[3], km = K[0] - K[3];
+  const cx<T> kt = {K[1], K[2]}, ktb = {K[1], -K[2]};
+  sp4<T> o;
+  o.c[0] = den * (km * g2 - ktb * g3 + m * g0);
+  o.c[1] = den * (kp * g3 - kt * g2 + m * g1);
+  o.c[2] = den * (kp * g0 + ktb * g1 + m * g2);
+  o.c[3] = den * (kt * g0 + km * g1 + m * g3);
+  return o;
+}
+
+// Off-shell barred spinor: fb V-slash (K-slash + m) * den, K along the fermion arrow
+// before the vertex, den = 1 / (K^2 - m^2).
+template <class T> HME_FN sp4<T> ffv_psibar(const sp4<T>& fb, const vw4<T>& V, const T* K, T m, T den) {
+  const cx<T> vp = V.c[0] + V.c[3], vm = V.c[0] - V.c[3];
+  const cx<T> vt = V.c[1] + mul_i(V.c[2]), vtb = V.c[1] - mul_i(V.c[2]);
+  const cx<T> h0 = fb.c[2] * vp + fb.c[3] * vt;
+  const cx<T> h1 = fb.c[2] * vtb + fb.c[3] * vm;
+  const cx<T> h2 = fb.c[0] * vm - fb.c[1] * vt;
+  const cx<T> h3 = fb.c[1] * vp - fb.c[0] * vtb;
+  const T kp = K[0] + K[3], km = K[0] - K[3];
+  const cx<T> kt = {K[1], K[2]}, ktb = {K[1], -K[2]};
+  sp4<T> o;
+  o.c[0] = den * (kp * h2 + kt * h3 + m * h0);
+  o.c[1] = den * (ktb * h2 + km * h3 + m * h1);
+  o.c[2] = den * (km * h0 - kt * h1 + m * h2);
+  o.c[3] = den * (kp * h1 - ktb * h0 + m * h3);
+  return o;
+}
+
+// Off-shell vector from a fermion pair through a massless propagator: J^mu = fb gamma^mu f * den.
+template <class T> HME_FN vw4<T> ffv_vec(const sp4<T>& fb, const sp4<T>& f, T den) {
+  vw4<T> J;
+  J.c[0] = den * (fb.c[0] * f.c[2] + fb.c[1] * f.c[3] + fb.c[2] * f.c[0] + fb.c[3] * f.c[1]);
+  J.c[1] = den * (fb.c[0] * f.c[3] + fb.c[1] * f.c[2] - fb.c[2] * f.c[1] - fb.c[3] * f.c[0]);
+  J.c[2] = den * mul_i(fb.c[1] * f.c[2] - fb.c[0] * f.c[3] + fb.c[2] * f.c[1] - fb.c[3] * f.c[0]);
+  J.c[3] = den * (fb.c[0] * f.c[2] - fb.c[1] * f.c[3] - fb.c[2] * f.c[0] + fb.c[3] * f.c[1]);
+  return J;
+}
+
+// Off-shell massive vector (unitary gauge, fixed width) from a fermion pair with chiral couplings:
+// J^mu = (j^mu - Q^mu (Q.j) / M^2) * den, j^mu = fb gamma^mu (gL P_L + gR P_R) f,
+// den = 1 / (Q^2 - M^2 + i M W) (complex).
+template <class T>
+HME_FN vw4<T> ffvlr_vec_massive(const sp4<T>& fb, const sp4<T>& f, T gL, T gR, const T* Q, T M, cx<T> den) {
+  vw4<T> j;
+  j.c[0] = gR * (fb.c[0] * f.c[2] + fb.c[1] * f.c[3]) + gL * (fb.c[2] * f.c[0] + fb.c[3] * f.c[1]);
+  j.c[1] = gR * (fb.c[0] * f.c[3] + fb.c[1] * f.c[2]) - gL * (fb.c[2] * f.c[1] + fb.c[3] * f.c[0]);
+  j.c[2] = mul_i(gR * (fb.c[1] * f.c[2] - fb.c[0] * f.c[3]) + gL * (fb.c[2] * f.c[1] - fb.c[3] * f.c[0]));
+  j.c[3] = gR * (fb.c[0] * f.c[2] - fb.c[1] * f.c[3]) - gL * (fb.c[2] * f.c[0] - fb.c[3] * f.c[1]);
+  const cx<T> qj = (T(1) / (M * M)) * mdot(Q, j);
+  vw4<T> J;
+  for (int mu = 0; mu < 4; ++mu) J.c[mu] = den * (j.c[mu] - Q[mu] * qj);
+  return J;
+}
+
+// ------------------------------------------------------------------ gluon self-couplings
+// Three-vector vertex V^{mu nu rho}(k, p, q) = g^{mu nu}(k - p)^rho + g^{nu rho}(p - q)^mu + g^{rho mu}(q - k)^nu
+// with all momenta incoming.
+
+// Amplitude a_mu b_nu c_rho V^{mu nu rho}(Qa, Qb, Qc) (ALOHA-style "VVV1_0").
+template <class T>
+HME_FN cx<T> vvv_amp(const vw4<T>& a, const T* Qa, const vw4<T>& b, const T* Qb, const vw4<T>& c, const T* Qc) {
+  T d1[4], d2[4], d3[4];
+  for (int mu = 0; mu < 4; ++mu) {
+    d1[mu] = Qa[mu] - Qb[mu];
+    d2[mu] = Qb[mu] - Qc[mu];
+    d3[mu] = Qc[mu] - Qa[mu];
+  }
+  return mdot(a, b) * mdot(d1, c) + mdot(b, c) * mdot(d2, a) + mdot(c, a) * mdot(d3, b);
+}
+
+// Off-shell vector through a massless propagator (ALOHA-style "VVV1P0_1"):
+// J^rho = V^{mu nu rho}(Qa, Qb, -Qa-Qb) a_mu b_nu * den
+//       = [(a.b)(Qa - Qb)^rho + b^rho (Qa + 2 Qb).a - a^rho (2 Qa + Qb).b] * den.
+template <class T> HME_FN vw4<T> vvv_vec(const vw4<T>& a, const T* Qa, const vw4<T>& b, const T* Qb, T den) {
+  T u[4], v[4], w[4];
+  for (int mu = 0; mu < 4; ++mu) {
+    u[mu] = Qa[mu] - Qb[mu];
+    v[mu] = Qa[mu] + 2 * Qb[mu];
+    w[mu] = 2 * Qa[mu] + Qb[mu];
+  }
+  const cx<T> ab = den * mdot(a, b), va = den * mdot(v, a), wb = den * mdot(w, b);
+  vw4<T> J;
+  for (int mu = 0; mu < 4; ++mu) J.c[mu] = u[mu] * ab + va * b.c[mu] - wb * a.c[mu];
+  return J;
+}
+
+// Four-vector vertex structures with legs (a: mu, b: nu, c: rho, d: sigma):
+//   S = 1: g^{mu rho} g^{nu sigma} - g^{mu sigma} g^{nu rho}
+//   S = 2: g^{mu nu} g^{rho sigma} - g^{mu sigma} g^{nu rho}
+//   S = 3: g^{mu nu} g^{rho sigma} - g^{mu rho} g^{nu sigma}
+template <int S, class T> HME_FN cx<T> vvvv_amp(const vw4<T>& a, const vw4<T>& b, const vw4<T>& c, const vw4<T>& d) {
+  if (S == 1) return mdot(a, c) * mdot(b, d) - mdot(a, d) * mdot(b, c);
+  if (S == 2) return mdot(a, b) * mdot(c, d) - mdot(a, d) * mdot(b, c);
+  return mdot(a, b) * mdot(c, d) - mdot(a, c) * mdot(b, d);
+}
+
+// Off-shell leg d through a massless propagator.
+template <int S, class T> HME_FN vw4<T> vvvv_vec(const vw4<T>& a, const vw4<T>& b, const vw4<T>& c, T den) {
+  vw4<T> J;
+  if (S == 1) {
+    const cx<T> x = den * mdot(a, c), y = den * mdot(b, c);
+    for (int mu = 0; mu < 4; ++mu) J.c[mu] = x * b.c[mu] - y * a.c[mu];
+  } else if (S == 2) {
+    const cx<T> x = den * mdot(a, b), y = den * mdot(b, c);
+    for (int mu = 0; mu < 4; ++mu) J.c[mu] = x * c.c[mu] - y * a.c[mu];
+  } else {
+    const cx<T> x = den * mdot(a, b), y = den * mdot(a, c);
+    for (int mu = 0; mu < 4; ++mu) J.c[mu] = x * c.c[mu] - y * b.c[mu];
+  }
+  return J;
+}
+
+}  // namespace hme

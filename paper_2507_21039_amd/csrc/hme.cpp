@@ -1,0 +1,273 @@
+// The C interface of include/hme.h: handle life cycle, parameter derivation,
+// the good-helicity filter and kernel dispatch.
+#include "../../include/hme.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "me2_kernels.h"
+#include "params.h"
+
+namespace hme {
+#define HME_DECLARE(NAME)                                                          \
+  ProcInfo info_##NAME();                                                          \
+  hipError_t launch_me2_##NAME(const LaunchArgs& a, int precision);                \
+  hipError_t launch_hel_##NAME(const double* mom, int nev, const ProcParams& prm, \
+                               double* out, hipStream_t s);
+HME_DECLARE(eemumu)
+HME_DECLARE(ggtt)
+HME_DECLARE(ggttg)
+HME_DECLARE(ggttgg)
+#undef HME_DECLARE
+
+struct ProcEntry {
+  ProcInfo (*info)();
+  hipError_t (*me2)(const LaunchArgs&, int);
+  hipError_t (*hel)(const double*, int, const ProcParams&, double*, hipStream_t);
+  bool qcd;            // g g -> t tbar + n g (otherwise e+ e- -> mu+ mu-)
+  double sample_sqrt_s;  // energy of the internal helicity-filter sample
+};
+
+static const ProcEntry kProcs[] = {
+    {info_eemumu, launch_me2_eemumu, launch_hel_eemumu, false, 500.0},
+    {info_ggtt, launch_me2_ggtt, launch_hel_ggtt, true, 1000.0},
+    {info_ggttg, launch_me2_ggttg, launch_hel_ggttg, true, 1500.0},
+    {info_ggttgg, launch_me2_ggttgg, launch_hel_ggttgg, true, 2000.0},
+};
+constexpr int kNumProcs = sizeof(kProcs) / sizeof(kProcs[0]);
+
+}  // namespace hme
+
+struct hme_handle {
+  int process = 0, precision = 0, device = 0;
+  hme::ProcInfo info{};
+  hme::ProcParams prm{};
+  std::vector<int> goodhel;
+  int* d_goodhel = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(HME_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Restores the caller's current device when it goes out of scope.
+struct DeviceGuard {
+  int prev = -1;
+  hipError_t err = hipSuccess;
+  explicit DeviceGuard(int dev) {
+    err = hipGetDevice(&prev);
+    if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+// A few flat phase-space points (massless RAMBO, then a common rescaling of the
+// three-momenta for the final-state masses) from a fixed seed.  Used only to
+// find the vanishing helicities; it never sees user data.
+std::vector<double> helicity_sample(const hme::ProcInfo& info, bool qcd, double mT, double sqrt_s, int nev) {
+  const int npar = info.npar, nout = npar - 2;
+  std::vector<double> masses(nout, 0.0);
+  if (qcd) masses[0] = masses[1] = mT;
+  std::mt19937_64 rng(0x6d655f68656cULL);
+  std::uniform_real_distribution<double> U(0.0, 1.0);
+  auto u01 = [&]() {
+    double x;
+    do x = U(rng); while (x <= 0.0);
+    return x;
+  };
+  std::vector<double> mom((size_t)nev * npar * 4, 0.0);
+  const double pi = 3.14159265358979323846;
+  for (int e = 0; e < nev; ++e) {
+    double* ev = &mom[(size_t)e * npar * 4];
+    ev[0] = ev[3] = sqrt_s / 2;
+    ev[4] = sqrt_s / 2;
+    ev[7] = -sqrt_s / 2;
+    std::vector<double> q(4 * nout), P(4, 0.0);
+    for (int i = 0; i < nout; ++i) {
+      const double c = 2 * u01() - 1, s = std::sqrt(1 - c * c), f = 2 * pi * u01();
+      const double q0 = -std::log(u01() * u01());
+      q[4 * i + 0] = q0;
+      q[4 * i + 1] = q0 * s * std::cos(f);
+      q[4 * i + 2] = q0 * s * std::sin(f);
+      q[4 * i + 3] = q0 * c;
+      for (int mu = 0; mu < 4; ++mu) P[mu] += q[4 * i + mu];
+    }
+    const double M = std::sqrt(P[0] * P[0] - P[1] * P[1] - P[2] * P[2] - P[3] * P[3]);
+    const double b[3] = {-P[1] / M, -P[2] / M, -P[3] / M};
+    const double x = sqrt_s / M, g = P[0] / M, a = 1 / (1 + g);
+    std::vector<double> k(4 * nout);
+    for (int i = 0; i < nout; ++i) {
+      const double* qi = &q[4 * i];
+      const double bq = b[0] * qi[1] + b[1] * qi[2] + b[2] * qi[3];
+      for (int j = 0; j < 3; ++j) k[4 * i + 1 + j] = x * (qi[1 + j] + b[j] * qi[0] + a * bq * b[j]);
+      k[4 * i] = x * (g * qi[0] + bq);
+    }
+    double xi = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double f = -sqrt_s, df = 0;
+      for (int i = 0; i < nout; ++i) {
+        const double E = std::sqrt(masses[i] * masses[i] + xi * xi * k[4 * i] * k[4 * i]);
+        f += E;
+        df += xi * k[4 * i] * k[4 * i] / E;
+      }
+      xi -= f / df;
+    }
+    for (int i = 0; i < nout; ++i) {
+      double* o = ev + 4 * (2 + i);
+      for (int j = 1; j < 4; ++j) o[j] = xi * k[4 * i + j];
+      o[0] = std::sqrt(masses[i] * masses[i] + o[1] * o[1] + o[2] * o[2] + o[3] * o[3]);
+    }
+  }
+  return mom;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hme_last_error(void) { return g_last_error.c_str(); }
+
+int hme_create(int process, const hme_sm_card* card, int precision, int device, hme_handle** out) {
+  if (!out) return fail(HME_E_ARG, "hme_create: out is NULL");
+  *out = nullptr;
+  if (!card) return fail(HME_E_ARG, "hme_create: card is NULL");
+  if (process < 0 || process >= hme::kNumProcs) return fail(HME_E_ARG, "hme_create: unknown process");
+  if (precision != HME_FP64 && precision != HME_MIXED) return fail(HME_E_ARG, "hme_create: unknown precision");
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess) return hip_fail(e, "hme_create: hipGetDeviceCount");
+  if (device < 0 || device >= ndev) return fail(HME_E_ARG, "hme_create: no such device");
+  hme::ProcParams prm;
+  std::string why;
+  if (!hme::derive_params(*card, prm, why)) return fail(HME_E_ARG, "hme_create: " + why);
+  const hme::ProcEntry& P = hme::kProcs[process];
+  DeviceGuard guard(device);
+  if (guard.err != hipSuccess) return hip_fail(guard.err, "hme_create: hipSetDevice");
+
+  auto* h = new hme_handle;
+  h->process = process;
+  h->precision = precision;
+  h->device = device;
+  h->info = P.info();
+  h->prm = prm;
+
+  // good-helicity filter on the internal sample
+  const int nev = 16, nhel = h->info.nhel;
+  std::vector<double> mom = helicity_sample(h->info, P.qcd, prm.mT, P.sample_sqrt_s, nev);
+  std::vector<double> mh((size_t)nev * nhel);
+  double *d_mom = nullptr, *d_out = nullptr;
+  auto cleanup = [&]() {
+    if (d_mom) (void)hipFree(d_mom);
+    if (d_out) (void)hipFree(d_out);
+  };
+  if ((e = hipMalloc(&d_mom, mom.size() * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc(&d_out, mh.size() * sizeof(double))) != hipSuccess) {
+    cleanup();
+    delete h;
+    return fail(HME_E_OOM, std::string("hme_create: ") + hipGetErrorString(e));
+  }
+  if ((e = hipMemcpy(d_mom, mom.data(), mom.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = P.hel(d_mom, nev, prm, d_out, nullptr)) != hipSuccess ||
+      (e = hipMemcpy(mh.data(), d_out, mh.size() * sizeof(double), hipMemcpyDeviceToHost)) != hipSuccess) {
+    cleanup();
+    delete h;
+    return hip_fail(e, "hme_create: helicity filter");
+  }
+  cleanup();
+  for (int k = 0; k < nhel; ++k) {
+    bool nonzero = false;
+    for (int ev = 0; ev < nev; ++ev) nonzero = nonzero || mh[(size_t)ev * nhel + k] != 0.0;
+    if (nonzero) h->goodhel.push_back(k);
+  }
+  if (h->goodhel.empty()) {
+    delete h;
+    return fail(HME_E_HIP, "hme_create: every helicity vanished on the internal sample");
+  }
+  if ((e = hipMalloc(&h->d_goodhel, h->goodhel.size() * sizeof(int))) != hipSuccess) {
+    delete h;
+    return fail(HME_E_OOM, std::string("hme_create: ") + hipGetErrorString(e));
+  }
+  if ((e = hipMemcpy(h->d_goodhel, h->goodhel.data(), h->goodhel.size() * sizeof(int), hipMemcpyHostToDevice)) !=
+      hipSuccess) {
+    (void)hipFree(h->d_goodhel);
+    delete h;
+    return hip_fail(e, "hme_create: upload helicities");
+  }
+  *out = h;
+  return HME_OK;
+}
+
+int hme_compute(hme_handle* h, double alpha_s, int64_t nevt, const double* momenta, double* me2, void* hip_stream) {
+  if (!h) return fail(HME_E_ARG, "hme_compute: handle is NULL");
+  if (nevt < 0) return fail(HME_E_ARG, "hme_compute: nevt < 0");
+  if (nevt == 0) return HME_OK;
+  if (!momenta || !me2) return fail(HME_E_ARG, "hme_compute: NULL momenta or me2");
+  if ((reinterpret_cast<uintptr_t>(momenta) | reinterpret_cast<uintptr_t>(me2)) & 7u)
+    return fail(HME_E_ARG, "hme_compute: pointers must be 8-byte aligned");
+  if (!(alpha_s > 0)) return fail(HME_E_ARG, "hme_compute: alpha_s must be positive");
+  DeviceGuard guard(h->device);
+  if (guard.err != hipSuccess) return hip_fail(guard.err, "hme_compute: hipSetDevice");
+  const double pi = 3.14159265358979323846;
+  const double gs2 = 4 * pi * alpha_s;
+  double norm = 1.0 / (h->info.iden * h->info.colour_denom);
+  for (int k = 0; k < h->info.gs_power / 2; ++k) norm *= gs2;
+  hme::LaunchArgs a{momenta, me2, nevt, h->d_goodhel, (int)h->goodhel.size(), h->prm, norm,
+                    static_cast<hipStream_t>(hip_stream)};
+  hipError_t e = hme::kProcs[h->process].me2(a, h->precision);
+  if (e != hipSuccess) return hip_fail(e, "hme_compute: launch");
+  return HME_OK;
+}
+
+int hme_query(const hme_handle* h, hme_info* info) {
+  if (!h || !info) return fail(HME_E_ARG, "hme_query: NULL argument");
+  std::memset(info, 0, sizeof *info);
+  info->process = h->process;
+  info->precision = h->precision;
+  info->npar = h->info.npar;
+  info->nhel = h->info.nhel;
+  info->ngoodhel = (int)h->goodhel.size();
+  info->ncol = h->info.ncol;
+  info->ndiag = h->info.ndiag;
+  info->namp = h->info.namp;
+  info->iden = h->info.iden;
+  info->flops_per_event = info->ngoodhel * h->info.flops_per_hel + h->info.flops_per_event;
+  info->bytes_per_event = h->info.npar * 4 * sizeof(double) + sizeof(double);
+  return HME_OK;
+}
+
+int hme_good_helicities(const hme_handle* h, int* out, int cap) {
+  if (!h || (!out && cap > 0) || cap < 0) return fail(HME_E_ARG, "hme_good_helicities: bad argument");
+  const int n = (int)h->goodhel.size();
+  for (int k = 0; k < n && k < cap; ++k) out[k] = h->goodhel[k];
+  return n;
+}
+
+int hme_destroy(hme_handle* h) {
+  if (!h) return HME_OK;
+  int rc = HME_OK;
+  if (h->d_goodhel) {
+    DeviceGuard guard(h->device);
+    hipError_t e = hipFree(h->d_goodhel);
+    if (e != hipSuccess) rc = hip_fail(e, "hme_destroy: hipFree");
+  }
+  delete h;
+  return rc;
+}
+
+}  // extern "C"

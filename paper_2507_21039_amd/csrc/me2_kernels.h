@@ -1,0 +1,130 @@
+// |M|^2 kernels: one event per group of LPE lanes, one good helicity per lane.
+//
+// A wavefront of 64 lanes holds 64 / LPE events.  Lane j of an event evaluates
+// the good helicities j, j + LPE, ... (the paper's helicity sum over
+// non-vanishing spin configurations, section "Parallel scattering amplitudes"):
+// external wavefunctions, the generated diagram sequence, the jamps and their
+// colour sum, all in registers.  The per-helicity |M_h|^2 are then summed
+// across the LPE lanes with butterfly shuffles in FP64, scaled by
+// g_s^(2n) / (IDEN * colour denominator), and lane 0 of the group stores the
+// event's result.  With LPE = 64 every lane of a wavefront reads the same
+// event record, so the momenta are wave-uniform.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "helas.h"
+#include "process.h"
+
+namespace hme {
+
+template <class Proc>
+HME_FN void load_event(const double* __restrict__ mom, int64_t ev, double (&p)[Proc::npar][4]) {
+  const double* src = mom + ev * (Proc::npar * 4);
+#pragma unroll
+  for (int k = 0; k < Proc::npar; ++k)
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) p[k][mu] = src[k * 4 + mu];
+}
+
+template <class Proc, class T, int LPE>
+__global__ void __launch_bounds__(256)
+    me2_kernel(const double* __restrict__ mom, double* __restrict__ out, int64_t nevt,
+               const int* __restrict__ goodhel, int ngood, ProcParams prm, double norm) {
+  constexpr int EPW = 64 / LPE;  // events per wavefront
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t ev = wave * EPW + lane / LPE;
+  const int sub = lane % LPE;
+  const int64_t evc = ev < nevt ? ev : nevt - 1;  // ragged tail: recompute the last event, store nothing
+  double p[Proc::npar][4];
+  load_event<Proc>(mom, evc, p);
+  double acc = 0.0;
+  for (int k = sub; k < ngood; k += LPE) {
+    cx<T> jamp[Proc::ncol];
+#pragma unroll
+    for (int c = 0; c < Proc::ncol; ++c) jamp[c] = {T(0), T(0)};
+    Proc::template amplitudes<T>(p, prm, (unsigned)goodhel[k], jamp);
+    acc += (double)Proc::template colour_sum<T>(jamp);
+  }
+#pragma unroll
+  for (int off = LPE / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (sub == 0 && ev < nevt) out[ev] = acc * norm;
+}
+
+// |M_h|^2 (colour-summed, unnormalised) for every helicity of a few events; used once at
+// set-up to find the helicities that vanish identically.
+template <class Proc>
+__global__ void __launch_bounds__(256) hel_kernel(const double* __restrict__ mom, int nev, ProcParams prm,
+                                                  double* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nev * Proc::nhel) return;
+  const int ev = t / Proc::nhel, h = t % Proc::nhel;
+  double p[Proc::npar][4];
+  load_event<Proc>(mom, ev, p);
+  cx<double> jamp[Proc::ncol];
+  for (int c = 0; c < Proc::ncol; ++c) jamp[c] = {0.0, 0.0};
+  Proc::template amplitudes<double>(p, prm, (unsigned)h, jamp);
+  out[t] = Proc::template colour_sum<double>(jamp);
+}
+
+// ------------------------------------------------------------------ launchers
+
+struct LaunchArgs {
+  const double* mom;
+  double* out;
+  int64_t nevt;
+  const int* goodhel;
+  int ngood;
+  ProcParams prm;
+  double norm;
+  hipStream_t stream;
+};
+
+struct ProcInfo {
+  int npar, nhel, ncol, ndiag, namp, gs_power;
+  double iden, colour_denom, flops_per_hel, flops_per_event;
+};
+
+template <class Proc> ProcInfo make_info() {
+  return ProcInfo{Proc::npar, Proc::nhel, Proc::ncol, Proc::ndiag, Proc::namp, Proc::gs_power,
+                  Proc::iden, Proc::colour_denom, Proc::flops_per_hel, Proc::flops_per_event};
+}
+
+// lanes per event: the smallest of 4, 16, 32, 64 that holds all good helicities (64 loops over more)
+inline int lanes_per_event(int ngood) {
+  if (ngood <= 4) return 4;
+  if (ngood <= 16) return 16;
+  if (ngood <= 32) return 32;
+  return 64;
+}
+
+template <class Proc, class T, int LPE> hipError_t launch_lpe(const LaunchArgs& a) {
+  constexpr int threads = 256;
+  constexpr int EPB = threads / LPE;  // events per block
+  const int64_t blocks = (a.nevt + EPB - 1) / EPB;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  me2_kernel<Proc, T, LPE><<<dim3((unsigned)blocks), dim3(threads), 0, a.stream>>>(
+      a.mom, a.out, a.nevt, a.goodhel, a.ngood, a.prm, a.norm);
+  return hipGetLastError();
+}
+
+template <class Proc, class T> hipError_t launch_me2(const LaunchArgs& a) {
+  switch (lanes_per_event(a.ngood)) {
+    case 4: return launch_lpe<Proc, T, 4>(a);
+    case 16: return launch_lpe<Proc, T, 16>(a);
+    case 32: return launch_lpe<Proc, T, 32>(a);
+    default: return launch_lpe<Proc, T, 64>(a);
+  }
+}
+
+template <class Proc>
+hipError_t launch_hel(const double* mom, int nev, const ProcParams& prm, double* out, hipStream_t s) {
+  const int n = nev * Proc::nhel;
+  hel_kernel<Proc><<<dim3((n + 255) / 256), dim3(256), 0, s>>>(mom, nev, prm, out);
+  return hipGetLastError();
+}
+
+}  // namespace hme

@@ -1,0 +1,17 @@
+// Kernels of one process (its own translation unit so processes compile in parallel).
+#include "me2_kernels.h"
+#include "procs/eemumu.h"
+
+namespace hme {
+
+ProcInfo info_eemumu() { return make_info<P_eemumu>(); }
+
+hipError_t launch_me2_eemumu(const LaunchArgs& a, int precision) {
+  return precision == 0 ? launch_me2<P_eemumu, double>(a) : launch_me2<P_eemumu, float>(a);
+}
+
+hipError_t launch_hel_eemumu(const double* mom, int nev, const ProcParams& prm, double* out, hipStream_t s) {
+  return launch_hel<P_eemumu>(mom, nev, prm, out, s);
+}
+
+}  // namespace hme

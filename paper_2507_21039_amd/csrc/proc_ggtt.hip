@@ -1,0 +1,17 @@
+// Kernels of one process (its own translation unit so processes compile in parallel).
+#include "me2_kernels.h"
+#include "procs/ggtt.h"
+
+namespace hme {
+
+ProcInfo info_ggtt() { return make_info<P_ggtt>(); }
+
+hipError_t launch_me2_ggtt(const LaunchArgs& a, int precision) {
+  return precision == 0 ? launch_me2<P_ggtt, double>(a) : launch_me2<P_ggtt, float>(a);
+}
+
+hipError_t launch_hel_ggtt(const double* mom, int nev, const ProcParams& prm, double* out, hipStream_t s) {
+  return launch_hel<P_ggtt>(mom, nev, prm, out, s);
+}
+
+}  // namespace hme

@@ -1,0 +1,17 @@
+// Kernels of one process (its own translation unit so processes compile in parallel).
+#include "me2_kernels.h"
+#include "procs/ggttg.h"
+
+namespace hme {
+
+ProcInfo info_ggttg() { return make_info<P_ggttg>(); }
+
+hipError_t launch_me2_ggttg(const LaunchArgs& a, int precision) {
+  return precision == 0 ? launch_me2<P_ggttg, double>(a) : launch_me2<P_ggttg, float>(a);
+}
+
+hipError_t launch_hel_ggttg(const double* mom, int nev, const ProcParams& prm, double* out, hipStream_t s) {
+  return launch_hel<P_ggttg>(mom, nev, prm, out, s);
+}
+
+}  // namespace hme

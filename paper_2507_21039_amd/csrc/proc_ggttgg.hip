@@ -1,0 +1,17 @@
+// Kernels of one process (its own translation unit so processes compile in parallel).
+#include "me2_kernels.h"
+#include "procs/ggttgg.h"
+
+namespace hme {
+
+ProcInfo info_ggttgg() { return make_info<P_ggttgg>(); }
+
+hipError_t launch_me2_ggttgg(const LaunchArgs& a, int precision) {
+  return precision == 0 ? launch_me2<P_ggttgg, double>(a) : launch_me2<P_ggttgg, float>(a);
+}
+
+hipError_t launch_hel_ggttgg(const double* mom, int nev, const ProcParams& prm, double* out, hipStream_t s) {
+  return launch_hel<P_ggttgg>(mom, nev, prm, out, s);
+}
+
+}  // namespace hme

@@ -1,0 +1,56 @@
+// Test-only: evaluates the generated process code on the host CPU (all helicities,
+// no filter) so the generator can be checked against the oracle without a GPU.
+// The library never uses this; its only compute path is the GPU kernel.
+#include <cstdint>
+#include <string>
+
+#include "../../paper_2507_21039_amd/csrc/params.h"
+#include "../../paper_2507_21039_amd/csrc/procs/eemumu.h"
+#include "../../paper_2507_21039_amd/csrc/procs/ggtt.h"
+#include "../../paper_2507_21039_amd/csrc/procs/ggttg.h"
+#include "../../paper_2507_21039_amd/csrc/procs/ggttgg.h"
+
+namespace {
+template <class Proc, class T>
+void run(const hme::ProcParams& prm, double alpha_s, int64_t nevt, const double* mom, double* out, double* per_hel) {
+  const double pi = 3.14159265358979323846;
+  double norm = 1.0 / (Proc::iden * Proc::colour_denom);
+  for (int k = 0; k < Proc::gs_power / 2; ++k) norm *= 4 * pi * alpha_s;
+  for (int64_t e = 0; e < nevt; ++e) {
+    double p[Proc::npar][4];
+    for (int k = 0; k < Proc::npar; ++k)
+      for (int mu = 0; mu < 4; ++mu) p[k][mu] = mom[(e * Proc::npar + k) * 4 + mu];
+    double acc = 0;
+    for (int h = 0; h < Proc::nhel; ++h) {
+      hme::cx<T> jamp[Proc::ncol];
+      for (auto& j : jamp) j = {T(0), T(0)};
+      Proc::template amplitudes<T>(p, prm, (unsigned)h, jamp);
+      const double v = (double)Proc::template colour_sum<T>(jamp) * norm;
+      if (per_hel) per_hel[e * Proc::nhel + h] = v;
+      acc += v;
+    }
+    out[e] = acc;
+  }
+}
+}  // namespace
+
+extern "C" int hostcheck_me2(int process, int precision, const double* card, double alpha_s, int64_t nevt,
+                             const double* mom, double* out, double* per_hel) {
+  hme_sm_card c{card[0], card[1], card[2], card[3], card[4], card[5]};
+  hme::ProcParams prm;
+  std::string why;
+  if (!hme::derive_params(c, prm, why)) return -1;
+  const bool f64 = precision == 0;
+  switch (process) {
+    case 0: f64 ? run<hme::P_eemumu, double>(prm, alpha_s, nevt, mom, out, per_hel)
+                : run<hme::P_eemumu, float>(prm, alpha_s, nevt, mom, out, per_hel); break;
+    case 1: f64 ? run<hme::P_ggtt, double>(prm, alpha_s, nevt, mom, out, per_hel)
+                : run<hme::P_ggtt, float>(prm, alpha_s, nevt, mom, out, per_hel); break;
+    case 2: f64 ? run<hme::P_ggttg, double>(prm, alpha_s, nevt, mom, out, per_hel)
+                : run<hme::P_ggttg, float>(prm, alpha_s, nevt, mom, out, per_hel); break;
+    case 3: f64 ? run<hme::P_ggttgg, double>(prm, alpha_s, nevt, mom, out, per_hel)
+                : run<hme::P_ggttgg, float>(prm, alpha_s, nevt, mom, out, per_hel); break;
+    default: return -1;
+  }
+  return 0;
+}

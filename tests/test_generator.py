@@ -1,0 +1,91 @@
+"""The generator of the GPU path: diagram counts, exact colour matrices, and the generated
+call sequences evaluated on the host CPU against the oracle.
+
+The host evaluation compiles the generated process headers for the CPU (test-only
+build, tests/hostcheck); it checks the generator and the Lorentz routines before
+any GPU run.  The parity tests proper run the same code on the GPU.
+"""
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2507_21039_amd.gen import colour, diagrams
+from workloads import configs
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+HOSTLIB = os.path.join(HERE, "_build", "libhostcheck.so")
+
+
+def test_diagram_counts():
+    # 3 / 16 / 123 / 1240 tree diagrams for g g -> t tbar + 0..3 g (four-gluon vertex counted once)
+    assert [len(diagrams.diagrams(tuple([0, 1] + list(range(4, 4 + n))))) for n in range(4)] == [3, 16, 123, 1240]
+
+
+def test_helicity_and_colour_counts():
+    assert [2 ** (4 + n) for n in range(4)] == [16, 32, 64, 128]
+    assert [len(colour.orderings(range(n + 2))) for n in range(4)] == [2, 6, 24, 120]
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5])
+def test_exact_colour_matrix_matches_oracle(n):
+    basis, C = colour.colour_matrix(range(n))
+    exact = np.array([[float(x) for x in row] for row in C])
+    assert np.abs(exact - oracle.colour_matrix(n)).max() <= 1e-13 * np.abs(exact).max()
+    N, D = colour.integer_form(C)
+    assert D == {2: 3, 3: 9, 4: 54, 5: 324}[n]
+    assert all(x == N[i][i] for i, row in enumerate(N) for x in [row[i]])
+
+
+def test_jamp_coefficients_are_units():
+    for n in range(3):
+        g = diagrams.build_graph(n)
+        for a in g.amps:
+            for c in a.colour.terms.values():
+                assert abs(c.re) + abs(c.im) == 1
+
+
+def _hostlib():
+    os.makedirs(os.path.dirname(HOSTLIB), exist_ok=True)
+    src = os.path.join(HERE, "hostcheck", "hostcheck.hip")
+    deps = [src] + [os.path.join(HERE, "..", "paper_2507_21039_amd", "csrc", f)
+                    for f in ("helas.h", "params.h", "procs/ggttgg.h")]
+    if not os.path.exists(HOSTLIB) or os.path.getmtime(HOSTLIB) < max(os.path.getmtime(d) for d in deps):
+        subprocess.run(["/opt/rocm/bin/hipcc", "-O1", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
+                        "-x", "hip", src, "-o", HOSTLIB], check=True)
+    L = ctypes.CDLL(HOSTLIB)
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.hostcheck_me2.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_double, ctypes.c_int64, dp, dp, dp]
+    return L
+
+
+@pytest.fixture(scope="module")
+def hostlib():
+    if not os.path.exists("/opt/rocm/bin/hipcc"):
+        pytest.skip("hipcc not available")
+    return _hostlib()
+
+
+def host_me2(L, proc, prec, p, card, alpha_s=0.118):
+    dp = ctypes.POINTER(ctypes.c_double)
+    p = np.ascontiguousarray(p)
+    card = np.ascontiguousarray(card)
+    out = np.empty(len(p))
+    assert L.hostcheck_me2(proc, prec, card.ctypes.data_as(dp), alpha_s, len(p), p.ctypes.data_as(dp),
+                           out.ctypes.data_as(dp), None) == 0
+    return out
+
+
+@pytest.mark.parametrize("key,proc,n", [("eemumu", 0, 4000), ("ggtt", 1, 4000), ("ggttg", 2, 600),
+                                        ("ggttgg", 3, 150)])
+def test_generated_code_on_host_matches_oracle(hostlib, card, key, proc, n):
+    p = configs.WORKLOADS[key].momenta(n)
+    ref = oracle.me2(proc, p, card)
+    got = host_me2(hostlib, proc, 0, p, card)
+    assert np.abs(got / ref - 1).max() <= 1e-13
+    mixed = host_me2(hostlib, proc, 1, p, card)
+    assert np.abs(mixed / ref - 1).max() <= 1e-5

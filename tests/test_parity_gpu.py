@@ -1,0 +1,173 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same seeded inputs.
+
+Tolerances: the FP64 path must agree with the FP64 oracle to 1e-12 relative in every
+event (the two evaluations share no code and differ only in rounding order); the mixed
+path (single-precision vertices, propagators, jamps and colour sum) to 1e-5 relative.
+Sizes span many wavefronts and end in a ragged tail; the full-size configurations are
+checked on sampled events in the launch configuration the benchmark uses.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2507_21039_amd as hme
+from workloads import configs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+FP64_TOL = 1e-12
+MIXED_TOL = 1e-5
+AS = 0.118
+
+CASES = [("eemumu", hme.EEMUMU, 16384), ("ggtt", hme.GGTT, 20011), ("ggttg", hme.GGTTG, 6007),
+         ("ggttgg", hme.GGTTGG, 2003)]
+
+
+@pytest.fixture(scope="module")
+def card():
+    return configs.card_array()
+
+
+@pytest.fixture(scope="module")
+def handles(card):
+    hs = {}
+    for _, proc, _ in CASES:
+        for prec in (hme.FP64, hme.MIXED):
+            print(f"[gpu] create process={proc} precision={prec}", flush=True)
+            hs[(proc, prec)] = hme.Handle(proc, card, prec)
+    yield hs
+    for h in hs.values():
+        h.close()
+
+
+def run(h, p, alpha_s=AS):
+    t = torch.from_numpy(np.ascontiguousarray(p)).cuda()
+    out = h.compute(t, alpha_s=alpha_s)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("key,proc,n", CASES)
+def test_fp64_parity(handles, card, key, proc, n):
+    print(f"[gpu] fp64 parity {key} n={n}", flush=True)
+    p = configs.WORKLOADS[key].momenta(n)
+    ref = oracle.me2(proc, p, card, AS)
+    got = run(handles[(proc, hme.FP64)], p)
+    rel = np.abs(got / ref - 1)
+    print(f"  max {rel.max():.3g} p99 {np.quantile(rel, 0.99):.3g} median {np.median(rel):.3g}")
+    assert np.all(np.isfinite(got))
+    assert rel.max() <= FP64_TOL
+
+
+@pytest.mark.parametrize("key,proc,n", CASES)
+def test_mixed_parity(handles, card, key, proc, n):
+    print(f"[gpu] mixed parity {key} n={n}", flush=True)
+    p = configs.WORKLOADS[key].momenta(n)
+    ref = oracle.me2(proc, p, card, AS)
+    got = run(handles[(proc, hme.MIXED)], p)
+    rel = np.abs(got / ref - 1)
+    print(f"  max {rel.max():.3g} p99 {np.quantile(rel, 0.99):.3g} median {np.median(rel):.3g}")
+    assert rel.max() <= MIXED_TOL
+
+
+def test_eemumu_closed_form_on_gpu(handles, card):
+    """All C1 events against the closed form (photon + Z, massless leptons)."""
+    p = configs.WORKLOADS["eemumu"].momenta()
+    got = run(handles[(hme.EEMUMU, hme.FP64)], p)
+    ew = oracle.ew(card)
+    sw2, cw2, e = ew["sw2"], ew["cw2"], ew["e"]
+    mZ, wZ = card[0], card[1]
+
+    def mdot(a, b):
+        return a[..., 0] * b[..., 0] - (a[..., 1:] * b[..., 1:]).sum(-1)
+
+    s = mdot(p[:, 0] + p[:, 1], p[:, 0] + p[:, 1])
+    t = mdot(p[:, 1] - p[:, 3], p[:, 1] - p[:, 3])
+    u = mdot(p[:, 1] - p[:, 2], p[:, 1] - p[:, 2])
+    gL, gR = -0.5 + sw2, sw2
+    A = lambda gi, gj: 1 / s + gi * gj / (sw2 * cw2) / (s - mZ ** 2 + 1j * mZ * wZ)
+    cf = e ** 4 * ((abs(A(gL, gL)) ** 2 + abs(A(gR, gR)) ** 2) * u ** 2
+                   + (abs(A(gL, gR)) ** 2 + abs(A(gR, gL)) ** 2) * t ** 2)
+    assert np.abs(got / cf - 1).max() <= 1e-12
+
+
+def test_good_helicities(handles):
+    # massless leptons: only the 4 chirality-allowed configurations survive
+    assert len(handles[(hme.EEMUMU, hme.FP64)].good_helicities()) == 4
+    for proc, nhel in [(hme.GGTT, 16), (hme.GGTTG, 32), (hme.GGTTGG, 64)]:
+        info = handles[(proc, hme.FP64)].query()
+        assert info["nhel"] == nhel
+        assert 0 < info["ngoodhel"] <= nhel
+
+
+def test_query_constants(handles):
+    expect = {hme.EEMUMU: (4, 1, 2, 4.0), hme.GGTT: (4, 2, 3, 256.0), hme.GGTTG: (5, 6, 16, 256.0),
+              hme.GGTTGG: (6, 24, 123, 512.0)}
+    for proc, (npar, ncol, ndiag, iden) in expect.items():
+        q = handles[(proc, hme.FP64)].query()
+        assert (q["npar"], q["ncol"], q["ndiag"], q["iden"]) == (npar, ncol, ndiag, iden)
+        assert q["flops_per_event"] > 0 and q["bytes_per_event"] == npar * 32 + 8
+
+
+def test_edge_sizes_and_batch_independence(handles, card):
+    """nevt = 0, 1, 63, 65 and split batches give bitwise the same per-event values."""
+    h = handles[(hme.GGTTG, hme.FP64)]
+    p = configs.WORKLOADS["ggttg"].momenta(300)
+    whole = run(h, p)
+    for a, b in [(0, 1), (1, 64), (64, 129), (129, 300)]:
+        part = run(h, p[a:b])
+        assert np.array_equal(part, whole[a:b])
+    t = torch.from_numpy(p).cuda()
+    out = torch.full((4,), -1.0, dtype=torch.float64, device="cuda")
+    h.compute_ptr(AS, 0, t.data_ptr(), out.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert torch.all(out == -1.0)
+
+
+def test_alpha_s_scaling(handles):
+    h = handles[(hme.GGTTGG, hme.FP64)]
+    p = configs.WORKLOADS["ggttgg"].momenta(100)
+    a = run(h, p, 0.118)
+    b = run(h, p, 0.236)
+    assert np.abs(b / a / 2 ** 4 - 1).max() <= 1e-14
+
+
+def test_argument_errors_on_gpu(handles, card):
+    h = handles[(hme.GGTT, hme.FP64)]
+    t = torch.zeros((8, 4, 4), dtype=torch.float64, device="cuda")
+    out = torch.zeros(8, dtype=torch.float64, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    with pytest.raises(hme.HmeError) as e:
+        h.compute_ptr(AS, -1, t.data_ptr(), out.data_ptr(), s)
+    assert e.value.code == hme.HME_E_ARG
+    with pytest.raises(hme.HmeError):
+        h.compute_ptr(AS, 8, t.data_ptr() + 4, out.data_ptr(), s)  # misaligned
+    with pytest.raises(hme.HmeError):
+        h.compute_ptr(AS, 8, 0, out.data_ptr(), s)
+    with pytest.raises(hme.HmeError):
+        h.compute_ptr(-1.0, 8, t.data_ptr(), out.data_ptr(), s)
+    with pytest.raises(hme.HmeError):
+        hme.Handle(hme.GGTT, card, hme.FP64, device=999)
+
+
+def test_nan_in_nan_out(handles):
+    h = handles[(hme.GGTT, hme.FP64)]
+    p = configs.WORKLOADS["ggtt"].momenta(64)
+    p[5, 2, 1] = np.nan
+    got = run(h, p)
+    assert np.isnan(got[5]) and np.all(np.isfinite(np.delete(got, 5)))
+
+
+@pytest.mark.parametrize("key,proc", [("ggtt", hme.GGTT), ("ggttg", hme.GGTTG), ("ggttgg", hme.GGTTGG)])
+def test_full_size_sampled(handles, card, key, proc):
+    """Full configuration size in the benchmark's launch, checked on 256 sampled events."""
+    w = configs.WORKLOADS[key]
+    print(f"[gpu] full size {key} n={w.nevt}", flush=True)
+    p = w.momenta()
+    got = run(handles[(proc, hme.FP64)], p)
+    assert np.all(np.isfinite(got)) and np.all(got > 0)
+    idx = np.unique(np.concatenate([np.random.default_rng(9).integers(0, w.nevt, 250), [0, w.nevt - 1]]))
+    ref = oracle.me2(proc, p[idx], card, AS)
+    assert np.abs(got[idx] / ref - 1).max() <= FP64_TOL
