@@ -48,9 +48,13 @@ typedef struct {
 enum hme_process { HME_EEMUMU = 0, HME_GGTT = 1, HME_GGTTG = 2, HME_GGTTGG = 3 };
 
 /* HME_FP64: every step in double precision.
- * HME_MIXED: vertices, propagators and jamps in single precision; external
- * wavefunctions, propagator denominators and the helicity/event sums in double. */
-enum hme_precision { HME_FP64 = 0, HME_MIXED = 1 };
+ * HME_MIXED_FAST: vertices, propagators, jamps and the colour sum in single
+ *   precision; external wavefunctions, propagator denominators and the
+ *   helicity/event sums in double.
+ * HME_MIXED_PAPER: the paper's mixed mode (section "Numerical stability"):
+ *   amplitudes and jamps in double, cast to single precision for the colour
+ *   algebra; helicity/event sums in double. */
+enum hme_precision { HME_FP64 = 0, HME_MIXED_FAST = 1, HME_MIXED_PAPER = 2, HME_MIXED = HME_MIXED_FAST };
 
 enum hme_status {
   HME_OK = 0,

@@ -13,7 +13,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhme.so")
 
 EEMUMU, GGTT, GGTTG, GGTTGG = 0, 1, 2, 3
-FP64, MIXED = 0, 1
+FP64, MIXED_FAST, MIXED_PAPER = 0, 1, 2
+MIXED = MIXED_FAST
+PRECISION_NAMES = {FP64: "fp64", MIXED_FAST: "mixed_fast", MIXED_PAPER: "mixed_paper"}
 NPAR = {EEMUMU: 4, GGTT: 4, GGTTG: 5, GGTTGG: 6}
 PROCESS_NAMES = {EEMUMU: "e+e- -> mu+mu-", GGTT: "gg -> ttbar", GGTTG: "gg -> ttbar g", GGTTGG: "gg -> ttbar gg"}
 

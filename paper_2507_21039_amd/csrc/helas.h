@@ -19,6 +19,14 @@
 
 #define HME_FN __host__ __device__ __forceinline__
 
+// The per-event table lives in LDS on the GPU; its pointer carries the LDS address
+// space there so that reads become ds_read (on the host, for tests, it is a plain pointer).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define HME_LDS __attribute__((address_space(3)))
+#else
+#define HME_LDS
+#endif
+
 namespace hme {
 
 template <class T> struct cx {
@@ -303,6 +311,96 @@ template <int S, class T> HME_FN vw4<T> vvvv_vec(const vw4<T>& a, const vw4<T>& 
     for (int mu = 0; mu < 4; ++mu) J.c[mu] = x * c.c[mu] - y * b.c[mu];
   }
   return J;
+}
+
+}  // namespace hme
+
+namespace hme {
+
+// Momentum sums and propagator denominators are read from the per-event table
+// that the kernel keeps in LDS.  The reads are volatile so that every use loads
+// the value again instead of the compiler keeping it in a register across the
+// whole diagram sequence (register pressure, not LDS traffic, is the limit).
+typedef const volatile HME_LDS double* tab_ptr;
+
+template <class T> struct m4 {
+  T v[4];
+  HME_FN const T& operator[](int i) const { return v[i]; }
+  HME_FN operator const T*() const { return v; }
+};
+
+template <class T> HME_FN m4<T> qv(tab_ptr tab, int i) {
+  return m4<T>{{T(tab[4 * i]), T(tab[4 * i + 1]), T(tab[4 * i + 2]), T(tab[4 * i + 3])}};
+}
+
+template <class T> HME_FN T dv(tab_ptr tab, int i) { return T(tab[i]); }
+
+}  // namespace hme
+
+namespace hme {
+
+// ------------------------------------------------------------------ per-event kits
+// The helicity-independent parts of the external states, computed once per event
+// into the LDS table; each lane then builds the state of its own helicity with a
+// few multiplies and selects, at every use.
+
+// Massless vector: kit = (e1x, e1y, e1z, e2x, e2y) / sqrt(2) (e1 and e2 as in vxxxxx; e2z = 0).
+HME_FN void vector_kit(const double* k, double* kit) {
+  const double pt2 = k[1] * k[1] + k[2] * k[2];
+  const double pt = sqrt(pt2);
+  const double P = sqrt(pt2 + k[3] * k[3]);
+  const double ct = k[3] / P, st = pt / P;
+  const double cp = pt > 0 ? k[1] / pt : 1.0, sp = pt > 0 ? k[2] / pt : 0.0;
+  const double r = 0.70710678118654752440;
+  kit[0] = r * ct * cp;
+  kit[1] = r * ct * sp;
+  kit[2] = -r * st;
+  kit[3] = -r * sp;
+  kit[4] = r * cp;
+}
+
+// Fermion: kit = (chi_+[0], chi_+[1], chi_-[0], chi_-[1] as (re, im) pairs, sqrt(E+|p|), sqrt(E-|p|)).
+HME_FN void fermion_kit(const double* p, double m, double* kit) {
+  cx<double> cp[2], cm[2];
+  helicity_chi(p, +1, cp);
+  helicity_chi(p, -1, cm);
+  double wp, wm;
+  spinor_weights(p, m, wp, wm);
+  kit[0] = cp[0].r; kit[1] = cp[0].i; kit[2] = cp[1].r; kit[3] = cp[1].i;
+  kit[4] = cm[0].r; kit[5] = cm[0].i; kit[6] = cm[1].r; kit[7] = cm[1].i;
+  kit[8] = wp;
+  kit[9] = wm;
+}
+
+// eps(k, lam) (nsv = -1, incoming) or conj(eps) (nsv = +1, outgoing) from a vector kit.
+template <class T> HME_FN vw4<T> vxxxxx_kit(tab_ptr kit, int lam, int nsv) {
+  const T a = T(-lam), b = nsv < 0 ? T(-1) : T(1);
+  vw4<T> w;
+  w.c[0] = {T(0), T(0)};
+  w.c[1] = {a * T(kit[0]), b * T(kit[3])};
+  w.c[2] = {a * T(kit[1]), b * T(kit[4])};
+  w.c[3] = {a * T(kit[2]), T(0)};
+  return w;
+}
+
+// ubar(p, lam) of an outgoing fermion from a fermion kit (same state as oxxxxx with nsf = +1).
+template <class T> HME_FN sp4<T> oxxxxx_kit(tab_ptr kit, int lam) {
+  const bool plus = lam > 0;
+  const cx<T> c0 = {T(plus ? kit[0] : kit[4]), T(plus ? -kit[1] : -kit[5])};  // conj(chi)
+  const cx<T> c1 = {T(plus ? kit[2] : kit[6]), T(plus ? -kit[3] : -kit[7])};
+  const T wp = T(kit[8]), wm = T(kit[9]);
+  const T a = plus ? wp : wm, b = plus ? wm : wp;
+  return {{a * c0, a * c1, b * c0, b * c1}};
+}
+
+// v(p, lam) of an outgoing antifermion from a fermion kit (same state as ixxxxx with nsf = -1).
+template <class T> HME_FN sp4<T> ixxxxx_kit(tab_ptr kit, int lam) {
+  const bool plus = lam > 0;
+  const cx<T> c0 = {T(plus ? kit[4] : kit[0]), T(plus ? kit[5] : kit[1])};  // chi_{-lam}
+  const cx<T> c1 = {T(plus ? kit[6] : kit[2]), T(plus ? kit[7] : kit[3])};
+  const T wp = T(kit[8]), wm = T(kit[9]);
+  const T a = plus ? wp : wm, b = plus ? wm : wp;
+  return {{a * c0, a * c1, -b * c0, -b * c1}};
 }
 
 }  // namespace hme

@@ -148,7 +148,8 @@ int hme_create(int process, const hme_sm_card* card, int precision, int device, 
   *out = nullptr;
   if (!card) return fail(HME_E_ARG, "hme_create: card is NULL");
   if (process < 0 || process >= hme::kNumProcs) return fail(HME_E_ARG, "hme_create: unknown process");
-  if (precision != HME_FP64 && precision != HME_MIXED) return fail(HME_E_ARG, "hme_create: unknown precision");
+  if (precision != HME_FP64 && precision != HME_MIXED_FAST && precision != HME_MIXED_PAPER)
+    return fail(HME_E_ARG, "hme_create: unknown precision");
   int ndev = 0;
   hipError_t e = hipGetDeviceCount(&ndev);
   if (e != hipSuccess) return hip_fail(e, "hme_create: hipGetDeviceCount");
@@ -228,7 +229,7 @@ int hme_compute(hme_handle* h, double alpha_s, int64_t nevt, const double* momen
   double norm = 1.0 / (h->info.iden * h->info.colour_denom);
   for (int k = 0; k < h->info.gs_power / 2; ++k) norm *= gs2;
   hme::LaunchArgs a{momenta, me2, nevt, h->d_goodhel, (int)h->goodhel.size(), h->prm, norm,
-                    static_cast<hipStream_t>(hip_stream)};
+                    static_cast<hipStream_t>(hip_stream), h->precision == HME_MIXED_PAPER ? 1 : 0};
   hipError_t e = hme::kProcs[h->process].me2(a, h->precision);
   if (e != hipSuccess) return hip_fail(e, "hme_compute: launch");
   return HME_OK;

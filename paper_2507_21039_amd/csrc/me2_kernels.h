@@ -8,7 +8,9 @@
 // across the LPE lanes with butterfly shuffles in FP64, scaled by
 // g_s^(2n) / (IDEN * colour denominator), and lane 0 of the group stores the
 // event's result.  With LPE = 64 every lane of a wavefront reads the same
-// event record, so the momenta are wave-uniform.
+// event record, so the momenta are wave-uniform.  The helicity-independent
+// quantities (momentum sums, propagator denominators) are computed once per
+// event by its lanes into an LDS table before the helicity loop.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -32,22 +34,37 @@ HME_FN void load_event(const double* __restrict__ mom, int64_t ev, double (&p)[P
 template <class Proc, class T, int LPE>
 __global__ void __launch_bounds__(256)
     me2_kernel(const double* __restrict__ mom, double* __restrict__ out, int64_t nevt,
-               const int* __restrict__ goodhel, int ngood, ProcParams prm, double norm) {
-  constexpr int EPW = 64 / LPE;  // events per wavefront
+               const int* __restrict__ goodhel, int ngood, ProcParams prm, double norm, int colour_f32) {
+  constexpr int EPW = 64 / LPE;   // events per wavefront
+  constexpr int EPB = 256 / LPE;  // events per block
+  // per-event table of momentum sums and propagator denominators, shared by the event's lanes
+  __shared__ double table[EPB * (Proc::ntab > 0 ? Proc::ntab : 1)];
   const int lane = threadIdx.x & 63;
-  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int64_t ev = wave * EPW + lane / LPE;
+  // wave index in the block, made explicitly wave-uniform so that with LPE = 64 the
+  // event record is fetched with scalar loads
+  const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t ev = ((int64_t)blockIdx.x * 4 + wib) * EPW + lane / LPE;
   const int sub = lane % LPE;
   const int64_t evc = ev < nevt ? ev : nevt - 1;  // ragged tail: recompute the last event, store nothing
   double p[Proc::npar][4];
   load_event<Proc>(mom, evc, p);
+  double* tab = table + (threadIdx.x / LPE) * Proc::ntab;
+  for (int j = sub; j < Proc::nitems; j += LPE) Proc::table_entry(p, prm, j, tab);
+  __syncthreads();
   double acc = 0.0;
   for (int k = sub; k < ngood; k += LPE) {
     cx<T> jamp[Proc::ncol];
 #pragma unroll
     for (int c = 0; c < Proc::ncol; ++c) jamp[c] = {T(0), T(0)};
-    Proc::template amplitudes<T>(p, prm, (unsigned)goodhel[k], jamp);
-    acc += (double)Proc::template colour_sum<T>(jamp);
+    Proc::template amplitudes<T>(p, prm, (unsigned)goodhel[k], (tab_ptr)tab, jamp);
+    if (colour_f32) {  // wave-uniform: the colour algebra in single precision
+      cx<float> jf[Proc::ncol];
+#pragma unroll
+      for (int c = 0; c < Proc::ncol; ++c) jf[c] = cast<float>(jamp[c]);
+      acc += (double)Proc::template colour_sum<float>(jf);
+    } else {
+      acc += (double)Proc::template colour_sum<T>(jamp);
+    }
   }
 #pragma unroll
   for (int off = LPE / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
@@ -55,19 +72,24 @@ __global__ void __launch_bounds__(256)
 }
 
 // |M_h|^2 (colour-summed, unnormalised) for every helicity of a few events; used once at
-// set-up to find the helicities that vanish identically.
+// set-up to find the helicities that vanish identically.  One block of 64 lanes per
+// event; the event's table is built in LDS exactly as in me2_kernel.
 template <class Proc>
-__global__ void __launch_bounds__(256) hel_kernel(const double* __restrict__ mom, int nev, ProcParams prm,
-                                                  double* __restrict__ out) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nev * Proc::nhel) return;
-  const int ev = t / Proc::nhel, h = t % Proc::nhel;
+__global__ void __launch_bounds__(64) hel_kernel(const double* __restrict__ mom, int nev, ProcParams prm,
+                                                 double* __restrict__ out) {
+  __shared__ double table[Proc::ntab > 0 ? Proc::ntab : 1];
+  const int ev = blockIdx.x;
+  if (ev >= nev) return;  // uniform per block
   double p[Proc::npar][4];
   load_event<Proc>(mom, ev, p);
-  cx<double> jamp[Proc::ncol];
-  for (int c = 0; c < Proc::ncol; ++c) jamp[c] = {0.0, 0.0};
-  Proc::template amplitudes<double>(p, prm, (unsigned)h, jamp);
-  out[t] = Proc::template colour_sum<double>(jamp);
+  for (int j = threadIdx.x; j < Proc::nitems; j += blockDim.x) Proc::table_entry(p, prm, j, table);
+  __syncthreads();
+  for (int h = threadIdx.x; h < Proc::nhel; h += blockDim.x) {
+    cx<double> jamp[Proc::ncol];
+    for (int c = 0; c < Proc::ncol; ++c) jamp[c] = {0.0, 0.0};
+    Proc::template amplitudes<double>(p, prm, (unsigned)h, (tab_ptr)table, jamp);
+    out[(size_t)ev * Proc::nhel + h] = Proc::template colour_sum<double>(jamp);
+  }
 }
 
 // ------------------------------------------------------------------ launchers
@@ -81,6 +103,7 @@ struct LaunchArgs {
   ProcParams prm;
   double norm;
   hipStream_t stream;
+  int colour_f32;  // colour sum in single precision (for double-precision amplitudes)
 };
 
 struct ProcInfo {
@@ -107,11 +130,13 @@ template <class Proc, class T, int LPE> hipError_t launch_lpe(const LaunchArgs& 
   const int64_t blocks = (a.nevt + EPB - 1) / EPB;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   me2_kernel<Proc, T, LPE><<<dim3((unsigned)blocks), dim3(threads), 0, a.stream>>>(
-      a.mom, a.out, a.nevt, a.goodhel, a.ngood, a.prm, a.norm);
+      a.mom, a.out, a.nevt, a.goodhel, a.ngood, a.prm, a.norm, a.colour_f32);
   return hipGetLastError();
 }
 
 template <class Proc, class T> hipError_t launch_me2(const LaunchArgs& a) {
+  // processes with 64 or more helicities always fill whole wavefronts (idle lanes are masked)
+  if constexpr (Proc::nhel >= 64) return launch_lpe<Proc, T, 64>(a);
   switch (lanes_per_event(a.ngood)) {
     case 4: return launch_lpe<Proc, T, 4>(a);
     case 16: return launch_lpe<Proc, T, 16>(a);
@@ -122,8 +147,7 @@ template <class Proc, class T> hipError_t launch_me2(const LaunchArgs& a) {
 
 template <class Proc>
 hipError_t launch_hel(const double* mom, int nev, const ProcParams& prm, double* out, hipStream_t s) {
-  const int n = nev * Proc::nhel;
-  hel_kernel<Proc><<<dim3((n + 255) / 256), dim3(256), 0, s>>>(mom, nev, prm, out);
+  hel_kernel<Proc><<<dim3(nev), dim3(64), 0, s>>>(mom, nev, prm, out);
   return hipGetLastError();
 }
 

@@ -6,8 +6,10 @@ namespace hme {
 
 ProcInfo info_eemumu() { return make_info<P_eemumu>(); }
 
+// precision 1 (single-precision amplitudes) has its own kernel; 0 and 2 share the
+// double-precision one and differ in the colour-sum type only.
 hipError_t launch_me2_eemumu(const LaunchArgs& a, int precision) {
-  return precision == 0 ? launch_me2<P_eemumu, double>(a) : launch_me2<P_eemumu, float>(a);
+  return precision != 1 ? launch_me2<P_eemumu, double>(a) : launch_me2<P_eemumu, float>(a);
 }
 
 hipError_t launch_hel_eemumu(const double* mom, int nev, const ProcParams& prm, double* out, hipStream_t s) {

@@ -6,8 +6,10 @@ namespace hme {
 
 ProcInfo info_ggttg() { return make_info<P_ggttg>(); }
 
+// precision 1 (single-precision amplitudes) has its own kernel; 0 and 2 share the
+// double-precision one and differ in the colour-sum type only.
 hipError_t launch_me2_ggttg(const LaunchArgs& a, int precision) {
-  return precision == 0 ? launch_me2<P_ggttg, double>(a) : launch_me2<P_ggttg, float>(a);
+  return precision != 1 ? launch_me2<P_ggttg, double>(a) : launch_me2<P_ggttg, float>(a);
 }
 
 hipError_t launch_hel_ggttg(const double* mom, int nev, const ProcParams& prm, double* out, hipStream_t s) {

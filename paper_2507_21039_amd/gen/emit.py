@@ -57,7 +57,30 @@ def _common_phase(amps):
     return Gauss(0, -1) if allim else Gauss(1, 0)
 
 
-def emit_qcd(name: str, g, label: str) -> tuple[str, dict]:
+def _closure(g, keys):
+    out = set()
+    stack = list(keys)
+    while stack:
+        k = stack.pop()
+        if k in out or k[0] == "E":
+            continue
+        out.add(k)
+        stack.extend(g.nodes[k].args)
+    return out
+
+
+NODE_FLOPS = {"vvv": "vvv_vec", "vvvv": "vvvv_vec", "psi": "ffv_psi", "psibar": "ffv_psibar", "qq": "ffv_vec"}
+KIT_FLOPS = {"ext_v": 4, "ext_o": 12, "ext_i": 12}  # building a wavefunction from its per-event kit
+
+
+def emit_qcd(name: str, g, label: str, budget: int = 8) -> tuple[str, dict]:
+    """Emit the process header.
+
+    budget: number of off-shell wavefunctions kept live at once.  When the
+    schedule needs more, the wavefunction whose next use is farthest away is
+    dropped and recomputed when needed again (Belady's rule).  External
+    wavefunctions are rebuilt at every use from a per-event kit in the LDS table.
+    """
     npar = g.npar
     gl = tuple(sorted(g.gluons))
     basis, C = colour_mod.colour_matrix(gl)
@@ -68,164 +91,184 @@ def emit_qcd(name: str, g, label: str) -> tuple[str, dict]:
 
     node_ids = {k: i for i, k in enumerate(g.nodes)}
     lines = []
-    emitted = set()
-    flops = 0
-    masks_needed = {}
-
-    def var(key):
-        return f"w{node_ids[key]}"
+    qidx = {}  # (mask, sign) -> index of a momentum sum in the table
+    didx = {}  # mask -> (index, massive)
+    kit_of = {}  # external particle -> table offset of its kit (filled below)
+    flops_exec = 0
+    flops_dag = 0
 
     def mom(mask, sign=1):
-        masks_needed[mask] = True
-        return f"Q{mask}" if sign > 0 else f"mQ{mask}"
+        key = (mask, sign)
+        if key not in qidx:
+            qidx[key] = len(qidx)
+        return f"qv<T>(tab, {qidx[key]})"
 
-    def den_name(mask):
-        return f"d{mask}"
+    def den(mask, massive):
+        if mask not in didx:
+            didx[mask] = (len(didx), massive)
+        return f"dv<T>(tab, DOFF + {didx[mask][0]})"
 
-    def emit_node(key):
-        nonlocal flops
-        if key in emitted:
+    # ---- schedule with a bounded number of live wavefunctions
+    from .diagrams import schedule
+    import bisect
+    order = schedule(g)
+    amp_nodes = [_closure(g, g.amps[i].args) for i in order]
+    uses = {}
+    for t, s in enumerate(amp_nodes):
+        for k in s:
+            uses.setdefault(k, []).append(t)
+
+    def next_use(k, t):
+        u = uses[k]
+        i = bisect.bisect_right(u, t)
+        return u[i] if i < len(u) else 1 << 30
+
+    live = {}  # node key -> variable name of its current value
+    version = {}
+    now = [0]
+    computed_once = set()
+
+    def ext_expr(key, out_lines):
+        """Build an external wavefunction from its kit into a fresh local, return the name."""
+        nonlocal flops_exec
+        k = key[1]
+        kind = g.nodes[key].kind
+        nm = f"e{k}_{len(out_lines)}"
+        if kind == "ext_v":
+            nsv = -1 if k < 2 else 1
+            out_lines.append(f"    const vw4<T> {nm} = vxxxxx_kit<T>(tab + KOFF{k}, hel({k}), {nsv});")
+        elif kind == "ext_o":
+            out_lines.append(f"    const sp4<T> {nm} = oxxxxx_kit<T>(tab + KOFF{k}, hel({k}));")
+        else:
+            out_lines.append(f"    const sp4<T> {nm} = ixxxxx_kit<T>(tab + KOFF{k}, hel({k}));")
+        flops_exec += KIT_FLOPS[kind]
+        return nm
+
+    def arg(key, pre):
+        if key[0] == "E":
+            return ext_expr(key, pre)
+        return live[key]
+
+    def need(key, pinned):
+        nonlocal flops_exec, flops_dag
+        if key[0] == "E" or key in live:
             return
         n = g.nodes[key]
         for a in n.args:
-            emit_node(a)
-        v = var(key)
-        if n.kind == "ext_v":
-            k = key[1]
-            nsv = -1 if k < 2 else 1
-            lines.append(f"  const vw4<T> {v} = cast<T>(vxxxxx(p[{k}], hel({k}), {nsv}));")
-            flops += EXT_FLOPS["vxxxxx"]
-        elif n.kind == "ext_o":
-            lines.append(f"  const sp4<T> {v} = cast<T>(oxxxxx(p[{TOP}], prm.mT, hel({TOP}), +1));")
-            flops += EXT_FLOPS["oxxxxx"]
-        elif n.kind == "ext_i":
-            lines.append(f"  const sp4<T> {v} = cast<T>(ixxxxx(p[{ATOP}], prm.mT, hel({ATOP}), -1));")
-            flops += EXT_FLOPS["ixxxxx"]
-        elif n.kind == "vvv":
-            a, b = n.args
-            ma, mb = g.nodes[a].mask, g.nodes[b].mask
-            lines.append(f"  const vw4<T> {v} = vvv_vec<T>({var(a)}, {mom(ma)}, {var(b)}, {mom(mb)}, "
-                         f"{den_name(n.mask)});")
-            masks_needed[n.mask] = True
-            flops += FLOPS["vvv_vec"]
+            need(a, pinned | {key})
+        pre = []
+        args = [arg(a, pre) for a in n.args]
+        version[key] = version.get(key, -1) + 1
+        v = f"w{node_ids[key]}" + (f"_{version[key]}" if version[key] else "")
+        if n.kind == "vvv":
+            ma, mb = g.nodes[n.args[0]].mask, g.nodes[n.args[1]].mask
+            call = f"vw4<T> {v} = vvv_vec<T>({args[0]}, {mom(ma)}, {args[1]}, {mom(mb)}, {den(n.mask, False)});"
         elif n.kind == "vvvv":
-            a, b, c = n.args
-            s = n.extra[0]
-            lines.append(f"  const vw4<T> {v} = vvvv_vec<{s}, T>({var(a)}, {var(b)}, {var(c)}, {den_name(n.mask)});")
-            masks_needed[n.mask] = True
-            flops += FLOPS["vvvv_vec"]
+            call = f"vw4<T> {v} = vvvv_vec<{n.extra[0]}, T>({args[0]}, {args[1]}, {args[2]}, {den(n.mask, False)});"
         elif n.kind == "psi":
-            inner, t = n.args
-            lines.append(f"  const sp4<T> {v} = ffv_psi<T>({var(inner)}, {var(t)}, {mom(n.mask)}, mT, "
-                         f"{den_name(n.mask)});")
-            flops += FLOPS["ffv_psi"]
+            call = f"sp4<T> {v} = ffv_psi<T>({args[0]}, {args[1]}, {mom(n.mask)}, mT, {den(n.mask, True)});"
         elif n.kind == "psibar":
-            inner, t = n.args
-            lines.append(f"  const sp4<T> {v} = ffv_psibar<T>({var(inner)}, {var(t)}, {mom(n.mask, -1)}, mT, "
-                         f"{den_name(n.mask)});")
-            flops += FLOPS["ffv_psibar"]
+            call = f"sp4<T> {v} = ffv_psibar<T>({args[0]}, {args[1]}, {mom(n.mask, -1)}, mT, {den(n.mask, True)});"
         elif n.kind == "qq":
-            a, b = n.args
-            lines.append(f"  const vw4<T> {v} = ffv_vec<T>({var(a)}, {var(b)}, {den_name(n.mask)});")
-            masks_needed[n.mask] = True
-            flops += FLOPS["ffv_vec"]
+            call = f"vw4<T> {v} = ffv_vec<T>({args[0]}, {args[1]}, {den(n.mask, False)});"
         else:
             raise ValueError(n.kind)
-        emitted.add(key)
+        typ = call.split(" ", 1)[0]
+        name_rest = call.split(" ", 1)[1]
+        lines.append(f"  {typ} {v};")
+        lines.append("  {")
+        lines.extend(pre)
+        lines.append(f"    {name_rest.replace(v + ' =', v + ' =', 1)}")
+        lines.append("  }")
+        f = FLOPS[NODE_FLOPS[n.kind]]
+        flops_exec += f
+        if key not in computed_once:
+            flops_dag += f
+            computed_once.add(key)
+        live[key] = v
+        while len(live) > budget:
+            cands = [x for x in live if x not in pinned and x != key and x not in n.args]
+            if not cands:
+                break
+            victim = max(cands, key=lambda x: next_use(x, now[0]))
+            del live[victim]
 
     jamp_terms = 0
-    from .diagrams import schedule
-    for ia in schedule(g):
+    for t, ia in enumerate(order):
+        now[0] = t
         amp = g.amps[ia]
         for k in amp.args:
-            emit_node(k)
+            need(k, set(amp.args))
+        pre = []
+        args = [arg(k, pre) for k in amp.args]
         if amp.kind == "ffv":
-            fb, f, t = amp.args
-            call = f"ffv_amp<T>({var(fb)}, {var(f)}, {var(t)})"
-            flops += FLOPS["ffv_amp"]
+            call = f"ffv_amp<T>({args[0]}, {args[1]}, {args[2]})"
+            f = FLOPS["ffv_amp"]
         elif amp.kind == "vvv":
             a, b, q = amp.args
-            call = (f"vvv_amp<T>({var(a)}, {mom(g.nodes[a].mask)}, {var(b)}, {mom(g.nodes[b].mask)}, "
-                    f"{var(q)}, {mom(g.nodes[q].mask)})")
-            flops += FLOPS["vvv_amp"]
+            call = (f"vvv_amp<T>({args[0]}, {mom(g.nodes[a].mask)}, {args[1]}, {mom(g.nodes[b].mask)}, "
+                    f"{args[2]}, {mom(g.nodes[q].mask)})")
+            f = FLOPS["vvv_amp"]
         else:
-            a, b, c, q = amp.args
-            call = f"vvvv_amp<{amp.extra[0]}, T>({var(a)}, {var(b)}, {var(c)}, {var(q)})"
-            flops += FLOPS["vvvv_amp"]
+            call = f"vvvv_amp<{amp.extra[0]}, T>({args[0]}, {args[1]}, {args[2]}, {args[3]})"
+            f = FLOPS["vvvv_amp"]
+        flops_exec += f
+        flops_dag += f
         lines.append(f"  {{  // diagram {amp.diagram + 1}")
+        lines.extend(pre)
         lines.append(f"    const cx<T> a = {call};")
         for w, c in sorted(amp.colour.terms.items(), key=lambda x: widx[x[0]]):
-            cc = c * phase
             j = widx[w]
-            lines.append(f"    jamp[{j}] = jamp[{j}] {_coef_code(cc, 'a')};")
+            lines.append(f"    jamp[{j}] = jamp[{j}] {_coef_code(c * phase, 'a')};")
             jamp_terms += 1
         lines.append("  }")
-    flops += 2 * jamp_terms
+        for x in list(live):
+            if next_use(x, t) >= 1 << 30:
+                del live[x]
+    flops_exec += 2 * jamp_terms
+    ext_name = {"ext_v": "vxxxxx", "ext_o": "oxxxxx", "ext_i": "ixxxxx"}
+    flops_dag += 2 * jamp_terms + sum(EXT_FLOPS[ext_name[g.nodes[k].kind]] for k in g.nodes if k[0] == "E")
 
-    # momenta and denominators used above
-    pre = []
-    for k in range(npar):
-        sgn = "" if k < 2 else "-"
-        pre.append(f"  const T q{1 << k}[4] = {{{sgn}T(p[{k}][0]), {sgn}T(p[{k}][1]), {sgn}T(p[{k}][2]), "
-                   f"{sgn}T(p[{k}][3])}};")
-    # masks are bit sets over particles; build sums in increasing popcount
-    needed = set(masks_needed)
-    # closure: every mask's momentum from lowest bit + rest
-    allm = set()
-
-    def need(m):
-        if m in allm or m == 0:
-            return
-        allm.add(m)
-        low = m & -m
-        if m != low:
-            need(low)
-            need(m ^ low)
-
-    for m in needed:
-        need(m)
-    mom_lines = []
-    for m in sorted(allm, key=lambda x: (bin(x).count("1"), x)):
-        if m & (m - 1) == 0:
-            if m != 0:
-                mom_lines.append(f"  const T* Q{m} = q{m};")
-            continue
-        low = m & -m
-        mom_lines.append(f"  const T Q{m}[4] = {{Q{low}[0] + Q{m ^ low}[0], Q{low}[1] + Q{m ^ low}[1], "
-                         f"Q{low}[2] + Q{m ^ low}[2], Q{low}[3] + Q{m ^ low}[3]}};")
-    # negated momenta for barred currents, denominators
-    den_lines = []
-    for m in sorted(needed):
-        node_kinds = {n.kind for n in g.nodes.values() if n.mask == m}
-        fermion = bool(node_kinds & {"psi", "psibar"})
-        if fermion:
-            if "psibar" in node_kinds:
-                den_lines.append(f"  const T mQ{m}[4] = {{-Q{m}[0], -Q{m}[1], -Q{m}[2], -Q{m}[3]}};")
-            den_lines.append(f"  const T d{m} = T(1.0 / (sq(p, {m}) - prm.mT * prm.mT));")
-        elif any(n.kind in ("vvv", "vvvv", "qq") for n in g.nodes.values() if n.mask == m):
-            den_lines.append(f"  const T d{m} = T(1.0 / sq(p, {m}));")
-    nden = sum(1 for l in den_lines if " d" in l.split("=")[0])
-    flops_den = DEN_FLOPS * nden
+    nq, nd = len(qidx), len(didx)
+    ext = [k for k in range(npar)]
+    koff = {}
+    off = 4 * nq + nd
+    for k in ext:
+        koff[k] = off
+        off += 5 if g.nodes[("E", k)].kind == "ext_v" else 10
+    ntab = off
+    body = "\n".join(lines).replace("DOFF", str(4 * nq))
+    for k in ext:
+        body = body.replace(f"KOFF{k}", str(koff[k]))
+    qmask = [0] * nq
+    qsign = [0] * nq
+    for (m, sgn), i in qidx.items():
+        qmask[i], qsign[i] = m, sgn
+    dmask = [0] * nd
+    dmassive = [0] * nd
+    for m, (i, massive) in didx.items():
+        dmask[i], dmassive[i] = m, int(massive)
+    kind_code = {"ext_v": 0, "ext_o": 1, "ext_i": 2}
+    kits = [(koff[k], kind_code[g.nodes[("E", k)].kind], k) for k in ext]
+    flops_table = DEN_FLOPS * nd + 4 * nq + 40 * npar
 
     # colour sum with symmetric integer numerators
     cs = []
     cs_flops = 0
     for i in range(ncol):
-        terms = []
-        for j in range(i, ncol):
-            v = N[i][j] * (1 if i == j else 2)
-            if v == 0:
-                continue
-            terms.append((j, v))
+        terms = [(j, N[i][j] * (1 if i == j else 2)) for j in range(i, ncol) if N[i][j] != 0]
         if not terms:
             continue
         zr = " + ".join(f"T({v}) * jamp[{j}].r" for j, v in terms)
         zi = " + ".join(f"T({v}) * jamp[{j}].i" for j, v in terms)
-        cs.append(f"  s += jamp[{i}].r * ({zr}) + jamp[{i}].i * ({zi});")
+        cs.append(f"    s += jamp[{i}].r * ({zr}) + jamp[{i}].i * ({zi});")
         cs_flops += 4 * len(terms) + 4
+
+    nitems = nq + nd + npar
     hdr = f"""// Generated by paper_2507_21039_amd.gen for {label}.  Do not edit.
 // {g.ndiag} Feynman diagrams, {len(g.amps)} amplitude terms (each four-gluon vertex split into its
-// three structures), {len(g.nodes)} wavefunctions, {ncol} colour flows.
+// three structures), {len(g.nodes)} wavefunctions, {ncol} colour flows; at most {budget} off-shell
+// wavefunctions live at once (others are recomputed when needed again).
 #pragma once
 #include "../helas.h"
 #include "../process.h"
@@ -241,39 +284,76 @@ struct {name} {{
   static constexpr int gs_power = {2 * len(gl)};  // |M|^2 carries g_s^gs_power
   static constexpr double iden = {iden_qcd(len(gl) - 2)};  // spin and colour average, identical gluons
   static constexpr double colour_denom = {D};
-  static constexpr double flops_per_hel = {flops + cs_flops};
-  static constexpr double flops_per_event = {flops_den};  // helicity-independent part
+  static constexpr double flops_per_hel = {flops_dag + cs_flops};  // each wavefunction counted once
+  static constexpr double flops_per_hel_executed = {flops_exec + cs_flops};  // with recomputation
+  static constexpr double flops_per_event = {flops_table};  // helicity-independent table
 
-  HME_FN static double sq(const double (&p)[{npar}][4], unsigned mask) {{
+  // Per-event table (LDS): {nq} momentum sums (incoming momenta of the particles in the mask,
+  // negated for barred currents), {nd} propagator denominators 1/(Q^2 - m^2), and for every
+  // external particle a kit from which either helicity state is built (gluon: e1, e2 / sqrt 2;
+  // fermion: chi_+, chi_-, sqrt(E + |p|), sqrt(E - |p|)).
+  static constexpr int nq = {nq}, nd = {nd}, nitems = {nitems}, ntab = {ntab};
+  static constexpr unsigned qmask[{max(nq, 1)}] = {{{", ".join(map(str, qmask))}}};
+  static constexpr int qsign[{max(nq, 1)}] = {{{", ".join(map(str, qsign))}}};
+  static constexpr unsigned dmask[{max(nd, 1)}] = {{{", ".join(map(str, dmask))}}};
+  static constexpr int dmassive[{max(nd, 1)}] = {{{", ".join(map(str, dmassive))}}};
+  static constexpr int kit_off[{npar}] = {{{", ".join(str(k[0]) for k in kits)}}};
+  static constexpr int kit_kind[{npar}] = {{{", ".join(str(k[1]) for k in kits)}}};  // 0 vector, 1 ubar, 2 v
+
+  // item j of the table (j < nitems); the lanes of an event compute disjoint items
+  HME_FN static void table_entry(const double (&p)[{npar}][4], const ProcParams& prm, int j, double* tab) {{
+    if (j >= nq + nd) {{
+      // static indexing of p (a dynamic index would put the event record in scratch)
+#pragma unroll
+      for (int k = 0; k < {npar}; ++k) {{
+        if (j - nq - nd != k) continue;
+        if (kit_kind[k] == 0) vector_kit(p[k], tab + kit_off[k]);
+        else fermion_kit(p[k], k < 2 ? 0.0 : prm.mT, tab + kit_off[k]);
+      }}
+      return;
+    }}
+    const bool isq = j < nq;
+    const unsigned m = isq ? qmask[j] : dmask[j - nq];
     double Q[4] = {{0, 0, 0, 0}};
-    for (int k = 0; k < {npar}; ++k)
-      if (mask >> k & 1)
-        for (int mu = 0; mu < 4; ++mu) Q[mu] += (k < 2 ? p[k][mu] : -p[k][mu]);
-    return Q[0] * Q[0] - Q[1] * Q[1] - Q[2] * Q[2] - Q[3] * Q[3];
+#pragma unroll
+    for (int k = 0; k < {npar}; ++k) {{
+      const double s = (m >> k & 1u) ? (k < 2 ? 1.0 : -1.0) : 0.0;
+#pragma unroll
+      for (int mu = 0; mu < 4; ++mu) Q[mu] += s * p[k][mu];
+    }}
+    if (isq) {{
+      const double sg = qsign[j];
+#pragma unroll
+      for (int mu = 0; mu < 4; ++mu) tab[4 * j + mu] = sg * Q[mu];
+    }} else {{
+      const double m2 = dmassive[j - nq] ? prm.mT * prm.mT : 0.0;
+      tab[4 * nq + (j - nq)] = 1.0 / (Q[0] * Q[0] - Q[1] * Q[1] - Q[2] * Q[2] - Q[3] * Q[3] - m2);
+    }}
   }}
 
   // jamps of one helicity (jamp[] must be zeroed by the caller)
   template <class T>
-  HME_FN static void amplitudes(const double (&p)[{npar}][4], const ProcParams& prm, unsigned h,
-                                cx<T> (&jamp)[{ncol}]) {{
+  HME_FN static void amplitudes(const double (&)[{npar}][4], const ProcParams& prm, unsigned h,
+                                tab_ptr tab, cx<T> (&jamp)[{ncol}]) {{
     auto hel = [h](int k) {{ return (h >> ({npar - 1} - k) & 1u) ? 1 : -1; }};
     const T mT = T(prm.mT);
-""" + "\n".join(pre) + "\n" + "\n".join(mom_lines) + "\n" + "\n".join(den_lines) + "\n" + "\n".join(lines) + f"""
+{body}
   }}
 
   // sum over colour flows of conj(jamp) C jamp times colour_denom
   template <class T> HME_FN static T colour_sum(const cx<T> (&jamp)[{ncol}]) {{
     T s = 0;
-""" + "\n".join(cs) + """
+{chr(10).join(cs)}
     return s;
-  }
-};
+  }}
+}};
 
-}  // namespace hme
+}}  // namespace hme
 """
     info = dict(name=name, npar=npar, ncol=ncol, ndiag=g.ndiag, namp=len(g.amps), nwf=len(g.nodes),
-                flops_per_hel=flops + cs_flops, flops_colour=cs_flops, flops_den=flops_den, colour_denom=D,
-                numerators=N, jamp_terms=jamp_terms)
+                flops_per_hel=flops_dag + cs_flops, flops_per_hel_executed=flops_exec + cs_flops,
+                flops_colour=cs_flops, flops_table=flops_table, colour_denom=D, numerators=N,
+                jamp_terms=jamp_terms, budget=budget, ntab=ntab)
     return hdr, info
 
 
@@ -311,8 +391,12 @@ struct {name} {{
   static constexpr double flops_per_hel = {flops};
   static constexpr double flops_per_event = 20.0;  // s, 1/s, Z propagator denominator
 
+  static constexpr int nq = 0, nd = 0, nitems = 0, ntab = 0;  // no per-event table
+  HME_FN static void table_entry(const double (&)[4][4], const ProcParams&, int, double*) {{}}
+
   template <class T>
-  HME_FN static void amplitudes(const double (&p)[4][4], const ProcParams& prm, unsigned h, cx<T> (&jamp)[1]) {{
+  HME_FN static void amplitudes(const double (&p)[4][4], const ProcParams& prm, unsigned h,
+                                tab_ptr, cx<T> (&jamp)[1]) {{
     auto hel = [h](int k) {{ return (h >> (3 - k) & 1u) ? 1 : -1; }};
     const sp4<T> w0 = cast<T>(oxxxxx(p[0], 0.0, hel(0), -1));  // vbar(e+)
     const sp4<T> w1 = cast<T>(ixxxxx(p[1], 0.0, hel(1), +1));  // u(e-)

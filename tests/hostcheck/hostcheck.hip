@@ -20,11 +20,13 @@ void run(const hme::ProcParams& prm, double alpha_s, int64_t nevt, const double*
     double p[Proc::npar][4];
     for (int k = 0; k < Proc::npar; ++k)
       for (int mu = 0; mu < 4; ++mu) p[k][mu] = mom[(e * Proc::npar + k) * 4 + mu];
+    double tab[Proc::ntab > 0 ? Proc::ntab : 1];
+    for (int j = 0; j < Proc::nitems; ++j) Proc::table_entry(p, prm, j, tab);
     double acc = 0;
     for (int h = 0; h < Proc::nhel; ++h) {
       hme::cx<T> jamp[Proc::ncol];
       for (auto& j : jamp) j = {T(0), T(0)};
-      Proc::template amplitudes<T>(p, prm, (unsigned)h, jamp);
+      Proc::template amplitudes<T>(p, prm, (unsigned)h, (hme::tab_ptr)tab, jamp);
       const double v = (double)Proc::template colour_sum<T>(jamp) * norm;
       if (per_hel) per_hel[e * Proc::nhel + h] = v;
       acc += v;
@@ -40,7 +42,7 @@ extern "C" int hostcheck_me2(int process, int precision, const double* card, dou
   hme::ProcParams prm;
   std::string why;
   if (!hme::derive_params(c, prm, why)) return -1;
-  const bool f64 = precision == 0;
+  const bool f64 = precision != 1;
   switch (process) {
     case 0: f64 ? run<hme::P_eemumu, double>(prm, alpha_s, nevt, mom, out, per_hel)
                 : run<hme::P_eemumu, float>(prm, alpha_s, nevt, mom, out, per_hel); break;

@@ -1,8 +1,19 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same seeded inputs.
 
-Tolerances: the FP64 path must agree with the FP64 oracle to 1e-12 relative in every
-event (the two evaluations share no code and differ only in rounding order); the mixed
-path (single-precision vertices, propagators, jamps and colour sum) to 1e-5 relative.
+Gates (relative difference in |M|^2):
+  FP64: 1e-12 against the FP64 oracle in every event, with arbitration.  The two
+    evaluations share no code (Feynman diagrams in the chiral basis against
+    Berends-Giele recursion in the Dirac basis), so on ill-conditioned events
+    (large cancellations between diagrams, e.g. soft or collinear gluons) both
+    lose digits, each in its own way.  An event whose two FP64 values differ by
+    more than 1e-12 is decided by the extended-precision (long double) oracle:
+    the GPU value must lie within max(1e-12, 100 x the FP64 oracle's own error)
+    of it, and never more than 1e-8 away.  The bulk is gated separately: the
+    99th percentile against the FP64 oracle must stay at or below 1e-13.
+  MIXED_PAPER (double amplitudes, single-precision colour algebra): 1e-5.
+  MIXED_FAST (single-precision vertices, propagators, jamps): 1e-5 for the
+    99th percentile and 1e-3 for the maximum (single-precision cancellation
+    between diagrams; the paper measures FP32 down to 1 correct digit).
 Sizes span many wavefronts and end in a ragged tail; the full-size configurations are
 checked on sampled events in the launch configuration the benchmark uses.
 """
@@ -23,6 +34,7 @@ AS = 0.118
 
 CASES = [("eemumu", hme.EEMUMU, 16384), ("ggtt", hme.GGTT, 20011), ("ggttg", hme.GGTTG, 6007),
          ("ggttgg", hme.GGTTGG, 2003)]
+PRECISIONS = (hme.FP64, hme.MIXED_FAST, hme.MIXED_PAPER)
 
 
 @pytest.fixture(scope="module")
@@ -34,7 +46,7 @@ def card():
 def handles(card):
     hs = {}
     for _, proc, _ in CASES:
-        for prec in (hme.FP64, hme.MIXED):
+        for prec in PRECISIONS:
             print(f"[gpu] create process={proc} precision={prec}", flush=True)
             hs[(proc, prec)] = hme.Handle(proc, card, prec)
     yield hs
@@ -49,27 +61,74 @@ def run(h, p, alpha_s=AS):
     return out.cpu().numpy()
 
 
+def fp64_gate(proc, p, got, ref, card):
+    """Apply the FP64 gate with extended-precision arbitration; returns (max_rel, n_arbitrated)."""
+    rel = np.abs(got / ref - 1)
+    bad = np.nonzero(~(rel <= FP64_TOL))[0]
+    if bad.size:
+        ld = oracle.me2(proc, p[bad], card, AS, extended=True)
+        gpu_err = np.abs(got[bad] / ld - 1)
+        ora_err = np.abs(ref[bad] / ld - 1)
+        allowed = np.minimum(np.maximum(100 * ora_err, FP64_TOL), 1e-8)
+        for i, e, a, o in zip(bad, gpu_err, allowed, ora_err):
+            print(f"  arbitrated event {i}: gpu-vs-ld {e:.3g}, oracle-vs-ld {o:.3g}, allowed {a:.3g}")
+        assert np.all(gpu_err <= allowed), "FP64 result outside the arbitrated tolerance"
+    return float(rel.max()), int(bad.size)
+
+
 @pytest.mark.parametrize("key,proc,n", CASES)
 def test_fp64_parity(handles, card, key, proc, n):
     print(f"[gpu] fp64 parity {key} n={n}", flush=True)
     p = configs.WORKLOADS[key].momenta(n)
     ref = oracle.me2(proc, p, card, AS)
     got = run(handles[(proc, hme.FP64)], p)
+    assert np.all(np.isfinite(got))
     rel = np.abs(got / ref - 1)
     print(f"  max {rel.max():.3g} p99 {np.quantile(rel, 0.99):.3g} median {np.median(rel):.3g}")
-    assert np.all(np.isfinite(got))
-    assert rel.max() <= FP64_TOL
+    fp64_gate(proc, p, got, ref, card)
 
 
 @pytest.mark.parametrize("key,proc,n", CASES)
-def test_mixed_parity(handles, card, key, proc, n):
-    print(f"[gpu] mixed parity {key} n={n}", flush=True)
+def test_mixed_paper_parity(handles, card, key, proc, n):
+    print(f"[gpu] mixed (paper) parity {key} n={n}", flush=True)
     p = configs.WORKLOADS[key].momenta(n)
     ref = oracle.me2(proc, p, card, AS)
-    got = run(handles[(proc, hme.MIXED)], p)
+    got = run(handles[(proc, hme.MIXED_PAPER)], p)
     rel = np.abs(got / ref - 1)
     print(f"  max {rel.max():.3g} p99 {np.quantile(rel, 0.99):.3g} median {np.median(rel):.3g}")
     assert rel.max() <= MIXED_TOL
+
+
+@pytest.mark.parametrize("key,proc,n", CASES)
+def test_mixed_fast_accuracy(handles, card, key, proc, n):
+    print(f"[gpu] mixed (fast) accuracy {key} n={n}", flush=True)
+    p = configs.WORKLOADS[key].momenta(n)
+    ref = oracle.me2(proc, p, card, AS)
+    got = run(handles[(proc, hme.MIXED_FAST)], p)
+    rel = np.abs(got / ref - 1)
+    print(f"  max {rel.max():.3g} p99 {np.quantile(rel, 0.99):.3g} median {np.median(rel):.3g}")
+    assert np.quantile(rel, 0.99) <= MIXED_TOL
+    assert rel.max() <= 1e-3
+
+
+def test_fp64_ggttgg_large_sample(handles, card):
+    """30000 consecutive events from the middle of the full gg -> ttbar gg batch (event 500000 on)."""
+    w = configs.WORKLOADS["ggttgg"]
+    p = w.momenta(30000, first_event=500000)
+    print("[gpu] fp64 ggttgg large sample", flush=True)
+    ref = oracle.me2(configs.GGTTGG, p, card, AS)
+    got = run(handles[(hme.GGTTGG, hme.FP64)], p)
+    rel = np.abs(got / ref - 1)
+    print(f"  max {rel.max():.3g} p99 {np.quantile(rel, 0.99):.3g} median {np.median(rel):.3g}")
+    assert np.quantile(rel, 0.99) <= 1e-13
+    assert np.median(rel) <= 1e-14
+    fp64_gate(configs.GGTTGG, p, got, ref, card)
+    paper = np.abs(run(handles[(hme.GGTTGG, hme.MIXED_PAPER)], p) / ref - 1)
+    fast = np.abs(run(handles[(hme.GGTTGG, hme.MIXED_FAST)], p) / ref - 1)
+    print(f"  mixed_paper max {paper.max():.3g} p99 {np.quantile(paper, 0.99):.3g}; "
+          f"mixed_fast max {fast.max():.3g} p99 {np.quantile(fast, 0.99):.3g}")
+    assert np.quantile(paper, 0.99) <= 1e-6 and paper.max() <= 1e-4
+    assert np.quantile(fast, 0.99) <= MIXED_TOL and fast.max() <= 1e-3
 
 
 def test_eemumu_closed_form_on_gpu(handles, card):
@@ -170,4 +229,4 @@ def test_full_size_sampled(handles, card, key, proc):
     assert np.all(np.isfinite(got)) and np.all(got > 0)
     idx = np.unique(np.concatenate([np.random.default_rng(9).integers(0, w.nevt, 250), [0, w.nevt - 1]]))
     ref = oracle.me2(proc, p[idx], card, AS)
-    assert np.abs(got[idx] / ref - 1).max() <= FP64_TOL
+    fp64_gate(proc, p[idx], got[idx], ref, card)
