@@ -64,6 +64,64 @@ def cpu_baseline(proc, p, gpu_out, card, target_s=12.0):
                 max_rel_diff_vs_gpu=float(rel.max()))
 
 
+def served_leg(card, precision, nwarm=200, ntimed=3000, budget=256 << 20, nstreams=4):
+    """Poisson request stream (200 requests/s, sizes log-uniform in 256..65536) through the server.
+
+    Latency is measured inside the library from hme_submit to the end of the request's batch
+    on the device.  Momenta come from per-process pools resident in HBM.
+    """
+    import threading
+
+    import torch
+
+    import paper_2507_21039_amd as hme
+    from workloads import configs
+    procs_avail = [configs.GGTT, configs.GGTTG, configs.GGTTGG]
+    arrival, procs, nevt, _ = configs.served_requests(nwarm + ntimed, processes=procs_avail)
+    w = configs.WORKLOADS["served"]
+    pools = {}
+    for p in procs_avail:
+        wl = configs.Workload("pool", p, 65536, w.sqrt_s, w.seed)
+        pools[p] = torch.from_numpy(wl.momenta()).cuda()
+    out = torch.empty(int(nevt.sum()), dtype=torch.float64, device="cuda")
+    offs = np.concatenate([[0], np.cumsum(nevt)[:-1]])
+    ids = [None] * len(nevt)
+    lat = np.zeros(len(nevt))
+    srv = hme.Server(card, precision, hbm_budget_bytes=budget, nstreams=nstreams)
+    try:
+        t0 = time.perf_counter()
+
+        def submitter():
+            for k in range(len(nevt)):
+                delay = t0 + arrival[k] - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                ids[k] = srv.submit_ptr(int(procs[k]), 0.118, int(nevt[k]), pools[int(procs[k])].data_ptr(),
+                                        out.data_ptr() + 8 * int(offs[k]))
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        for k in range(len(nevt)):
+            while ids[k] is None:
+                time.sleep(0.0002)
+            lat[k] = srv.wait(ids[k])
+        th.join()
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+    finally:
+        srv.close()
+    timed = lat[nwarm:]
+    span = arrival[-1] - arrival[nwarm]
+    return {"p50_ms": float(np.median(timed) * 1e3), "p99_ms": float(np.quantile(timed, 0.99) * 1e3),
+            "mean_ms": float(timed.mean() * 1e3), "max_ms": float(timed.max() * 1e3),
+            "requests": int(ntimed), "warmup_requests": int(nwarm),
+            "offered_events_per_s": float(nevt[nwarm:].sum() / span), "offered_requests_per_s": float(ntimed / span),
+            "wall_s": wall, "batches": int(st["batches"]), "graphs": int(st["graphs"]),
+            "precision": hme.PRECISION_NAMES[precision], "hbm_budget_bytes": budget, "streams": nstreams,
+            "processes": "gg->ttbar, gg->ttbar g, gg->ttbar gg (uniform)",
+            "note": "gg->ttbar ggg is not in this build; its share of the mix is spread over the other three"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +129,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--nevt", type=int, default=None, help="override the batch size (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); events are independent and "
@@ -136,6 +195,10 @@ def main():
                              ("mixed_paper", "f64 amplitudes and jamps, f32 colour algebra, f64 sums"))},
         "served": None,
     }
+    if not args.no_served:
+        log("[bench] served mix (Poisson, 200 requests/s)")
+        line["served"] = served_leg(card, hme.MIXED_FAST)
+        log(f"[bench] served p50 {line['served']['p50_ms']:.3f} ms p99 {line['served']['p99_ms']:.3f} ms")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(configs.GGTTGG, p, f64["out"], card)

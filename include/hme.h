@@ -101,6 +101,56 @@ int hme_destroy(hme_handle* h);
 /* Message describing the calling thread's most recent failure ("" if none). */
 const char* hme_last_error(void);
 
+/* ------------------------------------------------------------------ serving
+ * A persistent request loop over every process of the library on one device
+ * (the paper's multi-event interface and gridpack workers, section "Event
+ * generation interface" and "Gridpacks", feed many batches of varying size; the
+ * server keeps the tables resident and batches requests as they arrive).
+ *
+ * The server owns `nstreams` slots; slot k owns hbm_budget_bytes / nstreams of
+ * device memory (gathered momenta and |M|^2 of one batch) and its own stream.  A
+ * scheduler thread takes the oldest pending request and, while they fit in a
+ * free slot, later pending requests of the same process (continuous batching),
+ * then launches the batch as one captured hipGraph per (process, slot, size
+ * bucket): descriptor upload, gather kernel, |M|^2 kernel, scatter kernel (which
+ * also applies each request's alpha_s normalisation).  Batches on different
+ * slots overlap on the device.  Per-event arithmetic does not depend on the
+ * batch, so a request's |M|^2 are bitwise those of hme_compute on it alone.
+ * The server is thread-safe. */
+
+typedef struct hme_server hme_server;
+
+typedef struct {
+  uint64_t submitted, completed, batches, events, graphs;
+  int64_t slot_capacity_bytes; /* device bytes per slot */
+} hme_server_stats;
+
+/* Create a server for all processes at one precision.  hbm_budget_bytes is the
+ * total device working memory (split over nstreams slots, 1 <= nstreams <= 8). */
+int hme_server_create(const hme_sm_card* card, int precision, int device, size_t hbm_budget_bytes, int nstreams,
+                      hme_server** out);
+
+/* Queue |M|^2 of nevt events of `process`.  momenta_dev / me2_dev are caller-owned
+ * device pointers that must stay valid until hme_wait returns for *req_id.
+ * Returns HME_E_BUDGET if the request cannot fit in one slot; nothing is copied
+ * at submit time. */
+int hme_submit(hme_server* s, int process, double alpha_s, int64_t nevt, const double* momenta_dev, double* me2_dev,
+               uint64_t* req_id);
+
+/* Wait for a request: HME_OK once its |M|^2 are in me2_dev (the request is then
+ * forgotten), HME_E_TIMEOUT if timeout_s (< 0: forever) passes first, HME_E_ARG
+ * for an unknown id, HME_E_HIP if its batch failed. */
+int hme_wait(hme_server* s, uint64_t req_id, double timeout_s);
+
+/* As hme_wait; on HME_OK also stores the request's latency from hme_submit to the end of
+ * its batch on the device (host steady clock, seconds) in *latency_s (if not NULL). */
+int hme_wait_timed(hme_server* s, uint64_t req_id, double timeout_s, double* latency_s);
+
+int hme_server_stats_get(const hme_server* s, hme_server_stats* out);
+
+/* Drain all queued and in-flight work, then release the server (NULL is accepted). */
+int hme_server_destroy(hme_server* s);
+
 #ifdef __cplusplus
 }
 #endif

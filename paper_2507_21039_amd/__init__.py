@@ -21,7 +21,9 @@ PROCESS_NAMES = {EEMUMU: "e+e- -> mu+mu-", GGTT: "gg -> ttbar", GGTTG: "gg -> tt
 
 HME_OK, HME_E_ARG, HME_E_HIP, HME_E_OOM, HME_E_BUDGET, HME_E_TIMEOUT, HME_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 
-EXPORTED = ("hme_create", "hme_compute", "hme_query", "hme_good_helicities", "hme_destroy", "hme_last_error")
+EXPORTED = ("hme_create", "hme_compute", "hme_query", "hme_good_helicities", "hme_destroy", "hme_last_error",
+            "hme_server_create", "hme_submit", "hme_wait", "hme_wait_timed", "hme_server_stats_get",
+            "hme_server_destroy")
 
 
 class SmCard(ctypes.Structure):
@@ -32,6 +34,14 @@ class Info(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int) for n in ("process", "precision", "npar", "nhel", "ngoodhel", "ncol", "ndiag",
                                             "namp")] + \
                [(n, ctypes.c_double) for n in ("iden", "flops_per_event", "bytes_per_event")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "completed", "batches", "events", "graphs")] + \
+               [("slot_capacity_bytes", ctypes.c_int64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -61,7 +71,17 @@ def lib():
         L.hme_good_helicities.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int]
         L.hme_destroy.argtypes = [vp]
         L.hme_last_error.restype = ctypes.c_char_p
-        for name in ("hme_create", "hme_compute", "hme_query", "hme_good_helicities", "hme_destroy"):
+        L.hme_server_create.argtypes = [ctypes.POINTER(SmCard), ctypes.c_int, ctypes.c_int, ctypes.c_size_t,
+                                        ctypes.c_int, ctypes.POINTER(vp)]
+        L.hme_submit.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_int64, vp, vp,
+                                 ctypes.POINTER(ctypes.c_uint64)]
+        L.hme_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_double]
+        L.hme_wait_timed.argtypes = [vp, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
+        L.hme_server_stats_get.argtypes = [vp, ctypes.POINTER(ServerStats)]
+        L.hme_server_destroy.argtypes = [vp]
+        for name in ("hme_create", "hme_compute", "hme_query", "hme_good_helicities", "hme_destroy",
+                     "hme_server_create", "hme_submit", "hme_wait", "hme_wait_timed", "hme_server_stats_get",
+                     "hme_server_destroy"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -127,6 +147,61 @@ class Handle:
         if self._h:
             _check(lib().hme_destroy(self._h))
             self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Server:
+    """Persistent request loop over all processes on one device (hme_server_*)."""
+
+    def __init__(self, card, precision: int = FP64, device: int = 0, hbm_budget_bytes: int = 1 << 30,
+                 nstreams: int = 4):
+        self._s = ctypes.c_void_p()
+        _check(lib().hme_server_create(ctypes.byref(card_struct(card)), precision, device, int(hbm_budget_bytes),
+                                       nstreams, ctypes.byref(self._s)))
+
+    def submit_ptr(self, process: int, alpha_s: float, nevt: int, momenta_ptr: int, me2_ptr: int) -> int:
+        rid = ctypes.c_uint64()
+        _check(lib().hme_submit(self._s, process, float(alpha_s), int(nevt), ctypes.c_void_p(momenta_ptr),
+                                ctypes.c_void_p(me2_ptr), ctypes.byref(rid)))
+        return rid.value
+
+    def submit(self, process: int, momenta, out, alpha_s: float = 0.118) -> int:
+        """momenta [nevt, npar, 4] float64 GPU tensor, out [nevt] float64 GPU tensor (kept alive by the caller)."""
+        if momenta.dim() != 3 or momenta.shape[1] != NPAR[process] or not momenta.is_contiguous():
+            raise ValueError(f"momenta must be contiguous [nevt, {NPAR[process]}, 4]")
+        if out.numel() < momenta.shape[0] or not out.is_contiguous():
+            raise ValueError("out too small or not contiguous")
+        return self.submit_ptr(process, alpha_s, momenta.shape[0], momenta.data_ptr(), out.data_ptr())
+
+    def wait(self, req_id: int, timeout_s: float = -1.0):
+        """Returns the request's submit-to-completion latency in seconds, or None on timeout."""
+        lat = ctypes.c_double()
+        rc = lib().hme_wait_timed(self._s, req_id, float(timeout_s), ctypes.byref(lat))
+        if rc == HME_E_TIMEOUT:
+            return None
+        _check(rc)
+        return lat.value
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().hme_server_stats_get(self._s, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if self._s:
+            _check(lib().hme_server_destroy(self._s))
+            self._s = ctypes.c_void_p()
 
     def __del__(self):
         try:

@@ -19,7 +19,13 @@ ARCH = "gfx950"
 # -packed-fp32-ops keeps the compiler from emitting packed FP32 VALU instructions.
 HIPFLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wall", "-Wno-unused-variable",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = ["hme.cpp", "proc_eemumu.hip", "proc_ggtt.hip", "proc_ggttg.hip", "proc_ggttgg.hip"]
+SOURCES = ["hme.cpp", "server.hip", "proc_eemumu.hip", "proc_ggtt.hip", "proc_ggttg.hip", "proc_ggttgg.hip"]
+_KERNEL_DEPS = ["me2_kernels.h", "helas.h", "process.h"]
+DEPS = {
+    "hme.cpp": _KERNEL_DEPS + ["params.h", "../../include/hme.h"],
+    "server.hip": ["../../include/hme.h"],
+    **{f"proc_{p}.hip": _KERNEL_DEPS + [f"procs/{p}.h"] for p in ("eemumu", "ggtt", "ggttg", "ggttgg")},
+}
 
 
 def hipcc() -> str:
@@ -29,8 +35,11 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src: str, verbose: bool) -> str:
+def _compile(src: str, verbose: bool, force: bool) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    deps = [os.path.join(CSRC, d) for d in [src] + DEPS[src]] + [os.path.abspath(__file__)]
+    if not force and os.path.exists(obj) and os.path.getmtime(obj) >= max(os.path.getmtime(d) for d in deps):
+        return obj
     cmd = [hipcc(), *HIPFLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -40,13 +49,14 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False, jobs: int | None = None) -> str:
+def build(verbose: bool = False, jobs: int | None = None, force: bool = True) -> str:
+    """Generate the process headers and compile; force=False reuses objects newer than their sources."""
     from .gen.__main__ import generate
     generate(os.path.join(CSRC, "procs"))
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(len(SOURCES), max(1, len(os.sched_getaffinity(0))))
     with ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, verbose, force), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -57,4 +67,4 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, force="--incremental" not in sys.argv))

@@ -60,6 +60,14 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
+}  // namespace
+
+namespace hme {
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace hme
+
+namespace {
+
 int hip_fail(hipError_t e, const char* what) {
   return fail(HME_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
@@ -214,6 +222,31 @@ int hme_create(int process, const hme_sm_card* card, int precision, int device, 
   return HME_OK;
 }
 
+}  // extern "C"
+
+namespace hme {
+
+double handle_norm(const hme_handle* h, double alpha_s) {
+  const double pi = 3.14159265358979323846;
+  const double gs2 = 4 * pi * alpha_s;
+  double norm = 1.0 / (h->info.iden * h->info.colour_denom);
+  for (int k = 0; k < h->info.gs_power / 2; ++k) norm *= gs2;
+  return norm;
+}
+
+int handle_npar(const hme_handle* h) { return h->info.npar; }
+
+hipError_t launch_for_handle(const hme_handle* h, int64_t nevt_grid, const int64_t* nevt_dev, const double* mom,
+                             double* out, double norm, hipStream_t s) {
+  LaunchArgs a{mom, out, nevt_grid, h->d_goodhel, (int)h->goodhel.size(), h->prm, norm, s,
+               h->precision == HME_MIXED_PAPER ? 1 : 0, nevt_dev};
+  return kProcs[h->process].me2(a, h->precision);
+}
+
+}  // namespace hme
+
+extern "C" {
+
 int hme_compute(hme_handle* h, double alpha_s, int64_t nevt, const double* momenta, double* me2, void* hip_stream) {
   if (!h) return fail(HME_E_ARG, "hme_compute: handle is NULL");
   if (nevt < 0) return fail(HME_E_ARG, "hme_compute: nevt < 0");
@@ -224,13 +257,8 @@ int hme_compute(hme_handle* h, double alpha_s, int64_t nevt, const double* momen
   if (!(alpha_s > 0)) return fail(HME_E_ARG, "hme_compute: alpha_s must be positive");
   DeviceGuard guard(h->device);
   if (guard.err != hipSuccess) return hip_fail(guard.err, "hme_compute: hipSetDevice");
-  const double pi = 3.14159265358979323846;
-  const double gs2 = 4 * pi * alpha_s;
-  double norm = 1.0 / (h->info.iden * h->info.colour_denom);
-  for (int k = 0; k < h->info.gs_power / 2; ++k) norm *= gs2;
-  hme::LaunchArgs a{momenta, me2, nevt, h->d_goodhel, (int)h->goodhel.size(), h->prm, norm,
-                    static_cast<hipStream_t>(hip_stream), h->precision == HME_MIXED_PAPER ? 1 : 0};
-  hipError_t e = hme::kProcs[h->process].me2(a, h->precision);
+  hipError_t e = hme::launch_for_handle(h, nevt, nullptr, momenta, me2, hme::handle_norm(h, alpha_s),
+                                        static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return hip_fail(e, "hme_compute: launch");
   return HME_OK;
 }

@@ -34,12 +34,17 @@ HME_FN void load_event(const double* __restrict__ mom, int64_t ev, double (&p)[P
 template <class Proc, class T, int LPE>
 __global__ void __launch_bounds__(256)
     me2_kernel(const double* __restrict__ mom, double* __restrict__ out, int64_t nevt,
-               const int* __restrict__ goodhel, int ngood, ProcParams prm, double norm, int colour_f32) {
+               const int* __restrict__ goodhel, int ngood, ProcParams prm, double norm, int colour_f32,
+               const int64_t* __restrict__ nevt_dev) {
   constexpr int EPW = 64 / LPE;   // events per wavefront
   constexpr int EPB = 256 / LPE;  // events per block
   // per-event table of momentum sums and propagator denominators, shared by the event's lanes
   __shared__ double table[EPB * (Proc::ntab > 0 ? Proc::ntab : 1)];
   const int lane = threadIdx.x & 63;
+  // the event count comes from device memory when a captured graph launches a batch of
+  // varying size with a fixed grid; blocks past the end leave at once
+  if (nevt_dev) nevt = *nevt_dev;
+  if ((int64_t)blockIdx.x * EPB >= nevt) return;  // uniform per block
   // wave index in the block, made explicitly wave-uniform so that with LPE = 64 the
   // event record is fetched with scalar loads
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -104,6 +109,7 @@ struct LaunchArgs {
   double norm;
   hipStream_t stream;
   int colour_f32;  // colour sum in single precision (for double-precision amplitudes)
+  const int64_t* nevt_dev = nullptr;  // if set, the kernel reads the event count here (nevt sizes the grid)
 };
 
 struct ProcInfo {
@@ -130,7 +136,7 @@ template <class Proc, class T, int LPE> hipError_t launch_lpe(const LaunchArgs& 
   const int64_t blocks = (a.nevt + EPB - 1) / EPB;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   me2_kernel<Proc, T, LPE><<<dim3((unsigned)blocks), dim3(threads), 0, a.stream>>>(
-      a.mom, a.out, a.nevt, a.goodhel, a.ngood, a.prm, a.norm, a.colour_f32);
+      a.mom, a.out, a.nevt, a.goodhel, a.ngood, a.prm, a.norm, a.colour_f32, a.nevt_dev);
   return hipGetLastError();
 }
 

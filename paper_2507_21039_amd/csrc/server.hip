@@ -1,0 +1,434 @@
+// Serving: a persistent request loop with continuous batching, fixed per-slot HBM
+// regions (the memory budget), and one captured hipGraph per (process, slot, size
+// bucket).  See include/hme.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/hme.h"
+
+namespace hme {
+double handle_norm(const hme_handle* h, double alpha_s);
+int handle_npar(const hme_handle* h);
+hipError_t launch_for_handle(const hme_handle* h, int64_t nevt_grid, const int64_t* nevt_dev, const double* mom,
+                             double* out, double norm, hipStream_t s);
+void set_last_error(const std::string& msg);
+}  // namespace hme
+
+namespace {
+
+constexpr int kNumProcesses = 4;
+constexpr int kMaxBatchReq = 64;      // requests per batch
+constexpr int64_t kMinBucket = 256;   // smallest graph size bucket (events)
+
+struct ReqDesc {
+  const double* mom;  // caller's momenta [nevt][npar][4]
+  double* out;        // caller's |M|^2 [nevt]
+  int64_t nevt;
+  int64_t offset;  // first event of this request inside the slot
+  double norm;     // g_s^(2n) / (IDEN * colour denominator) for this request's alpha_s
+};
+
+// One batch as the device sees it; lives in pinned host memory and is copied to the
+// slot's device copy by the first node of the graph.
+struct BatchDesc {
+  int64_t nevt_total;
+  int64_t nreq;
+  ReqDesc req[kMaxBatchReq];
+};
+
+// Copy each request's momenta into the slot, contiguously.  grid.y = request index.
+__global__ void gather_kernel(const BatchDesc* __restrict__ b, double* __restrict__ slot_mom, int npar) {
+  const int r = blockIdx.y;
+  if (r >= b->nreq) return;
+  const ReqDesc d = b->req[r];
+  const int64_t n = d.nevt * npar * 4;
+  double* dst = slot_mom + d.offset * npar * 4;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = d.mom[i];
+}
+
+// Scale each request's raw |M|^2 by its normalisation and write them back to the caller.
+__global__ void scatter_kernel(const BatchDesc* __restrict__ b, const double* __restrict__ slot_out) {
+  const int r = blockIdx.y;
+  if (r >= b->nreq) return;
+  const ReqDesc d = b->req[r];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < d.nevt; i += (int64_t)gridDim.x * blockDim.x)
+    d.out[i] = slot_out[d.offset + i] * d.norm;
+}
+
+struct Request {
+  uint64_t id;
+  int process;
+  double alpha_s;
+  int64_t nevt;
+  const double* mom;
+  double* out;
+  bool done = false;
+  int status = HME_OK;
+  std::chrono::steady_clock::time_point t_submit, t_done;
+};
+
+struct Server;
+
+struct Batch {
+  Server* srv;
+  int slot;
+  std::vector<std::shared_ptr<Request>> reqs;
+};
+
+struct Slot {
+  hipStream_t stream = nullptr;
+  char* d_mem = nullptr;        // slot_bytes: gathered momenta of a batch, then its raw |M|^2
+  BatchDesc* d_desc = nullptr;  // device copy of the descriptor
+  BatchDesc* h_desc = nullptr; // pinned host descriptor
+  bool busy = false;
+  std::map<std::pair<int, int64_t>, hipGraphExec_t> graphs;  // (process, bucket) -> graph
+  std::vector<hipGraph_t> graph_defs;
+};
+
+}  // namespace
+
+struct hme_server {};
+
+namespace {
+
+struct Server : hme_server {
+  int device = 0, precision = 0;
+  int64_t slot_bytes = 0;
+  hme_handle* handles[kNumProcesses] = {};
+  std::vector<Slot> slots;
+  std::mutex mu;
+  std::condition_variable cv_sched;  // pending work or a freed slot
+  std::condition_variable cv_done;   // a request completed
+  std::deque<std::shared_ptr<Request>> pending;
+  std::unordered_map<uint64_t, std::shared_ptr<Request>> requests;
+  uint64_t next_id = 1;
+  int inflight = 0;
+  bool stop = false;
+  std::thread scheduler;
+  hme_server_stats stats{};
+
+  // events of `process` one slot holds: momenta (npar * 32 bytes) and |M|^2 (8 bytes) per event
+  int64_t capacity(int process) const {
+    const int npar = hme::handle_npar(handles[process]);
+    return (slot_bytes - 256) / (npar * 32 + 8);
+  }
+
+  static int64_t bucket_for(int64_t n, int64_t cap) {
+    int64_t b = kMinBucket;
+    while (b < n) b *= 2;
+    return std::min(b, cap);
+  }
+
+  // Capture gather -> |M|^2 -> scatter for one (process, bucket) on a slot.
+  hipError_t graph_for(Slot& sl, int process, int64_t bucket, hipGraphExec_t* out) {
+    auto key = std::make_pair(process, bucket);
+    auto it = sl.graphs.find(key);
+    if (it != sl.graphs.end()) {
+      *out = it->second;
+      return hipSuccess;
+    }
+    const int npar = hme::handle_npar(handles[process]);
+    // the batch's momenta at the start of the slot, its |M|^2 right after (256-byte aligned)
+    double* d_mom = reinterpret_cast<double*>(sl.d_mem);
+    double* d_out = reinterpret_cast<double*>(sl.d_mem + ((bucket * npar * 32 + 255) & ~int64_t(255)));
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(sl.stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t e1 = hipMemcpyAsync(sl.d_desc, sl.h_desc, sizeof(BatchDesc), hipMemcpyHostToDevice, sl.stream);
+    const unsigned gx = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, bucket * npar * 4 / 1024));
+    if (e1 == hipSuccess) {
+      gather_kernel<<<dim3(gx, kMaxBatchReq), dim3(256), 0, sl.stream>>>(sl.d_desc, d_mom, npar);
+      e1 = hipGetLastError();
+    }
+    if (e1 == hipSuccess)
+      e1 = hme::launch_for_handle(handles[process], bucket, &sl.d_desc->nevt_total, d_mom, d_out, 1.0, sl.stream);
+    if (e1 == hipSuccess) {
+      const unsigned sx = (unsigned)std::min<int64_t>(256, std::max<int64_t>(1, bucket / 1024));
+      scatter_kernel<<<dim3(sx, kMaxBatchReq), dim3(256), 0, sl.stream>>>(sl.d_desc, d_out);
+      e1 = hipGetLastError();
+    }
+    e = hipStreamEndCapture(sl.stream, &g);
+    if (e1 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return e1;
+    }
+    if (e != hipSuccess) return e;
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return e;
+    }
+    sl.graphs[key] = ex;
+    sl.graph_defs.push_back(g);
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      stats.graphs++;
+    }
+    *out = ex;
+    return hipSuccess;
+  }
+
+  static void on_batch_done(void* user) {
+    // runs on a HIP runtime thread after the batch's graph finished; no HIP calls here
+    Batch* b = static_cast<Batch*>(user);
+    Server* s = b->srv;
+    const auto now = std::chrono::steady_clock::now();
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      for (auto& r : b->reqs) {
+        r->done = true;
+        r->t_done = now;
+      }
+      s->slots[b->slot].busy = false;
+      s->inflight--;
+      s->stats.completed += b->reqs.size();
+    }
+    s->cv_done.notify_all();
+    s->cv_sched.notify_all();
+    delete b;
+  }
+
+  void fail_batch(Batch* b, hipError_t e) {
+    hme::set_last_error(std::string("server batch: ") + hipGetErrorString(e));
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto& r : b->reqs) {
+      r->done = true;
+      r->status = HME_E_HIP;
+      r->t_done = std::chrono::steady_clock::now();
+    }
+    slots[b->slot].busy = false;
+    inflight--;
+    stats.completed += b->reqs.size();
+  }
+
+  void run() {
+    hipError_t e0 = hipSetDevice(device);
+    (void)e0;
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+      int free_slot = -1;
+      cv_sched.wait(lk, [&] {
+        free_slot = -1;
+        for (size_t k = 0; k < slots.size(); ++k)
+          if (!slots[k].busy) {
+            free_slot = (int)k;
+            break;
+          }
+        return (stop && pending.empty()) || (!pending.empty() && free_slot >= 0);
+      });
+      if (pending.empty()) {
+        if (stop) break;
+        continue;
+      }
+      // continuous batching: the oldest request first, then later ones of the same process
+      auto head = pending.front();
+      pending.pop_front();
+      Batch* b = new Batch{this, free_slot, {head}};
+      const int64_t cap = capacity(head->process);
+      int64_t total = head->nevt;
+      for (auto it = pending.begin(); it != pending.end() && (int)b->reqs.size() < kMaxBatchReq;) {
+        if ((*it)->process == head->process && total + (*it)->nevt <= cap) {
+          total += (*it)->nevt;
+          b->reqs.push_back(*it);
+          it = pending.erase(it);
+        } else {
+          ++it;
+        }
+      }
+      Slot& sl = slots[free_slot];
+      sl.busy = true;
+      inflight++;
+      stats.batches++;
+      stats.events += total;
+      lk.unlock();
+
+      BatchDesc* d = sl.h_desc;
+      d->nevt_total = total;
+      d->nreq = (int64_t)b->reqs.size();
+      int64_t off = 0;
+      for (size_t i = 0; i < b->reqs.size(); ++i) {
+        const auto& r = b->reqs[i];
+        d->req[i] = ReqDesc{r->mom, r->out, r->nevt, off, hme::handle_norm(handles[r->process], r->alpha_s)};
+        off += r->nevt;
+      }
+      hipGraphExec_t ex = nullptr;
+      hipError_t e = graph_for(sl, head->process, bucket_for(total, cap), &ex);
+      if (e == hipSuccess) e = hipGraphLaunch(ex, sl.stream);
+      if (e == hipSuccess) e = hipLaunchHostFunc(sl.stream, &Server::on_batch_done, b);
+      if (e != hipSuccess) {
+        fail_batch(b, e);
+        delete b;
+        cv_done.notify_all();
+      }
+      lk.lock();
+    }
+  }
+};
+
+int srv_fail(int code, const std::string& msg) {
+  hme::set_last_error(msg);
+  return code;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hme_server_create(const hme_sm_card* card, int precision, int device, size_t hbm_budget_bytes, int nstreams,
+                      hme_server** out) {
+  if (!out) return srv_fail(HME_E_ARG, "hme_server_create: out is NULL");
+  *out = nullptr;
+  if (!card) return srv_fail(HME_E_ARG, "hme_server_create: card is NULL");
+  if (nstreams < 1 || nstreams > 8) return srv_fail(HME_E_ARG, "hme_server_create: nstreams must be 1..8");
+  if (hbm_budget_bytes < (size_t)nstreams * (1u << 20))
+    return srv_fail(HME_E_BUDGET, "hme_server_create: budget below 1 MiB per stream");
+  auto* s = new Server;
+  s->device = device;
+  s->precision = precision;
+  s->slot_bytes = (int64_t)(hbm_budget_bytes / nstreams) & ~int64_t(255);
+  for (int p = 0; p < kNumProcesses; ++p) {
+    int rc = hme_create(p, card, precision, device, &s->handles[p]);
+    if (rc != HME_OK) {
+      for (int q = 0; q < p; ++q) hme_destroy(s->handles[q]);
+      delete s;
+      return rc;
+    }
+  }
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(device);
+  s->slots.resize(nstreams);
+  hipError_t e = hipSuccess;
+  for (auto& sl : s->slots) {
+    if ((e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking)) != hipSuccess) break;
+    if ((e = hipMalloc(&sl.d_mem, s->slot_bytes)) != hipSuccess) break;
+    if ((e = hipMalloc(&sl.d_desc, sizeof(BatchDesc))) != hipSuccess) break;
+    if ((e = hipHostMalloc(&sl.h_desc, sizeof(BatchDesc), hipHostMallocDefault)) != hipSuccess) break;
+    std::memset(sl.h_desc, 0, sizeof(BatchDesc));
+  }
+  (void)hipSetDevice(prev);
+  if (e != hipSuccess) {
+    s->stop = true;
+    hme_server_destroy(s);
+    return srv_fail(HME_E_OOM, std::string("hme_server_create: ") + hipGetErrorString(e));
+  }
+  s->stats.slot_capacity_bytes = s->slot_bytes;
+  s->scheduler = std::thread([s] { s->run(); });
+  *out = s;
+  return HME_OK;
+}
+
+int hme_submit(hme_server* srv, int process, double alpha_s, int64_t nevt, const double* momenta_dev, double* me2_dev,
+               uint64_t* req_id) {
+  auto* s = static_cast<Server*>(srv);
+  if (!s || !req_id) return srv_fail(HME_E_ARG, "hme_submit: NULL server or req_id");
+  if (process < 0 || process >= kNumProcesses) return srv_fail(HME_E_ARG, "hme_submit: unknown process");
+  if (nevt < 0) return srv_fail(HME_E_ARG, "hme_submit: nevt < 0");
+  if (!(alpha_s > 0)) return srv_fail(HME_E_ARG, "hme_submit: alpha_s must be positive");
+  if (nevt > 0 && (!momenta_dev || !me2_dev)) return srv_fail(HME_E_ARG, "hme_submit: NULL momenta or me2");
+  if ((reinterpret_cast<uintptr_t>(momenta_dev) | reinterpret_cast<uintptr_t>(me2_dev)) & 7u)
+    return srv_fail(HME_E_ARG, "hme_submit: pointers must be 8-byte aligned");
+  if (nevt > s->capacity(process)) return srv_fail(HME_E_BUDGET, "hme_submit: request larger than a slot");
+  auto r = std::make_shared<Request>();
+  r->t_submit = std::chrono::steady_clock::now();
+  r->process = process;
+  r->alpha_s = alpha_s;
+  r->nevt = nevt;
+  r->mom = momenta_dev;
+  r->out = me2_dev;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return srv_fail(HME_E_ARG, "hme_submit: server is shutting down");
+    r->id = s->next_id++;
+    s->requests[r->id] = r;
+    s->stats.submitted++;
+    if (nevt == 0) {
+      r->done = true;
+      r->t_done = r->t_submit;
+      s->stats.completed++;
+    } else {
+      s->pending.push_back(r);
+    }
+  }
+  s->cv_sched.notify_one();
+  *req_id = r->id;
+  return HME_OK;
+}
+
+int hme_wait(hme_server* srv, uint64_t req_id, double timeout_s) {
+  return hme_wait_timed(srv, req_id, timeout_s, nullptr);
+}
+
+int hme_wait_timed(hme_server* srv, uint64_t req_id, double timeout_s, double* latency_s) {
+  auto* s = static_cast<Server*>(srv);
+  if (!s) return srv_fail(HME_E_ARG, "hme_wait: NULL server");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->requests.find(req_id);
+  if (it == s->requests.end()) return srv_fail(HME_E_ARG, "hme_wait: unknown request id");
+  std::shared_ptr<Request> r = it->second;
+  if (timeout_s < 0) {
+    s->cv_done.wait(lk, [&] { return r->done; });
+  } else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), [&] { return r->done; })) {
+    return srv_fail(HME_E_TIMEOUT, "hme_wait: timed out");
+  }
+  s->requests.erase(req_id);
+  if (latency_s) *latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
+  return r->status;
+}
+
+int hme_server_stats_get(const hme_server* srv, hme_server_stats* out) {
+  auto* s = static_cast<const Server*>(srv);
+  if (!s || !out) return srv_fail(HME_E_ARG, "hme_server_stats_get: NULL argument");
+  std::lock_guard<std::mutex> lk(const_cast<Server*>(s)->mu);
+  *out = s->stats;
+  return HME_OK;
+}
+
+int hme_server_destroy(hme_server* srv) {
+  auto* s = static_cast<Server*>(srv);
+  if (!s) return HME_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_sched.notify_all();
+  if (s->scheduler.joinable()) s->scheduler.join();
+  {
+    // wait for the last batches' callbacks
+    std::unique_lock<std::mutex> lk(s->mu);
+    s->cv_done.wait(lk, [&] { return s->inflight == 0; });
+  }
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(s->device);
+  for (auto& sl : s->slots) {
+    if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+    for (auto& kv : sl.graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto g : sl.graph_defs) (void)hipGraphDestroy(g);
+    if (sl.d_mem) (void)hipFree(sl.d_mem);
+    if (sl.d_desc) (void)hipFree(sl.d_desc);
+    if (sl.h_desc) (void)hipHostFree(sl.h_desc);
+    if (sl.stream) (void)hipStreamDestroy(sl.stream);
+  }
+  (void)hipSetDevice(prev);
+  for (auto* h : s->handles)
+    if (h) hme_destroy(h);
+  delete s;
+  return HME_OK;
+}
+
+}  // extern "C"

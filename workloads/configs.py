@@ -85,8 +85,11 @@ WORKLOADS = {
 }
 
 
-def served_requests(nreq: int, seed: int = 5):
-    """Request stream for the served mix: (arrival_s, process, nevt, first_event)."""
+def served_requests(nreq: int, seed: int = 5, processes=None):
+    """Request stream for the served mix: (arrival_s, process, nevt, first_event).
+
+    processes: the process ids drawn uniformly (default: the four gg -> ttbar + n g).
+    """
     from .philox import philox4x32, uniform_pairs
     w = WORKLOADS["served"]
     idx = np.arange(nreq, dtype=np.uint32)
@@ -98,7 +101,8 @@ def served_requests(nreq: int, seed: int = 5):
     u2, _ = uniform_pairs(words2)
     gaps = -np.log(u0) / w.extra["rate_hz"]
     arrival = np.cumsum(gaps)
-    procs = np.array(w.extra["processes"])[np.minimum((u1 * 4).astype(int), 3)]
+    plist = np.array(processes if processes is not None else w.extra["processes"])
+    procs = plist[np.minimum((u1 * len(plist)).astype(int), len(plist) - 1)]
     lo, hi = np.log(w.extra["min_batch"]), np.log(w.extra["max_batch"] + 1)
     nevt = np.minimum(np.floor(np.exp(lo + u2 * (hi - lo))).astype(np.int64), w.extra["max_batch"])
     first = np.concatenate([[0], np.cumsum(nevt)[:-1]])
