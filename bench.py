@@ -23,6 +23,29 @@ PEAK_FP64_VALU = 78.6e12  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 PEAK_FP32_VALU_UNPACKED = 78.6e12  # same lanes and rate; packed FP32 is not used
 PEAK_HBM = 8.0e12
 
+# HBM traffic of one FP64 gg -> ttbar gg launch (1,048,576 events) from rocprofv3 counters
+# (profiles/me2_ggttgg_1M_traffic.md): FETCH_SIZE and WRITE_SIZE in KiB, each scaled by what the
+# counter reads for a plain 256 MiB device copy.  Valid only for the kernel sources it was taken
+# on (sha256 prefix of me2_kernels.h + helas.h + procs/ggttgg.h); otherwise traffic is null.
+TRAFFIC = {"source_sha": "bb7d57f0ca3644f3", "nevt": 1048576,
+           "fetch_kib": 198802.1875, "write_kib": 8192.0, "fetch_factor": 262144 / 131095.0625, "write_factor": 1.0}
+
+
+def kernel_source_sha() -> str:
+    import hashlib
+    root = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2507_21039_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("me2_kernels.h", "helas.h", "procs/ggttgg.h"):
+        with open(os.path.join(root, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(nevt: int):
+    if kernel_source_sha() != TRAFFIC["source_sha"] or nevt != TRAFFIC["nevt"]:
+        return None
+    return 1024 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_factor"] + TRAFFIC["write_kib"] * TRAFFIC["write_factor"])
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -130,6 +153,9 @@ def main():
     ap.add_argument("--nevt", type=int, default=None, help="override the batch size (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--pmc", action="store_true",
+                    help="counter-collection mode: one FP64 launch, then a plain 256 MiB device copy "
+                         "(known traffic, for calibrating FETCH_SIZE / WRITE_SIZE); no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); events are independent and "
@@ -148,6 +174,15 @@ def main():
     p = w.momenta(nevt)
     mom = torch.from_numpy(p).cuda()
     out = torch.empty(nevt, dtype=torch.float64, device="cuda")
+    if args.pmc:
+        with hme.Handle(hme.GGTTGG, card, hme.FP64) as h:
+            h.compute(mom, out)
+        src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")  # 256 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] pmc mode: 1 FP64 launch + 256 MiB copy done")
+        return
     results = {}
     for prec, name in ((hme.FP64, "fp64"), (hme.MIXED_FAST, "mixed_fast"), (hme.MIXED_PAPER, "mixed_paper")):
         log(f"[bench] {name}: create")
@@ -183,8 +218,9 @@ def main():
                    "process": "gg->ttbar gg", "nevt": nevt, "diagrams": 123, "helicities": 64,
                    "good_helicities": f64["ngoodhel"], "colour_flows": 24},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": None,
-                     "flops_per_event": f64["flops_per_event"]},
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": measured_traffic(nevt),
+                     "traffic_unit": "bytes per launch (HBM, counter-based)",
+                     "algorithmic_bytes": 200 * nevt, "flops_per_event": f64["flops_per_event"]},
         "mixed": {
             name: {"value": results[name]["value"], "ms_per_step": results[name]["ms_per_step"], "dtype": dt,
                    "achieved_tflops": results[name]["achieved_tflops"],

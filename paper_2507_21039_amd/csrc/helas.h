@@ -372,35 +372,58 @@ HME_FN void fermion_kit(const double* p, double m, double* kit) {
   kit[9] = wm;
 }
 
+// A kit read out of the table (N values, already in the arithmetic type).
+template <class T, int N> struct kitv {
+  T v[N];
+};
+template <class T, int N> HME_FN kitv<T, N> load_kit(tab_ptr kit) {
+  kitv<T, N> r;
+#pragma unroll
+  for (int i = 0; i < N; ++i) r.v[i] = T(kit[i]);
+  return r;
+}
+
 // eps(k, lam) (nsv = -1, incoming) or conj(eps) (nsv = +1, outgoing) from a vector kit.
-template <class T> HME_FN vw4<T> vxxxxx_kit(tab_ptr kit, int lam, int nsv) {
+template <class T> HME_FN vw4<T> vxxxxx_from(const kitv<T, 5>& k, int lam, int nsv) {
   const T a = T(-lam), b = nsv < 0 ? T(-1) : T(1);
   vw4<T> w;
   w.c[0] = {T(0), T(0)};
-  w.c[1] = {a * T(kit[0]), b * T(kit[3])};
-  w.c[2] = {a * T(kit[1]), b * T(kit[4])};
-  w.c[3] = {a * T(kit[2]), T(0)};
+  w.c[1] = {a * k.v[0], b * k.v[3]};
+  w.c[2] = {a * k.v[1], b * k.v[4]};
+  w.c[3] = {a * k.v[2], T(0)};
   return w;
 }
 
 // ubar(p, lam) of an outgoing fermion from a fermion kit (same state as oxxxxx with nsf = +1).
-template <class T> HME_FN sp4<T> oxxxxx_kit(tab_ptr kit, int lam) {
+template <class T> HME_FN sp4<T> oxxxxx_from(const kitv<T, 10>& k, int lam) {
   const bool plus = lam > 0;
-  const cx<T> c0 = {T(plus ? kit[0] : kit[4]), T(plus ? -kit[1] : -kit[5])};  // conj(chi)
-  const cx<T> c1 = {T(plus ? kit[2] : kit[6]), T(plus ? -kit[3] : -kit[7])};
-  const T wp = T(kit[8]), wm = T(kit[9]);
-  const T a = plus ? wp : wm, b = plus ? wm : wp;
+  const cx<T> c0 = {plus ? k.v[0] : k.v[4], plus ? -k.v[1] : -k.v[5]};  // conj(chi)
+  const cx<T> c1 = {plus ? k.v[2] : k.v[6], plus ? -k.v[3] : -k.v[7]};
+  const T a = plus ? k.v[8] : k.v[9], b = plus ? k.v[9] : k.v[8];
   return {{a * c0, a * c1, b * c0, b * c1}};
 }
 
 // v(p, lam) of an outgoing antifermion from a fermion kit (same state as ixxxxx with nsf = -1).
-template <class T> HME_FN sp4<T> ixxxxx_kit(tab_ptr kit, int lam) {
+template <class T> HME_FN sp4<T> ixxxxx_from(const kitv<T, 10>& k, int lam) {
   const bool plus = lam > 0;
-  const cx<T> c0 = {T(plus ? kit[4] : kit[0]), T(plus ? kit[5] : kit[1])};  // chi_{-lam}
-  const cx<T> c1 = {T(plus ? kit[6] : kit[2]), T(plus ? kit[7] : kit[3])};
-  const T wp = T(kit[8]), wm = T(kit[9]);
-  const T a = plus ? wp : wm, b = plus ? wm : wp;
+  const cx<T> c0 = {plus ? k.v[4] : k.v[0], plus ? k.v[5] : k.v[1]};  // chi_{-lam}
+  const cx<T> c1 = {plus ? k.v[6] : k.v[2], plus ? k.v[7] : k.v[3]};
+  const T a = plus ? k.v[8] : k.v[9], b = plus ? k.v[9] : k.v[8];
   return {{a * c0, a * c1, -b * c0, -b * c1}};
 }
+
+template <class T> HME_FN vw4<T> vxxxxx_kit(tab_ptr kit, int lam, int nsv) {
+  return vxxxxx_from<T>(load_kit<T, 5>(kit), lam, nsv);
+}
+template <class T> HME_FN sp4<T> oxxxxx_kit(tab_ptr kit, int lam) { return oxxxxx_from<T>(load_kit<T, 10>(kit), lam); }
+template <class T> HME_FN sp4<T> ixxxxx_kit(tab_ptr kit, int lam) { return ixxxxx_from<T>(load_kit<T, 10>(kit), lam); }
+
+// Scheduling fence for the generated code: table reads issued before it are not moved
+// past it, so their LDS latency overlaps the arithmetic that follows.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define HME_FENCE() __builtin_amdgcn_sched_barrier(0)
+#else
+#define HME_FENCE() ((void)0)
+#endif
 
 }  // namespace hme

@@ -15,6 +15,7 @@ used as the algorithmic FLOP figure of the kernel.
 from __future__ import annotations
 
 import math
+import re
 
 from . import colour as colour_mod
 from .colour import Gauss
@@ -73,14 +74,80 @@ NODE_FLOPS = {"vvv": "vvv_vec", "vvvv": "vvvv_vec", "psi": "ffv_psi", "psibar": 
 KIT_FLOPS = {"ext_v": 4, "ext_o": 12, "ext_i": 12}  # building a wavefunction from its per-event kit
 
 
-def emit_qcd(name: str, g, label: str, budget: int = 8) -> tuple[str, dict]:
+UNIT = "@@UNIT@@"
+_READ = re.compile(r"(qv<T>\(tab, \d+\)|dv<T>\(tab, [^)]*\)|(vxxxxx|oxxxxx|ixxxxx)_kit<T>\(tab \+ (\w+), )")
+
+
+def prefetch_units(lines, enable, kits: bool = True):
+    """Split the body into units (one wavefunction or one amplitude term each).
+
+    With enable, every table read of a unit (momentum sums, denominators and, with
+    kits, the external-state kits) becomes a local loaded one unit earlier, fenced so
+    the loads are issued before the previous unit's arithmetic.
+    """
+    units, cur = [], None
+    for l in lines:
+        if l == UNIT:
+            cur = []
+            units.append(cur)
+        else:
+            cur.append(l)
+    if not enable:
+        return [l for u in units for l in u]
+    decls, bodies = [], []
+    for k, u in enumerate(units):
+        d = []
+        seen = {}
+
+        def repl(m):
+            txt = m.group(0)
+            if txt in seen:
+                return seen[txt]
+            nm = f"t{k}_{len(seen)}"
+            if txt.startswith("qv"):
+                d.append(f"  const m4<T> {nm} = {txt};")
+                seen[txt] = nm
+                return nm
+            if txt.startswith("dv"):
+                d.append(f"  const T {nm} = {txt};")
+                seen[txt] = nm
+                return nm
+            kind, off = m.group(2), m.group(3)
+            if not kits:
+                return txt
+            n = 5 if kind == "vxxxxx" else 10
+            d.append(f"  const kitv<T, {n}> {nm} = load_kit<T, {n}>(tab + {off});")
+            seen[txt] = f"{kind}_from<T>({nm}, "
+            return seen[txt]
+
+        body = [_READ.sub(repl, l) for l in u]
+        decls.append(d)
+        bodies.append(body)
+    out = decls[0] + ["  HME_FENCE();"] if units else []
+    for k in range(len(units)):
+        if k + 1 < len(units):
+            out += decls[k + 1]
+        out.append("  HME_FENCE();")
+        out += bodies[k]
+    return out
+
+
+def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all")) -> tuple[str, dict]:
     """Emit the process header.
 
-    budget: number of off-shell wavefunctions kept live at once.  When the
-    schedule needs more, the wavefunction whose next use is farthest away is
-    dropped and recomputed when needed again (Belady's rule).  External
-    wavefunctions are rebuilt at every use from a per-event kit in the LDS table.
+    budget: number of off-shell wavefunctions kept live at once, for the double and the
+    single precision schedule.  When a schedule needs more, the wavefunction whose next
+    use is farthest away is dropped and recomputed when needed again (Belady's rule).
+    External wavefunctions are rebuilt at every use from a per-event kit in the LDS table.
+    prefetch: per precision, "" (table reads at their use), "table" (momentum sums and
+    denominators read one unit ahead) or "all" (kits too).  The defaults are the fastest
+    measured on MI355X for g g -> t tbar g g: budget 4 without prefetch keeps the FP64
+    kernel at 2 waves per SIMD; FP32 gains more from hiding LDS latency.
     """
+    if isinstance(budget, int):
+        budget = (budget, budget)
+    if isinstance(prefetch, str):
+        prefetch = (prefetch, prefetch)
     npar = g.npar
     gl = tuple(sorted(g.gluons))
     basis, C = colour_mod.colour_matrix(gl)
@@ -90,12 +157,8 @@ def emit_qcd(name: str, g, label: str, budget: int = 8) -> tuple[str, dict]:
     phase = _common_phase(g.amps)
 
     node_ids = {k: i for i, k in enumerate(g.nodes)}
-    lines = []
     qidx = {}  # (mask, sign) -> index of a momentum sum in the table
     didx = {}  # mask -> (index, massive)
-    kit_of = {}  # external particle -> table offset of its kit (filled below)
-    flops_exec = 0
-    flops_dag = 0
 
     def mom(mask, sign=1):
         key = (mask, sign)
@@ -108,126 +171,137 @@ def emit_qcd(name: str, g, label: str, budget: int = 8) -> tuple[str, dict]:
             didx[mask] = (len(didx), massive)
         return f"dv<T>(tab, DOFF + {didx[mask][0]})"
 
-    # ---- schedule with a bounded number of live wavefunctions
-    from .diagrams import schedule
-    import bisect
-    order = schedule(g)
-    amp_nodes = [_closure(g, g.amps[i].args) for i in order]
-    uses = {}
-    for t, s in enumerate(amp_nodes):
-        for k in s:
-            uses.setdefault(k, []).append(t)
+    def emit_schedule(budget):
+        """One amplitude schedule under a live-wavefunction budget; returns the body lines."""
+        lines = []
+        flops_exec = 0
+        flops_dag = 0
+        # ---- schedule with a bounded number of live wavefunctions
+        from .diagrams import schedule
+        import bisect
+        order = schedule(g)
+        amp_nodes = [_closure(g, g.amps[i].args) for i in order]
+        uses = {}
+        for t, s in enumerate(amp_nodes):
+            for k in s:
+                uses.setdefault(k, []).append(t)
 
-    def next_use(k, t):
-        u = uses[k]
-        i = bisect.bisect_right(u, t)
-        return u[i] if i < len(u) else 1 << 30
+        def next_use(k, t):
+            u = uses[k]
+            i = bisect.bisect_right(u, t)
+            return u[i] if i < len(u) else 1 << 30
 
-    live = {}  # node key -> variable name of its current value
-    version = {}
-    now = [0]
-    computed_once = set()
+        live = {}  # node key -> variable name of its current value
+        version = {}
+        now = [0]
+        computed_once = set()
 
-    def ext_expr(key, out_lines):
-        """Build an external wavefunction from its kit into a fresh local, return the name."""
-        nonlocal flops_exec
-        k = key[1]
-        kind = g.nodes[key].kind
-        nm = f"e{k}_{len(out_lines)}"
-        if kind == "ext_v":
-            nsv = -1 if k < 2 else 1
-            out_lines.append(f"    const vw4<T> {nm} = vxxxxx_kit<T>(tab + KOFF{k}, hel({k}), {nsv});")
-        elif kind == "ext_o":
-            out_lines.append(f"    const sp4<T> {nm} = oxxxxx_kit<T>(tab + KOFF{k}, hel({k}));")
-        else:
-            out_lines.append(f"    const sp4<T> {nm} = ixxxxx_kit<T>(tab + KOFF{k}, hel({k}));")
-        flops_exec += KIT_FLOPS[kind]
-        return nm
+        def ext_expr(key, out_lines):
+            """Build an external wavefunction from its kit into a fresh local, return the name."""
+            nonlocal flops_exec
+            k = key[1]
+            kind = g.nodes[key].kind
+            nm = f"e{k}_{len(out_lines)}"
+            if kind == "ext_v":
+                nsv = -1 if k < 2 else 1
+                out_lines.append(f"    const vw4<T> {nm} = vxxxxx_kit<T>(tab + KOFF{k}, hel({k}), {nsv});")
+            elif kind == "ext_o":
+                out_lines.append(f"    const sp4<T> {nm} = oxxxxx_kit<T>(tab + KOFF{k}, hel({k}));")
+            else:
+                out_lines.append(f"    const sp4<T> {nm} = ixxxxx_kit<T>(tab + KOFF{k}, hel({k}));")
+            flops_exec += KIT_FLOPS[kind]
+            return nm
 
-    def arg(key, pre):
-        if key[0] == "E":
-            return ext_expr(key, pre)
-        return live[key]
+        def arg(key, pre):
+            if key[0] == "E":
+                return ext_expr(key, pre)
+            return live[key]
 
-    def need(key, pinned):
-        nonlocal flops_exec, flops_dag
-        if key[0] == "E" or key in live:
-            return
-        n = g.nodes[key]
-        for a in n.args:
-            need(a, pinned | {key})
-        pre = []
-        args = [arg(a, pre) for a in n.args]
-        version[key] = version.get(key, -1) + 1
-        v = f"w{node_ids[key]}" + (f"_{version[key]}" if version[key] else "")
-        if n.kind == "vvv":
-            ma, mb = g.nodes[n.args[0]].mask, g.nodes[n.args[1]].mask
-            call = f"vw4<T> {v} = vvv_vec<T>({args[0]}, {mom(ma)}, {args[1]}, {mom(mb)}, {den(n.mask, False)});"
-        elif n.kind == "vvvv":
-            call = f"vw4<T> {v} = vvvv_vec<{n.extra[0]}, T>({args[0]}, {args[1]}, {args[2]}, {den(n.mask, False)});"
-        elif n.kind == "psi":
-            call = f"sp4<T> {v} = ffv_psi<T>({args[0]}, {args[1]}, {mom(n.mask)}, mT, {den(n.mask, True)});"
-        elif n.kind == "psibar":
-            call = f"sp4<T> {v} = ffv_psibar<T>({args[0]}, {args[1]}, {mom(n.mask, -1)}, mT, {den(n.mask, True)});"
-        elif n.kind == "qq":
-            call = f"vw4<T> {v} = ffv_vec<T>({args[0]}, {args[1]}, {den(n.mask, False)});"
-        else:
-            raise ValueError(n.kind)
-        typ = call.split(" ", 1)[0]
-        name_rest = call.split(" ", 1)[1]
-        lines.append(f"  {typ} {v};")
-        lines.append("  {")
-        lines.extend(pre)
-        lines.append(f"    {name_rest.replace(v + ' =', v + ' =', 1)}")
-        lines.append("  }")
-        f = FLOPS[NODE_FLOPS[n.kind]]
-        flops_exec += f
-        if key not in computed_once:
+        def need(key, pinned):
+            nonlocal flops_exec, flops_dag
+            if key[0] == "E" or key in live:
+                return
+            n = g.nodes[key]
+            for a in n.args:
+                need(a, pinned | {key})
+            pre = []
+            args = [arg(a, pre) for a in n.args]
+            version[key] = version.get(key, -1) + 1
+            v = f"w{node_ids[key]}" + (f"_{version[key]}" if version[key] else "")
+            if n.kind == "vvv":
+                ma, mb = g.nodes[n.args[0]].mask, g.nodes[n.args[1]].mask
+                call = f"vw4<T> {v} = vvv_vec<T>({args[0]}, {mom(ma)}, {args[1]}, {mom(mb)}, {den(n.mask, False)});"
+            elif n.kind == "vvvv":
+                call = f"vw4<T> {v} = vvvv_vec<{n.extra[0]}, T>({args[0]}, {args[1]}, {args[2]}, {den(n.mask, False)});"
+            elif n.kind == "psi":
+                call = f"sp4<T> {v} = ffv_psi<T>({args[0]}, {args[1]}, {mom(n.mask)}, mT, {den(n.mask, True)});"
+            elif n.kind == "psibar":
+                call = f"sp4<T> {v} = ffv_psibar<T>({args[0]}, {args[1]}, {mom(n.mask, -1)}, mT, {den(n.mask, True)});"
+            elif n.kind == "qq":
+                call = f"vw4<T> {v} = ffv_vec<T>({args[0]}, {args[1]}, {den(n.mask, False)});"
+            else:
+                raise ValueError(n.kind)
+            typ = call.split(" ", 1)[0]
+            name_rest = call.split(" ", 1)[1]
+            lines.append(UNIT)
+            lines.append(f"  {typ} {v};")
+            lines.append("  {")
+            lines.extend(pre)
+            lines.append(f"    {name_rest.replace(v + ' =', v + ' =', 1)}")
+            lines.append("  }")
+            f = FLOPS[NODE_FLOPS[n.kind]]
+            flops_exec += f
+            if key not in computed_once:
+                flops_dag += f
+                computed_once.add(key)
+            live[key] = v
+            while len(live) > budget:
+                cands = [x for x in live if x not in pinned and x != key and x not in n.args]
+                if not cands:
+                    break
+                victim = max(cands, key=lambda x: next_use(x, now[0]))
+                del live[victim]
+
+        jamp_terms = 0
+        for t, ia in enumerate(order):
+            now[0] = t
+            amp = g.amps[ia]
+            for k in amp.args:
+                need(k, set(amp.args))
+            pre = []
+            args = [arg(k, pre) for k in amp.args]
+            if amp.kind == "ffv":
+                call = f"ffv_amp<T>({args[0]}, {args[1]}, {args[2]})"
+                f = FLOPS["ffv_amp"]
+            elif amp.kind == "vvv":
+                a, b, q = amp.args
+                call = (f"vvv_amp<T>({args[0]}, {mom(g.nodes[a].mask)}, {args[1]}, {mom(g.nodes[b].mask)}, "
+                        f"{args[2]}, {mom(g.nodes[q].mask)})")
+                f = FLOPS["vvv_amp"]
+            else:
+                call = f"vvvv_amp<{amp.extra[0]}, T>({args[0]}, {args[1]}, {args[2]}, {args[3]})"
+                f = FLOPS["vvvv_amp"]
+            flops_exec += f
             flops_dag += f
-            computed_once.add(key)
-        live[key] = v
-        while len(live) > budget:
-            cands = [x for x in live if x not in pinned and x != key and x not in n.args]
-            if not cands:
-                break
-            victim = max(cands, key=lambda x: next_use(x, now[0]))
-            del live[victim]
+            lines.append(UNIT)
+            lines.append(f"  {{  // diagram {amp.diagram + 1}")
+            lines.extend(pre)
+            lines.append(f"    const cx<T> a = {call};")
+            for w, c in sorted(amp.colour.terms.items(), key=lambda x: widx[x[0]]):
+                j = widx[w]
+                lines.append(f"    jamp[{j}] = jamp[{j}] {_coef_code(c * phase, 'a')};")
+                jamp_terms += 1
+            lines.append("  }")
+            for x in list(live):
+                if next_use(x, t) >= 1 << 30:
+                    del live[x]
+        flops_exec += 2 * jamp_terms
+        ext_name = {"ext_v": "vxxxxx", "ext_o": "oxxxxx", "ext_i": "ixxxxx"}
+        flops_dag += 2 * jamp_terms + sum(EXT_FLOPS[ext_name[g.nodes[k].kind]] for k in g.nodes if k[0] == "E")
+        return lines, flops_exec, flops_dag, jamp_terms
 
-    jamp_terms = 0
-    for t, ia in enumerate(order):
-        now[0] = t
-        amp = g.amps[ia]
-        for k in amp.args:
-            need(k, set(amp.args))
-        pre = []
-        args = [arg(k, pre) for k in amp.args]
-        if amp.kind == "ffv":
-            call = f"ffv_amp<T>({args[0]}, {args[1]}, {args[2]})"
-            f = FLOPS["ffv_amp"]
-        elif amp.kind == "vvv":
-            a, b, q = amp.args
-            call = (f"vvv_amp<T>({args[0]}, {mom(g.nodes[a].mask)}, {args[1]}, {mom(g.nodes[b].mask)}, "
-                    f"{args[2]}, {mom(g.nodes[q].mask)})")
-            f = FLOPS["vvv_amp"]
-        else:
-            call = f"vvvv_amp<{amp.extra[0]}, T>({args[0]}, {args[1]}, {args[2]}, {args[3]})"
-            f = FLOPS["vvvv_amp"]
-        flops_exec += f
-        flops_dag += f
-        lines.append(f"  {{  // diagram {amp.diagram + 1}")
-        lines.extend(pre)
-        lines.append(f"    const cx<T> a = {call};")
-        for w, c in sorted(amp.colour.terms.items(), key=lambda x: widx[x[0]]):
-            j = widx[w]
-            lines.append(f"    jamp[{j}] = jamp[{j}] {_coef_code(c * phase, 'a')};")
-            jamp_terms += 1
-        lines.append("  }")
-        for x in list(live):
-            if next_use(x, t) >= 1 << 30:
-                del live[x]
-    flops_exec += 2 * jamp_terms
-    ext_name = {"ext_v": "vxxxxx", "ext_o": "oxxxxx", "ext_i": "ixxxxx"}
-    flops_dag += 2 * jamp_terms + sum(EXT_FLOPS[ext_name[g.nodes[k].kind]] for k in g.nodes if k[0] == "E")
+    lines_d, flops_exec_d, flops_dag, jamp_terms = emit_schedule(budget[0])
+    lines_f, flops_exec_f, _, _ = emit_schedule(budget[1])
 
     nq, nd = len(qidx), len(didx)
     ext = [k for k in range(npar)]
@@ -237,9 +311,14 @@ def emit_qcd(name: str, g, label: str, budget: int = 8) -> tuple[str, dict]:
         koff[k] = off
         off += 5 if g.nodes[("E", k)].kind == "ext_v" else 10
     ntab = off
-    body = "\n".join(lines).replace("DOFF", str(4 * nq))
-    for k in ext:
-        body = body.replace(f"KOFF{k}", str(koff[k]))
+    def finish(lines, pf):
+        lines = [l.replace("DOFF", str(4 * nq)) for l in lines]
+        for k in ext:
+            lines = [l.replace(f"KOFF{k}", str(koff[k])) for l in lines]
+        return "\n".join(prefetch_units(lines, bool(pf), kits=(pf != "table")))
+
+    body_d = finish(lines_d, prefetch[0])
+    body_f = finish(lines_f, prefetch[1])
     qmask = [0] * nq
     qsign = [0] * nq
     for (m, sgn), i in qidx.items():
@@ -267,8 +346,8 @@ def emit_qcd(name: str, g, label: str, budget: int = 8) -> tuple[str, dict]:
     nitems = nq + nd + npar
     hdr = f"""// Generated by paper_2507_21039_amd.gen for {label}.  Do not edit.
 // {g.ndiag} Feynman diagrams, {len(g.amps)} amplitude terms (each four-gluon vertex split into its
-// three structures), {len(g.nodes)} wavefunctions, {ncol} colour flows; at most {budget} off-shell
-// wavefunctions live at once (others are recomputed when needed again).
+// three structures), {len(g.nodes)} wavefunctions, {ncol} colour flows; at most {budget[0]} (double) or
+// {budget[1]} (float) off-shell wavefunctions live at once (others are recomputed when needed again).
 #pragma once
 #include "../helas.h"
 #include "../process.h"
@@ -285,7 +364,7 @@ struct {name} {{
   static constexpr double iden = {iden_qcd(len(gl) - 2)};  // spin and colour average, identical gluons
   static constexpr double colour_denom = {D};
   static constexpr double flops_per_hel = {flops_dag + cs_flops};  // each wavefunction counted once
-  static constexpr double flops_per_hel_executed = {flops_exec + cs_flops};  // with recomputation
+  static constexpr double flops_per_hel_executed = {flops_exec_d + cs_flops};  // with recomputation (double)
   static constexpr double flops_per_event = {flops_table};  // helicity-independent table
 
   // Per-event table (LDS): {nq} momentum sums (incoming momenta of the particles in the mask,
@@ -331,13 +410,29 @@ struct {name} {{
     }}
   }}
 
-  // jamps of one helicity (jamp[] must be zeroed by the caller)
+  // jamps of one helicity (jamp[] must be zeroed by the caller); the schedule depends on the
+  // arithmetic type (budget {budget[0]} / prefetch "{prefetch[0]}" for double, {budget[1]} / "{prefetch[1]}" for float)
   template <class T>
-  HME_FN static void amplitudes(const double (&)[{npar}][4], const ProcParams& prm, unsigned h,
+  HME_FN static void amplitudes(const double (&p)[{npar}][4], const ProcParams& prm, unsigned h,
                                 tab_ptr tab, cx<T> (&jamp)[{ncol}]) {{
+    if constexpr (sizeof(T) == 8)
+      amplitudes_d<T>(prm, h, tab, jamp);
+    else
+      amplitudes_f<T>(prm, h, tab, jamp);
+  }}
+
+  template <class T>
+  HME_FN static void amplitudes_d(const ProcParams& prm, unsigned h, tab_ptr tab, cx<T> (&jamp)[{ncol}]) {{
     auto hel = [h](int k) {{ return (h >> ({npar - 1} - k) & 1u) ? 1 : -1; }};
     const T mT = T(prm.mT);
-{body}
+{body_d}
+  }}
+
+  template <class T>
+  HME_FN static void amplitudes_f(const ProcParams& prm, unsigned h, tab_ptr tab, cx<T> (&jamp)[{ncol}]) {{
+    auto hel = [h](int k) {{ return (h >> ({npar - 1} - k) & 1u) ? 1 : -1; }};
+    const T mT = T(prm.mT);
+{body_f}
   }}
 
   // sum over colour flows of conj(jamp) C jamp times colour_denom
@@ -351,9 +446,10 @@ struct {name} {{
 }}  // namespace hme
 """
     info = dict(name=name, npar=npar, ncol=ncol, ndiag=g.ndiag, namp=len(g.amps), nwf=len(g.nodes),
-                flops_per_hel=flops_dag + cs_flops, flops_per_hel_executed=flops_exec + cs_flops,
+                flops_per_hel=flops_dag + cs_flops, flops_per_hel_executed=flops_exec_d + cs_flops,
+                flops_per_hel_executed_f32=flops_exec_f + cs_flops,
                 flops_colour=cs_flops, flops_table=flops_table, colour_denom=D, numerators=N,
-                jamp_terms=jamp_terms, budget=budget, ntab=ntab)
+                jamp_terms=jamp_terms, budget=list(budget), prefetch=list(prefetch), ntab=ntab)
     return hdr, info
 
 
