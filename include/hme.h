@@ -45,7 +45,10 @@ typedef struct {
   double mZ, wZ, alpha_inv, Gf, mT, wT;
 } hme_sm_card;
 
-enum hme_process { HME_EEMUMU = 0, HME_GGTT = 1, HME_GGTTG = 2, HME_GGTTGG = 3 };
+/* HME_GGTTGGG (1240 diagrams, 120 colour flows) is evaluated in pieces over a jamp
+ * workspace (see hme_compute) and only at HME_MIXED_FAST; other precisions return
+ * HME_E_UNSUPPORTED from hme_create. */
+enum hme_process { HME_EEMUMU = 0, HME_GGTT = 1, HME_GGTTG = 2, HME_GGTTGG = 3, HME_GGTTGGG = 4 };
 
 /* HME_FP64: every step in double precision.
  * HME_MIXED_FAST: vertices, propagators, jamps and the colour sum in single
@@ -84,7 +87,10 @@ int hme_create(int process, const hme_sm_card* card, int precision, int device, 
  * NULL for the default stream).  `momenta` and `me2` are caller-owned device
  * pointers, 8-byte aligned, [nevt][npar][4] and [nevt] doubles.  alpha_s is the
  * strong coupling for this call.  nevt = 0 is a successful no-op; any nevt >= 1
- * is valid (partial wavefronts are masked).  Not thread-safe per handle. */
+ * is valid (partial wavefronts are masked).  Not thread-safe per handle.
+ * HME_GGTTGGG also takes a device workspace of min(nevt, 16384) * 120 * ngoodhel * 8
+ * bytes, allocated and released on `hip_stream` in stream order (HME_E_OOM if that
+ * fails); larger batches run as consecutive sub-batches of 16384 events. */
 int hme_compute(hme_handle* h, double alpha_s, int64_t nevt, const double* momenta, double* me2, void* hip_stream);
 
 /* Fill `info` with the handle's process constants. */

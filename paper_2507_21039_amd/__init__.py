@@ -12,12 +12,13 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhme.so")
 
-EEMUMU, GGTT, GGTTG, GGTTGG = 0, 1, 2, 3
+EEMUMU, GGTT, GGTTG, GGTTGG, GGTTGGG = 0, 1, 2, 3, 4
 FP64, MIXED_FAST, MIXED_PAPER = 0, 1, 2
 MIXED = MIXED_FAST
 PRECISION_NAMES = {FP64: "fp64", MIXED_FAST: "mixed_fast", MIXED_PAPER: "mixed_paper"}
-NPAR = {EEMUMU: 4, GGTT: 4, GGTTG: 5, GGTTGG: 6}
-PROCESS_NAMES = {EEMUMU: "e+e- -> mu+mu-", GGTT: "gg -> ttbar", GGTTG: "gg -> ttbar g", GGTTGG: "gg -> ttbar gg"}
+NPAR = {EEMUMU: 4, GGTT: 4, GGTTG: 5, GGTTGG: 6, GGTTGGG: 7}
+PROCESS_NAMES = {EEMUMU: "e+e- -> mu+mu-", GGTT: "gg -> ttbar", GGTTG: "gg -> ttbar g", GGTTGG: "gg -> ttbar gg",
+                 GGTTGGG: "gg -> ttbar ggg"}
 
 HME_OK, HME_E_ARG, HME_E_HIP, HME_E_OOM, HME_E_BUDGET, HME_E_TIMEOUT, HME_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 

@@ -19,13 +19,20 @@ ARCH = "gfx950"
 # -packed-fp32-ops keeps the compiler from emitting packed FP32 VALU instructions.
 HIPFLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wall", "-Wno-unused-variable",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = ["hme.cpp", "server.hip", "proc_eemumu.hip", "proc_ggtt.hip", "proc_ggttg.hip", "proc_ggttgg.hip"]
 _KERNEL_DEPS = ["me2_kernels.h", "helas.h", "process.h"]
+_PROCS = ("eemumu", "ggtt", "ggttg", "ggttgg", "ggttggg")
+# g g -> t tbar g g g runs as pieces, one generated translation unit each
+PIECES = {"ggttggg": 12}
+SOURCES = ["hme.cpp", "server.hip"] + [f"proc_{p}.hip" for p in _PROCS] + [
+    f"procs/{p}_c{c}.hip" for p, n in PIECES.items() for c in range(n)]
 DEPS = {
     "hme.cpp": _KERNEL_DEPS + ["params.h", "../../include/hme.h"],
     "server.hip": ["../../include/hme.h"],
-    **{f"proc_{p}.hip": _KERNEL_DEPS + [f"procs/{p}.h"] for p in ("eemumu", "ggtt", "ggttg", "ggttgg")},
+    **{f"proc_{p}.hip": _KERNEL_DEPS + [f"procs/{p}.h"] for p in _PROCS},
+    **{f"procs/{p}_c{c}.hip": _KERNEL_DEPS + [f"procs/{p}.h", f"procs/{p}_c{c}.h"]
+       for p, n in PIECES.items() for c in range(n)},
 }
+DEPS["proc_ggttggg.hip"] = DEPS["proc_ggttggg.hip"] + ["procs/ggttggg_chunks.h"]
 
 
 def hipcc() -> str:
@@ -51,8 +58,11 @@ def _compile(src: str, verbose: bool, force: bool) -> str:
 
 def build(verbose: bool = False, jobs: int | None = None, force: bool = True) -> str:
     """Generate the process headers and compile; force=False reuses objects newer than their sources."""
-    from .gen.__main__ import generate
-    generate(os.path.join(CSRC, "procs"))
+    from .gen.__main__ import PROCESSES, generate
+    infos = generate(os.path.join(CSRC, "procs"))
+    for p, n in PIECES.items():
+        if infos[p]["nchunk"] != n or PROCESSES[p][3] != n:
+            raise RuntimeError(f"{p}: generator makes {infos[p]['nchunk']} pieces, build expects {n}")
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(len(SOURCES), max(1, len(os.sched_getaffinity(0))))
     with ThreadPoolExecutor(jobs) as ex:

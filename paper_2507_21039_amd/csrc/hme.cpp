@@ -23,6 +23,7 @@ HME_DECLARE(eemumu)
 HME_DECLARE(ggtt)
 HME_DECLARE(ggttg)
 HME_DECLARE(ggttgg)
+HME_DECLARE(ggttggg)
 #undef HME_DECLARE
 
 struct ProcEntry {
@@ -38,7 +39,11 @@ static const ProcEntry kProcs[] = {
     {info_ggtt, launch_me2_ggtt, launch_hel_ggtt, true, 1000.0},
     {info_ggttg, launch_me2_ggttg, launch_hel_ggttg, true, 1500.0},
     {info_ggttgg, launch_me2_ggttgg, launch_hel_ggttgg, true, 2000.0},
+    {info_ggttggg, launch_me2_ggttggg, launch_hel_ggttggg, true, 2000.0},
 };
+
+// events per sub-batch of a process evaluated in pieces (workspace ncol * ngood * 8 bytes each)
+constexpr int64_t kChunkSubBatch = 16384;
 constexpr int kNumProcs = sizeof(kProcs) / sizeof(kProcs[0]);
 
 }  // namespace hme
@@ -169,6 +174,9 @@ int hme_create(int process, const hme_sm_card* card, int precision, int device, 
   DeviceGuard guard(device);
   if (guard.err != hipSuccess) return hip_fail(guard.err, "hme_create: hipSetDevice");
 
+  if (P.info().nchunk > 0 && precision != HME_MIXED_FAST)
+    return fail(HME_E_UNSUPPORTED, "hme_create: this process is built for HME_MIXED_FAST only");
+
   auto* h = new hme_handle;
   h->process = process;
   h->precision = precision;
@@ -236,10 +244,12 @@ double handle_norm(const hme_handle* h, double alpha_s) {
 
 int handle_npar(const hme_handle* h) { return h->info.npar; }
 
+bool handle_chunked(const hme_handle* h) { return h->info.nchunk > 0; }
+
 hipError_t launch_for_handle(const hme_handle* h, int64_t nevt_grid, const int64_t* nevt_dev, const double* mom,
-                             double* out, double norm, hipStream_t s) {
+                             double* out, double norm, hipStream_t s, void* ws, int64_t ws_events) {
   LaunchArgs a{mom, out, nevt_grid, h->d_goodhel, (int)h->goodhel.size(), h->prm, norm, s,
-               h->precision == HME_MIXED_PAPER ? 1 : 0, nevt_dev};
+               h->precision == HME_MIXED_PAPER ? 1 : 0, nevt_dev, ws, ws_events};
   return kProcs[h->process].me2(a, h->precision);
 }
 
@@ -257,8 +267,22 @@ int hme_compute(hme_handle* h, double alpha_s, int64_t nevt, const double* momen
   if (!(alpha_s > 0)) return fail(HME_E_ARG, "hme_compute: alpha_s must be positive");
   DeviceGuard guard(h->device);
   if (guard.err != hipSuccess) return hip_fail(guard.err, "hme_compute: hipSetDevice");
-  hipError_t e = hme::launch_for_handle(h, nevt, nullptr, momenta, me2, hme::handle_norm(h, alpha_s),
-                                        static_cast<hipStream_t>(hip_stream));
+  const auto stream = static_cast<hipStream_t>(hip_stream);
+  void* ws = nullptr;
+  int64_t ws_events = 0;
+  hipError_t e;
+  if (hme::handle_chunked(h)) {
+    // jamp workspace, allocated and released in stream order
+    ws_events = nevt < hme::kChunkSubBatch ? nevt : hme::kChunkSubBatch;
+    const size_t bytes = (size_t)ws_events * h->info.ncol * h->goodhel.size() * 2 * sizeof(float);
+    if ((e = hipMallocAsync(&ws, bytes, stream)) != hipSuccess)
+      return fail(HME_E_OOM, std::string("hme_compute: workspace: ") + hipGetErrorString(e));
+  }
+  e = hme::launch_for_handle(h, nevt, nullptr, momenta, me2, hme::handle_norm(h, alpha_s), stream, ws, ws_events);
+  if (ws) {
+    const hipError_t ef = hipFreeAsync(ws, stream);
+    if (e == hipSuccess) e = ef;
+  }
   if (e != hipSuccess) return hip_fail(e, "hme_compute: launch");
   return HME_OK;
 }

@@ -97,6 +97,118 @@ __global__ void __launch_bounds__(64) hel_kernel(const double* __restrict__ mom,
   }
 }
 
+// ------------------------------------------------- processes evaluated in pieces
+//
+// For the largest process one straight-line kernel would not compile in reasonable
+// time, and its 120 jamps would not fit in registers beside the wavefunctions.  The
+// generator then cuts the amplitude schedule into pieces; each piece is a kernel that
+// adds its terms to the jamps of the flows it touches, kept between kernels in a
+// device workspace
+//     ws[event][flow][good helicity]   (cx<float>, events of one sub-batch)
+// so that the LPE lanes of an event, which hold consecutive helicities, touch
+// consecutive addresses.  A last kernel reads all jamps of a helicity back, forms the
+// colour sum and reduces over helicities as me2_kernel does.  Single precision only.
+
+// the per-event table in LDS, built by the event's lanes (as in me2_kernel)
+template <class Proc, int LPE>
+HME_FN void build_table(const double (&p)[Proc::npar][4], const ProcParams& prm, int sub, double* tab) {
+  for (int j = sub; j < Proc::nitems; j += LPE) Proc::table_entry(p, prm, j, tab);
+}
+
+template <class Proc, class Chunk, int LPE>
+__global__ void __launch_bounds__(256)
+    chunk_kernel(const double* __restrict__ mom, cx<float>* __restrict__ ws, int64_t nevt,
+                 const int* __restrict__ goodhel, int ngood, ProcParams prm) {
+  constexpr int EPW = 64 / LPE, EPB = 256 / LPE;
+  __shared__ double table[EPB * Proc::ntab];
+  const int lane = threadIdx.x & 63;
+  if ((int64_t)blockIdx.x * EPB >= nevt) return;  // uniform per block
+  const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t ev = ((int64_t)blockIdx.x * 4 + wib) * EPW + lane / LPE;
+  const int sub = lane % LPE;
+  const int64_t evc = ev < nevt ? ev : nevt - 1;  // ragged tail: recompute the last event, store nothing
+  double p[Proc::npar][4];
+  load_event<Proc>(mom, evc, p);
+  double* tab = table + (threadIdx.x / LPE) * Proc::ntab;
+  build_table<Proc, LPE>(p, prm, sub, tab);
+  __syncthreads();
+  if (ev >= nevt) return;  // no barrier follows
+  cx<float>* w = ws + (size_t)ev * Proc::ncol * ngood;
+  for (int k = sub; k < ngood; k += LPE) {
+    cx<float> jamp[Chunk::nw];
+#pragma unroll
+    for (int c = 0; c < Chunk::nw; ++c) jamp[c] = {0.f, 0.f};
+    Chunk::template amplitudes<float>(prm, (unsigned)goodhel[k], (tab_ptr)tab, jamp);
+#pragma unroll
+    for (int c = 0; c < Chunk::nw; ++c) {
+      cx<float>* dst = w + (size_t)Chunk::words[c] * ngood + k;
+      if (Chunk::fresh[c])
+        *dst = jamp[c];
+      else
+        *dst = *dst + jamp[c];
+    }
+  }
+}
+
+// colour sum of the workspace jamps; per_hel = 0: out[ev] = norm * sum over helicities,
+// per_hel = 1: out[ev * ngood + k] = colour sum of good helicity k (unnormalised)
+template <class Proc, int LPE>
+__global__ void __launch_bounds__(256)
+    colour_kernel(const cx<float>* __restrict__ ws, double* __restrict__ out, int64_t nevt, int ngood,
+                  double norm, int per_hel) {
+  constexpr int EPW = 64 / LPE, EPB = 256 / LPE;
+  const int lane = threadIdx.x & 63;
+  if ((int64_t)blockIdx.x * EPB >= nevt) return;
+  const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t ev = ((int64_t)blockIdx.x * 4 + wib) * EPW + lane / LPE;
+  const int sub = lane % LPE;
+  const int64_t evc = ev < nevt ? ev : nevt - 1;
+  const cx<float>* w = ws + (size_t)evc * Proc::ncol * ngood;
+  double acc = 0.0;
+  for (int k = sub; k < ngood; k += LPE) {
+    cx<float> jamp[Proc::ncol];
+#pragma unroll
+    for (int c = 0; c < Proc::ncol; ++c) jamp[c] = w[(size_t)c * ngood + k];
+    const double v = (double)Proc::template colour_sum<float>(jamp);
+    if (per_hel && ev < nevt) out[(size_t)ev * ngood + k] = v;
+    acc += v;
+  }
+#pragma unroll
+  for (int off = LPE / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (!per_hel && sub == 0 && ev < nevt) out[ev] = acc * norm;
+}
+
+struct ChunkArgs {
+  const double* mom;  // momenta of the sub-batch's first event
+  cx<float>* ws;      // workspace, nevt * ncol * ngood entries
+  int64_t nevt;       // events in the sub-batch
+  const int* goodhel;
+  int ngood;
+  ProcParams prm;
+  hipStream_t stream;
+};
+
+template <class Proc> constexpr int chunk_lpe() { return Proc::nhel >= 64 ? 64 : 32; }
+
+template <class Proc, class Chunk> hipError_t launch_chunk(const ChunkArgs& a) {
+  constexpr int LPE = chunk_lpe<Proc>(), EPB = 256 / LPE;
+  const int64_t blocks = (a.nevt + EPB - 1) / EPB;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  chunk_kernel<Proc, Chunk, LPE><<<dim3((unsigned)blocks), dim3(256), 0, a.stream>>>(a.mom, a.ws, a.nevt, a.goodhel,
+                                                                                     a.ngood, a.prm);
+  return hipGetLastError();
+}
+
+template <class Proc>
+hipError_t launch_colour(const cx<float>* ws, double* out, int64_t nevt, int ngood, double norm, int per_hel,
+                         hipStream_t s) {
+  constexpr int LPE = chunk_lpe<Proc>(), EPB = 256 / LPE;
+  const int64_t blocks = (nevt + EPB - 1) / EPB;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  colour_kernel<Proc, LPE><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(ws, out, nevt, ngood, norm, per_hel);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ launchers
 
 struct LaunchArgs {
@@ -110,16 +222,19 @@ struct LaunchArgs {
   hipStream_t stream;
   int colour_f32;  // colour sum in single precision (for double-precision amplitudes)
   const int64_t* nevt_dev = nullptr;  // if set, the kernel reads the event count here (nevt sizes the grid)
+  void* ws = nullptr;                 // jamp workspace of a process evaluated in pieces
+  int64_t ws_events = 0;              // events the workspace holds (the sub-batch size)
 };
 
 struct ProcInfo {
   int npar, nhel, ncol, ndiag, namp, gs_power;
   double iden, colour_denom, flops_per_hel, flops_per_event;
+  int nchunk;  // 0: one kernel; otherwise pieces + colour kernel over a jamp workspace
 };
 
 template <class Proc> ProcInfo make_info() {
   return ProcInfo{Proc::npar, Proc::nhel, Proc::ncol, Proc::ndiag, Proc::namp, Proc::gs_power,
-                  Proc::iden, Proc::colour_denom, Proc::flops_per_hel, Proc::flops_per_event};
+                  Proc::iden, Proc::colour_denom, Proc::flops_per_hel, Proc::flops_per_event, Proc::nchunk};
 }
 
 // lanes per event: the smallest of 4, 16, 32, 64 that holds all good helicities (64 loops over more)

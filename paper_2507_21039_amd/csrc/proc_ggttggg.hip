@@ -1,0 +1,54 @@
+// g g -> t tbar g g g: the helicity filter, the colour kernel and the sequence of
+// piece kernels (each piece in its own generated translation unit).
+#include "me2_kernels.h"
+#include "procs/ggttggg.h"
+#include "procs/ggttggg_chunks.h"
+
+namespace hme {
+
+using P7 = P_ggttggg;
+static_assert(sizeof(chunks_ggttggg) / sizeof(chunks_ggttggg[0]) == P7::nchunk, "piece table out of date");
+
+ProcInfo info_ggttggg() { return make_info<P7>(); }
+
+// all pieces, then the colour sum, for consecutive sub-batches of a.ws_events events
+static hipError_t run_pieces(const double* mom, double* out, int64_t nevt, const int* goodhel, int ngood,
+                             const ProcParams& prm, double norm, int per_hel, cx<float>* ws, int64_t ws_events,
+                             hipStream_t s) {
+  for (int64_t e0 = 0; e0 < nevt; e0 += ws_events) {
+    const int64_t n = nevt - e0 < ws_events ? nevt - e0 : ws_events;
+    const ChunkArgs c{mom + e0 * P7::npar * 4, ws, n, goodhel, ngood, prm, s};
+    for (int k = 0; k < P7::nchunk; ++k) {
+      const hipError_t e = chunks_ggttggg[k](c);
+      if (e != hipSuccess) return e;
+    }
+    const hipError_t e = launch_colour<P7>(ws, out + (per_hel ? e0 * ngood : e0), n, ngood, norm, per_hel, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// single precision only (the library rejects other precisions when the handle is made)
+hipError_t launch_me2_ggttggg(const LaunchArgs& a, int precision) {
+  if (precision != 1 || a.nevt_dev || !a.ws || a.ws_events <= 0) return hipErrorInvalidValue;
+  return run_pieces(a.mom, a.out, a.nevt, a.goodhel, a.ngood, a.prm, a.norm, 0, static_cast<cx<float>*>(a.ws),
+                    a.ws_events, a.stream);
+}
+
+// |M_h|^2 of every helicity for nev events (set-up only; synchronous, own workspace)
+hipError_t launch_hel_ggttggg(const double* mom, int nev, const ProcParams& prm, double* out, hipStream_t s) {
+  int hel[P7::nhel];
+  for (int h = 0; h < P7::nhel; ++h) hel[h] = h;
+  int* d_hel = nullptr;
+  cx<float>* ws = nullptr;
+  hipError_t e = hipMalloc(&d_hel, sizeof hel);
+  if (e == hipSuccess) e = hipMalloc(&ws, (size_t)nev * P7::ncol * P7::nhel * sizeof(cx<float>));
+  if (e == hipSuccess) e = hipMemcpy(d_hel, hel, sizeof hel, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = run_pieces(mom, out, nev, d_hel, P7::nhel, prm, 1.0, 1, ws, nev, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (ws) (void)hipFree(ws);
+  if (d_hel) (void)hipFree(d_hel);
+  return e;
+}
+
+}  // namespace hme

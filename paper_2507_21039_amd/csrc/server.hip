@@ -22,7 +22,7 @@ namespace hme {
 double handle_norm(const hme_handle* h, double alpha_s);
 int handle_npar(const hme_handle* h);
 hipError_t launch_for_handle(const hme_handle* h, int64_t nevt_grid, const int64_t* nevt_dev, const double* mom,
-                             double* out, double norm, hipStream_t s);
+                             double* out, double norm, hipStream_t s, void* ws, int64_t ws_events);
 void set_last_error(const std::string& msg);
 }  // namespace hme
 
@@ -154,7 +154,8 @@ struct Server : hme_server {
       e1 = hipGetLastError();
     }
     if (e1 == hipSuccess)
-      e1 = hme::launch_for_handle(handles[process], bucket, &sl.d_desc->nevt_total, d_mom, d_out, 1.0, sl.stream);
+      e1 = hme::launch_for_handle(handles[process], bucket, &sl.d_desc->nevt_total, d_mom, d_out, 1.0, sl.stream,
+                                 nullptr, 0);
     if (e1 == hipSuccess) {
       const unsigned sx = (unsigned)std::min<int64_t>(256, std::max<int64_t>(1, bucket / 1024));
       scatter_kernel<<<dim3(sx, kMaxBatchReq), dim3(256), 0, sl.stream>>>(sl.d_desc, d_out);
@@ -336,6 +337,7 @@ int hme_submit(hme_server* srv, int process, double alpha_s, int64_t nevt, const
                uint64_t* req_id) {
   auto* s = static_cast<Server*>(srv);
   if (!s || !req_id) return srv_fail(HME_E_ARG, "hme_submit: NULL server or req_id");
+  if (process == HME_GGTTGGG) return srv_fail(HME_E_UNSUPPORTED, "hme_submit: process not served");
   if (process < 0 || process >= kNumProcesses) return srv_fail(HME_E_ARG, "hme_submit: unknown process");
   if (nevt < 0) return srv_fail(HME_E_ARG, "hme_submit: nevt < 0");
   if (!(alpha_s > 0)) return srv_fail(HME_E_ARG, "hme_submit: alpha_s must be positive");

@@ -132,7 +132,8 @@ def prefetch_units(lines, enable, kits: bool = True):
     return out
 
 
-def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all")) -> tuple[str, dict]:
+def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chunks: int = 0,
+             file_stem: str = ""):
     """Emit the process header.
 
     budget: number of off-shell wavefunctions kept live at once, for the double and the
@@ -143,6 +144,11 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all")) -> 
     denominators read one unit ahead) or "all" (kits too).  The defaults are the fastest
     measured on MI355X for g g -> t tbar g g: budget 4 without prefetch keeps the FP64
     kernel at 2 waves per SIMD; FP32 gains more from hiding LDS latency.
+    chunks: if nonzero, cut the single-precision schedule into that many contiguous pieces,
+    each emitted as its own struct (returned in info["chunk_headers"]) that adds its terms to
+    the jamps of the flows it touches; the main header then holds the table and the colour
+    sum only.  Used where one straight-line kernel would be too large to compile and to keep
+    its jamps in registers.
     """
     if isinstance(budget, int):
         budget = (budget, budget)
@@ -171,15 +177,21 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all")) -> 
             didx[mask] = (len(didx), massive)
         return f"dv<T>(tab, DOFF + {didx[mask][0]})"
 
-    def emit_schedule(budget):
-        """One amplitude schedule under a live-wavefunction budget; returns the body lines."""
+    from .diagrams import schedule
+    full_order = schedule(g)
+
+    def emit_schedule(budget, order=None, wmap=None):
+        """One amplitude schedule under a live-wavefunction budget; returns the body lines.
+
+        order: the amplitude terms to evaluate (default: all, in schedule order);
+        wmap: colour flow -> index into the jamp array (default: all flows in basis order).
+        """
         lines = []
         flops_exec = 0
         flops_dag = 0
-        # ---- schedule with a bounded number of live wavefunctions
-        from .diagrams import schedule
         import bisect
-        order = schedule(g)
+        order = full_order if order is None else order
+        wmap = widx if wmap is None else wmap
         amp_nodes = [_closure(g, g.amps[i].args) for i in order]
         uses = {}
         for t, s in enumerate(amp_nodes):
@@ -287,8 +299,8 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all")) -> 
             lines.append(f"  {{  // diagram {amp.diagram + 1}")
             lines.extend(pre)
             lines.append(f"    const cx<T> a = {call};")
-            for w, c in sorted(amp.colour.terms.items(), key=lambda x: widx[x[0]]):
-                j = widx[w]
+            for w, c in sorted(amp.colour.terms.items(), key=lambda x: wmap[x[0]]):
+                j = wmap[w]
                 lines.append(f"    jamp[{j}] = jamp[{j}] {_coef_code(c * phase, 'a')};")
                 jamp_terms += 1
             lines.append("  }")
@@ -300,8 +312,30 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all")) -> 
         flops_dag += 2 * jamp_terms + sum(EXT_FLOPS[ext_name[g.nodes[k].kind]] for k in g.nodes if k[0] == "E")
         return lines, flops_exec, flops_dag, jamp_terms
 
-    lines_d, flops_exec_d, flops_dag, jamp_terms = emit_schedule(budget[0])
-    lines_f, flops_exec_f, _, _ = emit_schedule(budget[1])
+    if chunks:
+        # chunked form: contiguous pieces of the schedule, each with the flows it touches
+        K = chunks
+        size = (len(full_order) + K - 1) // K
+        pieces = [full_order[c * size:(c + 1) * size] for c in range(K)]
+        chunk_out = []
+        seen_words = set()
+        flops_dag_total = 0
+        for c, piece in enumerate(pieces):
+            words = sorted({w for i in piece for w in g.amps[i].colour.terms}, key=lambda w: widx[w])
+            wm = {w: j for j, w in enumerate(words)}
+            fresh = [w not in seen_words for w in words]
+            seen_words |= set(words)
+            lines_c, fexec_c, fdag_c, jt_c = emit_schedule(budget[1], piece, wm)
+            chunk_out.append((words, fresh, lines_c, fexec_c, fdag_c, jt_c))
+        assert len(seen_words) == ncol
+        lines_d = lines_f = []
+        flops_exec_d = flops_exec_f = sum(x[3] for x in chunk_out)
+        # a wavefunction recomputed by several chunks counts once in the DAG figure
+        flops_dag = emit_schedule(budget[1])[2]
+        jamp_terms = sum(x[5] for x in chunk_out)
+    else:
+        lines_d, flops_exec_d, flops_dag, jamp_terms = emit_schedule(budget[0])
+        lines_f, flops_exec_f, _, _ = emit_schedule(budget[1])
 
     nq, nd = len(qidx), len(didx)
     ext = [k for k in range(npar)]
@@ -319,6 +353,35 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all")) -> 
 
     body_d = finish(lines_d, prefetch[0])
     body_f = finish(lines_f, prefetch[1])
+    chunk_headers = []
+    for c, (words, fresh, lines_c, fexec_c, fdag_c, jt_c) in enumerate(chunk_out if chunks else []):
+        body_c = finish(lines_c, prefetch[1])
+        chunk_headers.append(f"""// Generated by paper_2507_21039_amd.gen for {label}, piece {c} of {len(chunk_out)}.  Do not edit.
+// {len(pieces[c])} of the {len(g.amps)} amplitude terms, adding to {len(words)} of the {ncol} colour flows.
+#pragma once
+#include "{file_stem}.h"
+
+namespace hme {{
+
+struct {name}_c{c} {{
+  using Base = {name};
+  static constexpr int nw = {len(words)};  // colour flows this piece adds to
+  static constexpr int words[{len(words)}] = {{{", ".join(str(widx[w]) for w in words)}}};
+  // 1 where no earlier piece adds to the flow (its workspace entry is written, not updated)
+  static constexpr int fresh[{len(words)}] = {{{", ".join(str(int(f)) for f in fresh)}}};
+  static constexpr double flops_per_hel_executed = {fexec_c};
+
+  // this piece's contributions to the jamps words[] of one helicity (jamp[] zeroed by the caller)
+  template <class T>
+  HME_FN static void amplitudes(const ProcParams& prm, unsigned h, tab_ptr tab, cx<T> (&jamp)[{len(words)}]) {{
+    auto hel = [h](int k) {{ return (h >> ({npar - 1} - k) & 1u) ? 1 : -1; }};
+    const T mT = T(prm.mT);
+{body_c}
+  }}
+}};
+
+}}  // namespace hme
+""")
     qmask = [0] * nq
     qsign = [0] * nq
     for (m, sgn), i in qidx.items():
@@ -344,6 +407,40 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all")) -> 
         cs_flops += 4 * len(terms) + 4
 
     nitems = nq + nd + npar
+    if chunks:
+        amp_section = (f"  // the amplitude terms are split into {len(chunk_out)} contiguous pieces of the schedule\n"
+                       f"  // ({name}_c0 .. {name}_c{len(chunk_out) - 1}); each runs as its own kernel and adds\n"
+                       f"  // its terms to the jamps kept in a device workspace between kernels\n"
+                       f"  static constexpr int nchunk = {len(chunk_out)};\n\n")
+    else:
+        amp_section = f"""  static constexpr int nchunk = 0;  // one kernel evaluates every amplitude term
+
+  // jamps of one helicity (jamp[] must be zeroed by the caller); the schedule depends on the
+  // arithmetic type (budget {budget[0]} / prefetch "{prefetch[0]}" for double, {budget[1]} / "{prefetch[1]}" for float)
+  template <class T>
+  HME_FN static void amplitudes(const double (&p)[{npar}][4], const ProcParams& prm, unsigned h,
+                                tab_ptr tab, cx<T> (&jamp)[{ncol}]) {{
+    if constexpr (sizeof(T) == 8)
+      amplitudes_d<T>(prm, h, tab, jamp);
+    else
+      amplitudes_f<T>(prm, h, tab, jamp);
+  }}
+
+  template <class T>
+  HME_FN static void amplitudes_d(const ProcParams& prm, unsigned h, tab_ptr tab, cx<T> (&jamp)[{ncol}]) {{
+    auto hel = [h](int k) {{ return (h >> ({npar - 1} - k) & 1u) ? 1 : -1; }};
+    const T mT = T(prm.mT);
+{body_d}
+  }}
+
+  template <class T>
+  HME_FN static void amplitudes_f(const ProcParams& prm, unsigned h, tab_ptr tab, cx<T> (&jamp)[{ncol}]) {{
+    auto hel = [h](int k) {{ return (h >> ({npar - 1} - k) & 1u) ? 1 : -1; }};
+    const T mT = T(prm.mT);
+{body_f}
+  }}
+
+"""
     hdr = f"""// Generated by paper_2507_21039_amd.gen for {label}.  Do not edit.
 // {g.ndiag} Feynman diagrams, {len(g.amps)} amplitude terms (each four-gluon vertex split into its
 // three structures), {len(g.nodes)} wavefunctions, {ncol} colour flows; at most {budget[0]} (double) or
@@ -410,32 +507,7 @@ struct {name} {{
     }}
   }}
 
-  // jamps of one helicity (jamp[] must be zeroed by the caller); the schedule depends on the
-  // arithmetic type (budget {budget[0]} / prefetch "{prefetch[0]}" for double, {budget[1]} / "{prefetch[1]}" for float)
-  template <class T>
-  HME_FN static void amplitudes(const double (&p)[{npar}][4], const ProcParams& prm, unsigned h,
-                                tab_ptr tab, cx<T> (&jamp)[{ncol}]) {{
-    if constexpr (sizeof(T) == 8)
-      amplitudes_d<T>(prm, h, tab, jamp);
-    else
-      amplitudes_f<T>(prm, h, tab, jamp);
-  }}
-
-  template <class T>
-  HME_FN static void amplitudes_d(const ProcParams& prm, unsigned h, tab_ptr tab, cx<T> (&jamp)[{ncol}]) {{
-    auto hel = [h](int k) {{ return (h >> ({npar - 1} - k) & 1u) ? 1 : -1; }};
-    const T mT = T(prm.mT);
-{body_d}
-  }}
-
-  template <class T>
-  HME_FN static void amplitudes_f(const ProcParams& prm, unsigned h, tab_ptr tab, cx<T> (&jamp)[{ncol}]) {{
-    auto hel = [h](int k) {{ return (h >> ({npar - 1} - k) & 1u) ? 1 : -1; }};
-    const T mT = T(prm.mT);
-{body_f}
-  }}
-
-  // sum over colour flows of conj(jamp) C jamp times colour_denom
+{amp_section}  // sum over colour flows of conj(jamp) C jamp times colour_denom
   template <class T> HME_FN static T colour_sum(const cx<T> (&jamp)[{ncol}]) {{
     T s = 0;
 {chr(10).join(cs)}
@@ -449,7 +521,8 @@ struct {name} {{
                 flops_per_hel=flops_dag + cs_flops, flops_per_hel_executed=flops_exec_d + cs_flops,
                 flops_per_hel_executed_f32=flops_exec_f + cs_flops,
                 flops_colour=cs_flops, flops_table=flops_table, colour_denom=D, numerators=N,
-                jamp_terms=jamp_terms, budget=list(budget), prefetch=list(prefetch), ntab=ntab)
+                jamp_terms=jamp_terms, budget=list(budget), prefetch=list(prefetch), ntab=ntab,
+                nchunk=len(chunk_headers), chunk_headers=chunk_headers)
     return hdr, info
 
 
@@ -481,6 +554,7 @@ struct {name} {{
   static constexpr int ncol = 1;
   static constexpr int ndiag = 2;
   static constexpr int namp = 2;
+  static constexpr int nchunk = 0;
   static constexpr int gs_power = 0;
   static constexpr double iden = 4.0;  // average over the initial helicities
   static constexpr double colour_denom = 1.0;

@@ -1,0 +1,81 @@
+// Test-only: evaluates the generated g g -> t tbar g g g pieces on the host CPU (all
+// helicities, no filter), adding each piece's jamps into the 120 flows exactly as the
+// piece kernels do through their workspace, so the split can be checked against the
+// oracle without a GPU.  The library never uses this.
+#include <cstdint>
+#include <string>
+
+#include "../../paper_2507_21039_amd/csrc/params.h"
+#include "../../paper_2507_21039_amd/csrc/procs/ggttggg_c0.h"
+#include "../../paper_2507_21039_amd/csrc/procs/ggttggg_c1.h"
+#include "../../paper_2507_21039_amd/csrc/procs/ggttggg_c2.h"
+#include "../../paper_2507_21039_amd/csrc/procs/ggttggg_c3.h"
+#include "../../paper_2507_21039_amd/csrc/procs/ggttggg_c4.h"
+#include "../../paper_2507_21039_amd/csrc/procs/ggttggg_c5.h"
+#include "../../paper_2507_21039_amd/csrc/procs/ggttggg_c6.h"
+#include "../../paper_2507_21039_amd/csrc/procs/ggttggg_c7.h"
+#include "../../paper_2507_21039_amd/csrc/procs/ggttggg_c8.h"
+#include "../../paper_2507_21039_amd/csrc/procs/ggttggg_c9.h"
+#include "../../paper_2507_21039_amd/csrc/procs/ggttggg_c10.h"
+#include "../../paper_2507_21039_amd/csrc/procs/ggttggg_c11.h"
+
+namespace {
+using P = hme::P_ggttggg;
+static_assert(P::nchunk == 12, "update the piece list");
+
+template <class C, class T>
+void add_piece(const hme::ProcParams& prm, unsigned h, hme::tab_ptr tab, hme::cx<T> (&jamp)[P::ncol]) {
+  hme::cx<T> part[C::nw];
+  for (auto& j : part) j = {T(0), T(0)};
+  C::template amplitudes<T>(prm, h, tab, part);
+  for (int c = 0; c < C::nw; ++c) jamp[C::words[c]] = C::fresh[c] ? part[c] : jamp[C::words[c]] + part[c];
+}
+
+template <class T>
+void run(const hme::ProcParams& prm, double alpha_s, int64_t nevt, const double* mom, double* out) {
+  const double pi = 3.14159265358979323846;
+  double norm = 1.0 / (P::iden * P::colour_denom);
+  for (int k = 0; k < P::gs_power / 2; ++k) norm *= 4 * pi * alpha_s;
+  for (int64_t e = 0; e < nevt; ++e) {
+    double p[P::npar][4];
+    for (int k = 0; k < P::npar; ++k)
+      for (int mu = 0; mu < 4; ++mu) p[k][mu] = mom[(e * P::npar + k) * 4 + mu];
+    double tab[P::ntab];
+    for (int j = 0; j < P::nitems; ++j) P::table_entry(p, prm, j, tab);
+    double acc = 0;
+    for (int h = 0; h < P::nhel; ++h) {
+      hme::cx<T> jamp[P::ncol];
+      // poison: every flow must be written by its first piece before it is read
+      for (auto& j : jamp) j = {T(1e30), T(1e30)};
+      const auto t = (hme::tab_ptr)tab;
+      add_piece<hme::P_ggttggg_c0, T>(prm, h, t, jamp);
+      add_piece<hme::P_ggttggg_c1, T>(prm, h, t, jamp);
+      add_piece<hme::P_ggttggg_c2, T>(prm, h, t, jamp);
+      add_piece<hme::P_ggttggg_c3, T>(prm, h, t, jamp);
+      add_piece<hme::P_ggttggg_c4, T>(prm, h, t, jamp);
+      add_piece<hme::P_ggttggg_c5, T>(prm, h, t, jamp);
+      add_piece<hme::P_ggttggg_c6, T>(prm, h, t, jamp);
+      add_piece<hme::P_ggttggg_c7, T>(prm, h, t, jamp);
+      add_piece<hme::P_ggttggg_c8, T>(prm, h, t, jamp);
+      add_piece<hme::P_ggttggg_c9, T>(prm, h, t, jamp);
+      add_piece<hme::P_ggttggg_c10, T>(prm, h, t, jamp);
+      add_piece<hme::P_ggttggg_c11, T>(prm, h, t, jamp);
+      acc += (double)P::template colour_sum<T>(jamp) * norm;
+    }
+    out[e] = acc;
+  }
+}
+}  // namespace
+
+extern "C" int hostcheck7_me2(int precision, const double* card, double alpha_s, int64_t nevt, const double* mom,
+                              double* out) {
+  hme_sm_card c{card[0], card[1], card[2], card[3], card[4], card[5]};
+  hme::ProcParams prm;
+  std::string why;
+  if (!hme::derive_params(c, prm, why)) return -1;
+  if (precision == 1)
+    run<float>(prm, alpha_s, nevt, mom, out);
+  else
+    run<double>(prm, alpha_s, nevt, mom, out);
+  return 0;
+}

@@ -89,3 +89,55 @@ def test_generated_code_on_host_matches_oracle(hostlib, card, key, proc, n):
     assert np.abs(got / ref - 1).max() <= 1e-13
     mixed = host_me2(hostlib, proc, 1, p, card)
     assert np.abs(mixed / ref - 1).max() <= 1e-5
+
+
+HOSTLIB7 = os.path.join(HERE, "_build", "libhostcheck7.so")
+
+
+@pytest.fixture(scope="module")
+def hostlib7():
+    if not os.path.exists("/opt/rocm/bin/hipcc"):
+        pytest.skip("hipcc not available")
+    src = os.path.join(HERE, "hostcheck", "hostcheck7.hip")
+    procs = os.path.join(HERE, "..", "paper_2507_21039_amd", "csrc", "procs")
+    deps = [src] + [os.path.join(procs, f) for f in os.listdir(procs) if f.startswith("ggttggg")]
+    if not os.path.exists(HOSTLIB7) or os.path.getmtime(HOSTLIB7) < max(os.path.getmtime(d) for d in deps):
+        os.makedirs(os.path.dirname(HOSTLIB7), exist_ok=True)
+        subprocess.run(["/opt/rocm/bin/hipcc", "-O1", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
+                        "-x", "hip", src, "-o", HOSTLIB7], check=True)
+    L = ctypes.CDLL(HOSTLIB7)
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.hostcheck7_me2.argtypes = [ctypes.c_int, dp, ctypes.c_double, ctypes.c_int64, dp, dp]
+    return L
+
+
+def test_pieces_cover_every_term_once():
+    """The split of g g -> t tbar g g g: every amplitude term in exactly one piece, every flow
+    written first by exactly one piece."""
+    import json
+    info = json.load(open(os.path.join(HERE, "..", "paper_2507_21039_amd", "csrc", "procs", "processes.json")))
+    assert info["ggttggg"]["nchunk"] >= 2 and info["ggttggg"]["ncol"] == 120
+    import re
+    procs = os.path.join(HERE, "..", "paper_2507_21039_amd", "csrc", "procs")
+    first = []
+    nterms = 0
+    for c in range(info["ggttggg"]["nchunk"]):
+        text = open(os.path.join(procs, f"ggttggg_c{c}.h")).read()
+        nterms += int(re.search(r"// (\d+) of the 1890 amplitude terms", text).group(1))
+        words = [int(x) for x in re.search(r"words\[\d+\] = \{([^}]*)\}", text).group(1).split(",")]
+        fresh = [int(x) for x in re.search(r"fresh\[\d+\] = \{([^}]*)\}", text).group(1).split(",")]
+        first += [w for w, f in zip(words, fresh) if f]
+    assert nterms == 1890
+    assert sorted(first) == list(range(120))
+
+
+def test_generated_pieces_on_host_match_oracle(hostlib7, card):
+    """g g -> t tbar g g g evaluated piece by piece (as the GPU does through its workspace) on the host."""
+    dp = ctypes.POINTER(ctypes.c_double)
+    p = np.ascontiguousarray(configs.WORKLOADS["ggttggg"].momenta(6))
+    ref = oracle.me2(configs.GGTTGGG, p, card)
+    for prec, tol in ((0, 1e-13), (1, 1e-5)):
+        out = np.empty(len(p))
+        assert hostlib7.hostcheck7_me2(prec, card.ctypes.data_as(dp), 0.118, len(p), p.ctypes.data_as(dp),
+                                       out.ctypes.data_as(dp)) == 0
+        assert np.abs(out / ref - 1).max() <= tol, prec

@@ -230,3 +230,67 @@ def test_full_size_sampled(handles, card, key, proc):
     idx = np.unique(np.concatenate([np.random.default_rng(9).integers(0, w.nevt, 250), [0, w.nevt - 1]]))
     ref = oracle.me2(proc, p[idx], card, AS)
     fp64_gate(proc, p[idx], got[idx], ref, card)
+
+
+# ---------------------------------------------------------------- g g -> t tbar g g g
+# Evaluated in pieces over a jamp workspace, single precision only (MIXED_FAST gate).
+
+@pytest.fixture(scope="module")
+def h7(card):
+    print("[gpu] create process=ggttggg precision=mixed_fast", flush=True)
+    h = hme.Handle(hme.GGTTGGG, card, hme.MIXED_FAST)
+    yield h
+    h.close()
+
+
+def test_ggttggg_other_precisions_unsupported(card):
+    for prec in (hme.FP64, hme.MIXED_PAPER):
+        with pytest.raises(hme.HmeError) as e:
+            hme.Handle(hme.GGTTGGG, card, prec)
+        assert e.value.code == hme.HME_E_UNSUPPORTED
+
+
+def test_ggttggg_constants(h7):
+    q = h7.query()
+    assert (q["npar"], q["nhel"], q["ncol"], q["ndiag"], q["iden"]) == (7, 128, 120, 1240, 1536.0)
+    assert 0 < q["ngoodhel"] <= 128 and len(h7.good_helicities()) == q["ngoodhel"]
+
+
+def test_ggttggg_mixed_fast_accuracy(h7, card):
+    p = configs.WORKLOADS["ggttggg"].momenta(67)
+    print("[gpu] ggttggg mixed (fast) accuracy n=67", flush=True)
+    ref = oracle.me2(configs.GGTTGGG, p, card, AS)
+    got = run(h7, p)
+    rel = np.abs(got / ref - 1)
+    print(f"  max {rel.max():.3g} p99 {np.quantile(rel, 0.99):.3g} median {np.median(rel):.3g}")
+    assert np.quantile(rel, 0.99) <= MIXED_TOL
+    assert rel.max() <= 1e-3
+
+
+def test_ggttggg_sub_batches_and_edges(h7, card):
+    """Across the 16384-event sub-batch boundary and at ragged sizes, per-event values are bitwise
+    those of smaller calls; a few events on both sides of the boundary against the oracle."""
+    n = 16384 + 700
+    p = configs.WORKLOADS["ggttggg"].momenta(n)
+    print(f"[gpu] ggttggg sub-batches n={n}", flush=True)
+    whole = run(h7, p)
+    assert np.all(np.isfinite(whole)) and np.all(whole > 0)
+    for a, b in [(0, 1), (1, 64), (16380, 16390), (16383, n)]:
+        assert np.array_equal(run(h7, p[a:b]), whole[a:b]), (a, b)
+    idx = np.array([0, 1, 16382, 16383, 16384, 16385, n - 1])
+    ref = oracle.me2(configs.GGTTGGG, p[idx], card, AS)
+    assert np.abs(whole[idx] / ref - 1).max() <= 1e-3
+
+
+def test_ggttggg_full_request_sampled(h7, card):
+    """The largest served request (65536 events) in one call, checked on sampled events."""
+    w = configs.WORKLOADS["ggttggg"]
+    print(f"[gpu] ggttggg full size n={w.nevt}", flush=True)
+    p = w.momenta()
+    got = run(h7, p)
+    assert np.all(np.isfinite(got)) and np.all(got > 0)
+    idx = np.unique(np.concatenate([np.random.default_rng(11).integers(0, w.nevt, 30), [w.nevt - 1]]))
+    ref = oracle.me2(configs.GGTTGGG, p[idx], card, AS)
+    rel = np.abs(got[idx] / ref - 1)
+    print(f"  max {rel.max():.3g} median {np.median(rel):.3g}")
+    assert rel.max() <= 1e-3 and np.median(rel) <= MIXED_TOL

@@ -23,7 +23,7 @@ def mdot(a, b):
     return a[..., 0] * b[..., 0] - (a[..., 1:] * b[..., 1:]).sum(-1)
 
 
-@pytest.mark.parametrize("name", ["eemumu", "ggtt", "ggttg", "ggttgg"])
+@pytest.mark.parametrize("name", ["eemumu", "ggtt", "ggttg", "ggttgg", "ggttggg"])
 def test_rambo_conservation_and_mass_shell(name):
     w = configs.WORKLOADS[name]
     p = w.momenta(4000)

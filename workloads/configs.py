@@ -77,6 +77,8 @@ WORKLOADS = {
     "ggtt": Workload("ggtt", GGTT, 524288, 1000.0, 2),
     "ggttg": Workload("ggttg", GGTTG, 1048576, 1500.0, 3, _cut_gluon_pt, "pT(g) > 20 GeV"),
     "ggttgg": Workload("ggttgg", GGTTGG, 1048576, 2000.0, 4, _cut_gluon_dr, "dR(g,g) > 0.4"),
+    # the served mix's largest process on its own, at the largest request size (no cuts)
+    "ggttggg": Workload("ggttggg", GGTTGGG, 65536, 2000.0, 5),
     # served mix: request sizes log-uniform in [256, 65536], processes uniform over
     # the four gg -> ttbar + n g, Poisson arrivals with mean 200 requests/s
     "served": Workload("served", GGTTGGG, 0, 2000.0, 5,
