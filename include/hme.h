@@ -122,6 +122,9 @@ const char* hme_last_error(void);
  * also applies each request's alpha_s normalisation).  Batches on different
  * slots overlap on the device.  Per-event arithmetic does not depend on the
  * batch, so a request's |M|^2 are bitwise those of hme_compute on it alone.
+ * HME_GGTTGGG is served only at HME_MIXED_FAST (hme_submit returns
+ * HME_E_UNSUPPORTED otherwise); its jamp workspace, for sub-batches of up to 4096
+ * events, takes at most half of each slot, and its requests must fit beside it.
  * The server is thread-safe. */
 
 typedef struct hme_server hme_server;

@@ -246,6 +246,11 @@ int handle_npar(const hme_handle* h) { return h->info.npar; }
 
 bool handle_chunked(const hme_handle* h) { return h->info.nchunk > 0; }
 
+// workspace bytes per event of a sub-batch (0 for a process evaluated in one kernel)
+int64_t handle_ws_bytes_per_event(const hme_handle* h) {
+  return handle_chunked(h) ? (int64_t)h->info.ncol * (int64_t)h->goodhel.size() * 2 * (int64_t)sizeof(float) : 0;
+}
+
 hipError_t launch_for_handle(const hme_handle* h, int64_t nevt_grid, const int64_t* nevt_dev, const double* mom,
                              double* out, double norm, hipStream_t s, void* ws, int64_t ws_events) {
   LaunchArgs a{mom, out, nevt_grid, h->d_goodhel, (int)h->goodhel.size(), h->prm, norm, s,
@@ -274,7 +279,7 @@ int hme_compute(hme_handle* h, double alpha_s, int64_t nevt, const double* momen
   if (hme::handle_chunked(h)) {
     // jamp workspace, allocated and released in stream order
     ws_events = nevt < hme::kChunkSubBatch ? nevt : hme::kChunkSubBatch;
-    const size_t bytes = (size_t)ws_events * h->info.ncol * h->goodhel.size() * 2 * sizeof(float);
+    const size_t bytes = (size_t)ws_events * (size_t)hme::handle_ws_bytes_per_event(h);
     if ((e = hipMallocAsync(&ws, bytes, stream)) != hipSuccess)
       return fail(HME_E_OOM, std::string("hme_compute: workspace: ") + hipGetErrorString(e));
   }

@@ -109,6 +109,17 @@ __global__ void __launch_bounds__(64) hel_kernel(const double* __restrict__ mom,
 // consecutive addresses.  A last kernel reads all jamps of a helicity back, forms the
 // colour sum and reduces over helicities as me2_kernel does.  Single precision only.
 
+// Events in a sub-batch: at most nevt (which sizes the grid); when a captured graph reads
+// the batch's event count from device memory, only those left after the sub-batch's
+// first event e0 (none if the batch ends before it).
+HME_FN int64_t sub_batch_events(int64_t nevt, const int64_t* nevt_dev, int64_t e0) {
+  if (nevt_dev) {
+    const int64_t left = *nevt_dev - e0;
+    if (left < nevt) nevt = left;
+  }
+  return nevt;
+}
+
 // the per-event table in LDS, built by the event's lanes (as in me2_kernel)
 template <class Proc, int LPE>
 HME_FN void build_table(const double (&p)[Proc::npar][4], const ProcParams& prm, int sub, double* tab) {
@@ -118,10 +129,12 @@ HME_FN void build_table(const double (&p)[Proc::npar][4], const ProcParams& prm,
 template <class Proc, class Chunk, int LPE>
 __global__ void __launch_bounds__(256)
     chunk_kernel(const double* __restrict__ mom, cx<float>* __restrict__ ws, int64_t nevt,
-                 const int* __restrict__ goodhel, int ngood, ProcParams prm) {
+                 const int* __restrict__ goodhel, int ngood, ProcParams prm, const int64_t* __restrict__ nevt_dev,
+                 int64_t e0) {
   constexpr int EPW = 64 / LPE, EPB = 256 / LPE;
   __shared__ double table[EPB * Proc::ntab];
   const int lane = threadIdx.x & 63;
+  nevt = sub_batch_events(nevt, nevt_dev, e0);
   if ((int64_t)blockIdx.x * EPB >= nevt) return;  // uniform per block
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t ev = ((int64_t)blockIdx.x * 4 + wib) * EPW + lane / LPE;
@@ -155,9 +168,10 @@ __global__ void __launch_bounds__(256)
 template <class Proc, int LPE>
 __global__ void __launch_bounds__(256)
     colour_kernel(const cx<float>* __restrict__ ws, double* __restrict__ out, int64_t nevt, int ngood,
-                  double norm, int per_hel) {
+                  double norm, int per_hel, const int64_t* __restrict__ nevt_dev, int64_t e0) {
   constexpr int EPW = 64 / LPE, EPB = 256 / LPE;
   const int lane = threadIdx.x & 63;
+  nevt = sub_batch_events(nevt, nevt_dev, e0);
   if ((int64_t)blockIdx.x * EPB >= nevt) return;
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t ev = ((int64_t)blockIdx.x * 4 + wib) * EPW + lane / LPE;
@@ -186,6 +200,8 @@ struct ChunkArgs {
   int ngood;
   ProcParams prm;
   hipStream_t stream;
+  const int64_t* nevt_dev;  // if set: the batch's event count (device), of which this sub-batch
+  int64_t e0;               // starts at event e0
 };
 
 template <class Proc> constexpr int chunk_lpe() { return Proc::nhel >= 64 ? 64 : 32; }
@@ -194,18 +210,19 @@ template <class Proc, class Chunk> hipError_t launch_chunk(const ChunkArgs& a) {
   constexpr int LPE = chunk_lpe<Proc>(), EPB = 256 / LPE;
   const int64_t blocks = (a.nevt + EPB - 1) / EPB;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  chunk_kernel<Proc, Chunk, LPE><<<dim3((unsigned)blocks), dim3(256), 0, a.stream>>>(a.mom, a.ws, a.nevt, a.goodhel,
-                                                                                     a.ngood, a.prm);
+  chunk_kernel<Proc, Chunk, LPE><<<dim3((unsigned)blocks), dim3(256), 0, a.stream>>>(
+      a.mom, a.ws, a.nevt, a.goodhel, a.ngood, a.prm, a.nevt_dev, a.e0);
   return hipGetLastError();
 }
 
 template <class Proc>
 hipError_t launch_colour(const cx<float>* ws, double* out, int64_t nevt, int ngood, double norm, int per_hel,
-                         hipStream_t s) {
+                         const int64_t* nevt_dev, int64_t e0, hipStream_t s) {
   constexpr int LPE = chunk_lpe<Proc>(), EPB = 256 / LPE;
   const int64_t blocks = (nevt + EPB - 1) / EPB;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  colour_kernel<Proc, LPE><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(ws, out, nevt, ngood, norm, per_hel);
+  colour_kernel<Proc, LPE><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(ws, out, nevt, ngood, norm, per_hel,
+                                                                         nevt_dev, e0);
   return hipGetLastError();
 }
 

@@ -11,18 +11,21 @@ static_assert(sizeof(chunks_ggttggg) / sizeof(chunks_ggttggg[0]) == P7::nchunk, 
 
 ProcInfo info_ggttggg() { return make_info<P7>(); }
 
-// all pieces, then the colour sum, for consecutive sub-batches of a.ws_events events
-static hipError_t run_pieces(const double* mom, double* out, int64_t nevt, const int* goodhel, int ngood,
-                             const ProcParams& prm, double norm, int per_hel, cx<float>* ws, int64_t ws_events,
-                             hipStream_t s) {
+// All pieces, then the colour sum, for consecutive sub-batches of ws_events events.  nevt
+// sizes the launches; with nevt_dev set (a captured graph) the kernels take the batch's
+// event count from device memory and sub-batches past its end do nothing.
+static hipError_t run_pieces(const double* mom, double* out, int64_t nevt, const int64_t* nevt_dev,
+                             const int* goodhel, int ngood, const ProcParams& prm, double norm, int per_hel,
+                             cx<float>* ws, int64_t ws_events, hipStream_t s) {
   for (int64_t e0 = 0; e0 < nevt; e0 += ws_events) {
     const int64_t n = nevt - e0 < ws_events ? nevt - e0 : ws_events;
-    const ChunkArgs c{mom + e0 * P7::npar * 4, ws, n, goodhel, ngood, prm, s};
+    const ChunkArgs c{mom + e0 * P7::npar * 4, ws, n, goodhel, ngood, prm, s, nevt_dev, e0};
     for (int k = 0; k < P7::nchunk; ++k) {
       const hipError_t e = chunks_ggttggg[k](c);
       if (e != hipSuccess) return e;
     }
-    const hipError_t e = launch_colour<P7>(ws, out + (per_hel ? e0 * ngood : e0), n, ngood, norm, per_hel, s);
+    const hipError_t e = launch_colour<P7>(ws, out + (per_hel ? e0 * ngood : e0), n, ngood, norm, per_hel,
+                                           nevt_dev, e0, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -30,9 +33,9 @@ static hipError_t run_pieces(const double* mom, double* out, int64_t nevt, const
 
 // single precision only (the library rejects other precisions when the handle is made)
 hipError_t launch_me2_ggttggg(const LaunchArgs& a, int precision) {
-  if (precision != 1 || a.nevt_dev || !a.ws || a.ws_events <= 0) return hipErrorInvalidValue;
-  return run_pieces(a.mom, a.out, a.nevt, a.goodhel, a.ngood, a.prm, a.norm, 0, static_cast<cx<float>*>(a.ws),
-                    a.ws_events, a.stream);
+  if (precision != 1 || !a.ws || a.ws_events <= 0) return hipErrorInvalidValue;
+  return run_pieces(a.mom, a.out, a.nevt, a.nevt_dev, a.goodhel, a.ngood, a.prm, a.norm, 0,
+                    static_cast<cx<float>*>(a.ws), a.ws_events, a.stream);
 }
 
 // |M_h|^2 of every helicity for nev events (set-up only; synchronous, own workspace)
@@ -44,7 +47,7 @@ hipError_t launch_hel_ggttggg(const double* mom, int nev, const ProcParams& prm,
   hipError_t e = hipMalloc(&d_hel, sizeof hel);
   if (e == hipSuccess) e = hipMalloc(&ws, (size_t)nev * P7::ncol * P7::nhel * sizeof(cx<float>));
   if (e == hipSuccess) e = hipMemcpy(d_hel, hel, sizeof hel, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = run_pieces(mom, out, nev, d_hel, P7::nhel, prm, 1.0, 1, ws, nev, s);
+  if (e == hipSuccess) e = run_pieces(mom, out, nev, nullptr, d_hel, P7::nhel, prm, 1.0, 1, ws, nev, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (ws) (void)hipFree(ws);
   if (d_hel) (void)hipFree(d_hel);

@@ -21,6 +21,7 @@
 namespace hme {
 double handle_norm(const hme_handle* h, double alpha_s);
 int handle_npar(const hme_handle* h);
+int64_t handle_ws_bytes_per_event(const hme_handle* h);
 hipError_t launch_for_handle(const hme_handle* h, int64_t nevt_grid, const int64_t* nevt_dev, const double* mom,
                              double* out, double norm, hipStream_t s, void* ws, int64_t ws_events);
 void set_last_error(const std::string& msg);
@@ -28,7 +29,8 @@ void set_last_error(const std::string& msg);
 
 namespace {
 
-constexpr int kNumProcesses = 4;
+constexpr int kNumProcesses = 5;
+constexpr int64_t kMaxSubBatch = 4096;  // events per sub-batch of a process evaluated in pieces
 constexpr int kMaxBatchReq = 64;      // requests per batch
 constexpr int64_t kMinBucket = 256;   // smallest graph size bucket (events)
 
@@ -90,7 +92,9 @@ struct Batch {
 
 struct Slot {
   hipStream_t stream = nullptr;
-  char* d_mem = nullptr;        // slot_bytes: gathered momenta of a batch, then its raw |M|^2
+  // slot_bytes: gathered momenta of a batch, then its raw |M|^2; a process evaluated in
+  // pieces also uses the last ws_bytes as its jamp workspace
+  char* d_mem = nullptr;
   BatchDesc* d_desc = nullptr;  // device copy of the descriptor
   BatchDesc* h_desc = nullptr; // pinned host descriptor
   bool busy = false;
@@ -107,7 +111,8 @@ namespace {
 struct Server : hme_server {
   int device = 0, precision = 0;
   int64_t slot_bytes = 0;
-  hme_handle* handles[kNumProcesses] = {};
+  int64_t ws_bytes = 0, ws_events = 0;  // workspace of the processes evaluated in pieces
+  hme_handle* handles[kNumProcesses] = {};  // NULL: process not served at this precision
   std::vector<Slot> slots;
   std::mutex mu;
   std::condition_variable cv_sched;  // pending work or a freed slot
@@ -120,9 +125,14 @@ struct Server : hme_server {
   std::thread scheduler;
   hme_server_stats stats{};
 
-  // events of `process` one slot holds: momenta (npar * 32 bytes) and |M|^2 (8 bytes) per event
+  // events of `process` one slot holds: momenta (npar * 32 bytes) and |M|^2 (8 bytes) per
+  // event, beside the workspace for a process evaluated in pieces
   int64_t capacity(int process) const {
     const int npar = hme::handle_npar(handles[process]);
+    if (hme::handle_ws_bytes_per_event(handles[process]) > 0) {
+      if (ws_events <= 0) return 0;
+      return (slot_bytes - ws_bytes - 512) / (npar * 32 + 8);
+    }
     return (slot_bytes - 256) / (npar * 32 + 8);
   }
 
@@ -153,9 +163,11 @@ struct Server : hme_server {
       gather_kernel<<<dim3(gx, kMaxBatchReq), dim3(256), 0, sl.stream>>>(sl.d_desc, d_mom, npar);
       e1 = hipGetLastError();
     }
+    const bool pieces = hme::handle_ws_bytes_per_event(handles[process]) > 0;
+    void* d_ws = pieces ? sl.d_mem + (slot_bytes - ws_bytes) : nullptr;
     if (e1 == hipSuccess)
       e1 = hme::launch_for_handle(handles[process], bucket, &sl.d_desc->nevt_total, d_mom, d_out, 1.0, sl.stream,
-                                 nullptr, 0);
+                                 d_ws, pieces ? ws_events : 0);
     if (e1 == hipSuccess) {
       const unsigned sx = (unsigned)std::min<int64_t>(256, std::max<int64_t>(1, bucket / 1024));
       scatter_kernel<<<dim3(sx, kMaxBatchReq), dim3(256), 0, sl.stream>>>(sl.d_desc, d_out);
@@ -303,10 +315,20 @@ int hme_server_create(const hme_sm_card* card, int precision, int device, size_t
   s->slot_bytes = (int64_t)(hbm_budget_bytes / nstreams) & ~int64_t(255);
   for (int p = 0; p < kNumProcesses; ++p) {
     int rc = hme_create(p, card, precision, device, &s->handles[p]);
+    if (rc == HME_E_UNSUPPORTED) continue;  // not served at this precision
     if (rc != HME_OK) {
       for (int q = 0; q < p; ++q) hme_destroy(s->handles[q]);
       delete s;
       return rc;
+    }
+    // the workspace: half the slot at most, whole 64-event groups, 256-byte aligned
+    const int64_t per_event = hme::handle_ws_bytes_per_event(s->handles[p]);
+    if (per_event > 0) {
+      int64_t n = std::min<int64_t>(kMaxSubBatch, s->slot_bytes / 2 / per_event) & ~int64_t(63);
+      if (s->ws_events == 0 || n < s->ws_events) {
+        s->ws_events = n;
+        s->ws_bytes = (n * per_event + 255) & ~int64_t(255);
+      }
     }
   }
   int prev = 0;
@@ -337,8 +359,8 @@ int hme_submit(hme_server* srv, int process, double alpha_s, int64_t nevt, const
                uint64_t* req_id) {
   auto* s = static_cast<Server*>(srv);
   if (!s || !req_id) return srv_fail(HME_E_ARG, "hme_submit: NULL server or req_id");
-  if (process == HME_GGTTGGG) return srv_fail(HME_E_UNSUPPORTED, "hme_submit: process not served");
   if (process < 0 || process >= kNumProcesses) return srv_fail(HME_E_ARG, "hme_submit: unknown process");
+  if (!s->handles[process]) return srv_fail(HME_E_UNSUPPORTED, "hme_submit: process not served at this precision");
   if (nevt < 0) return srv_fail(HME_E_ARG, "hme_submit: nevt < 0");
   if (!(alpha_s > 0)) return srv_fail(HME_E_ARG, "hme_submit: alpha_s must be positive");
   if (nevt > 0 && (!momenta_dev || !me2_dev)) return srv_fail(HME_E_ARG, "hme_submit: NULL momenta or me2");

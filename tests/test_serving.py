@@ -134,3 +134,51 @@ def test_budget_and_wait_errors(gpu_setup):
         first = srv.wait(rid, 0.0)
         if first is None:
             assert srv.wait(rid, -1.0) is not None
+
+
+@pytest.mark.gpu
+def test_served_ggttggg_equals_alone(gpu_setup):
+    """The process evaluated in pieces, served beside another: bitwise equal to hme_compute alone
+    (the server's sub-batches are smaller than the handle's; per-event values do not depend on it)."""
+    torch, card, pools = gpu_setup
+    p7 = torch.from_numpy(configs.WORKLOADS["ggttggg"].momenta(9000)).cuda()
+    rng = np.random.default_rng(3)
+    reqs = []
+    for i in range(12):
+        proc = [hme.GGTTGG, hme.GGTTGGG][i % 2]
+        nevt = int(rng.integers(1, 3000)) if proc == hme.GGTTGG else int(rng.integers(1, 9000 // 2))
+        start = int(rng.integers(0, (6000 if proc == hme.GGTTGG else 9000) - nevt))
+        reqs.append((proc, start, nevt))
+    src = {hme.GGTTGG: pools[hme.GGTTGG], hme.GGTTGGG: p7}
+    alone = []
+    hs = {p: hme.Handle(p, card, hme.MIXED_FAST) for p in src}
+    for proc, start, nevt in reqs:
+        alone.append(hs[proc].compute(src[proc][start:start + nevt].contiguous()))
+    torch.cuda.synchronize()
+    alone = [a.cpu().numpy() for a in alone]
+    for h in hs.values():
+        h.close()
+    print("[gpu] served ggttggg vs alone", flush=True)
+    with hme.Server(card, hme.MIXED_FAST, hbm_budget_bytes=1 << 30, nstreams=2) as srv:
+        for rnd in range(2):
+            outs, ids = [], []
+            for proc, start, nevt in reqs:
+                o = torch.full((nevt,), -1.0, dtype=torch.float64, device="cuda")
+                outs.append(o)
+                ids.append(srv.submit(proc, src[proc][start:start + nevt], o))
+            for rid in ids:
+                assert srv.wait(rid) is not None
+            torch.cuda.synchronize()
+            for k, o in enumerate(outs):
+                assert np.array_equal(o.cpu().numpy(), alone[k]), f"round {rnd} request {k} {reqs[k]}"
+
+
+@pytest.mark.gpu
+def test_ggttggg_not_served_in_fp64(gpu_setup):
+    torch, card, pools = gpu_setup
+    with hme.Server(card, hme.FP64, hbm_budget_bytes=8 << 20, nstreams=1) as srv:
+        p = torch.zeros((4, 7, 4), dtype=torch.float64, device="cuda")
+        o = torch.zeros(4, dtype=torch.float64, device="cuda")
+        with pytest.raises(hme.HmeError) as e:
+            srv.submit(hme.GGTTGGG, p, o)
+        assert e.value.code == hme.HME_E_UNSUPPORTED
