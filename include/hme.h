@@ -74,6 +74,7 @@ typedef struct {
   double iden;             /* averaging and symmetry factor applied to the output */
   double flops_per_event;  /* algorithmic floating-point operations per event (all good helicities) */
   double bytes_per_event;  /* HBM traffic per event: momenta in + |M|^2 out */
+  double workspace_bytes_per_event; /* jamp workspace of a process evaluated in pieces (else 0) */
 } hme_info;
 
 /* Create a handle for `process` on HIP device `device`.  Uploads nothing but a
@@ -88,9 +89,10 @@ int hme_create(int process, const hme_sm_card* card, int precision, int device, 
  * pointers, 8-byte aligned, [nevt][npar][4] and [nevt] doubles.  alpha_s is the
  * strong coupling for this call.  nevt = 0 is a successful no-op; any nevt >= 1
  * is valid (partial wavefronts are masked).  Not thread-safe per handle.
- * HME_GGTTGGG also takes a device workspace of min(nevt, 16384) * 120 * ngoodhel * 8
- * bytes, allocated and released on `hip_stream` in stream order (HME_E_OOM if that
- * fails); larger batches run as consecutive sub-batches of 16384 events. */
+ * HME_GGTTGGG also takes a device workspace of min(nevt, 8192) events times
+ * hme_info.workspace_bytes_per_event (about 2 MB per event), allocated and released on
+ * `hip_stream` in stream order (HME_E_OOM if that fails); larger batches run as
+ * consecutive sub-batches of 8192 events. */
 int hme_compute(hme_handle* h, double alpha_s, int64_t nevt, const double* momenta, double* me2, void* hip_stream);
 
 /* Fill `info` with the handle's process constants. */

@@ -34,7 +34,8 @@ class SmCard(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int) for n in ("process", "precision", "npar", "nhel", "ngoodhel", "ncol", "ndiag",
                                             "namp")] + \
-               [(n, ctypes.c_double) for n in ("iden", "flops_per_event", "bytes_per_event")]
+               [(n, ctypes.c_double) for n in ("iden", "flops_per_event", "bytes_per_event",
+                                               "workspace_bytes_per_event")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

@@ -43,7 +43,7 @@ static const ProcEntry kProcs[] = {
 };
 
 // events per sub-batch of a process evaluated in pieces (workspace ncol * ngood * 8 bytes each)
-constexpr int64_t kChunkSubBatch = 16384;
+constexpr int64_t kChunkSubBatch = 8192;
 constexpr int kNumProcs = sizeof(kProcs) / sizeof(kProcs[0]);
 
 }  // namespace hme
@@ -248,7 +248,7 @@ bool handle_chunked(const hme_handle* h) { return h->info.nchunk > 0; }
 
 // workspace bytes per event of a sub-batch (0 for a process evaluated in one kernel)
 int64_t handle_ws_bytes_per_event(const hme_handle* h) {
-  return handle_chunked(h) ? (int64_t)h->info.ncol * (int64_t)h->goodhel.size() * 2 * (int64_t)sizeof(float) : 0;
+  return handle_chunked(h) ? (int64_t)h->info.nslot * (int64_t)h->goodhel.size() * 2 * (int64_t)sizeof(float) : 0;
 }
 
 hipError_t launch_for_handle(const hme_handle* h, int64_t nevt_grid, const int64_t* nevt_dev, const double* mom,
@@ -306,6 +306,7 @@ int hme_query(const hme_handle* h, hme_info* info) {
   info->iden = h->info.iden;
   info->flops_per_event = info->ngoodhel * h->info.flops_per_hel + h->info.flops_per_event;
   info->bytes_per_event = h->info.npar * 4 * sizeof(double) + sizeof(double);
+  info->workspace_bytes_per_event = (double)hme::handle_ws_bytes_per_event(h);
   return HME_OK;
 }
 

@@ -101,13 +101,15 @@ __global__ void __launch_bounds__(64) hel_kernel(const double* __restrict__ mom,
 //
 // For the largest process one straight-line kernel would not compile in reasonable
 // time, and its 120 jamps would not fit in registers beside the wavefunctions.  The
-// generator then cuts the amplitude schedule into pieces; each piece is a kernel that
-// adds its terms to the jamps of the flows it touches, kept between kernels in a
-// device workspace
-//     ws[event][flow][good helicity]   (cx<float>, events of one sub-batch)
-// so that the LPE lanes of an event, which hold consecutive helicities, touch
-// consecutive addresses.  A last kernel reads all jamps of a helicity back, forms the
-// colour sum and reduces over helicities as me2_kernel does.  Single precision only.
+// generator then cuts the amplitude schedule into pieces, each a kernel.  A piece keeps
+// at most a fixed number of flows in registers; a flow's partial sum leaves its register
+// after its last term in the piece, or earlier when the register is needed, and is
+// written to a slot of its own in a device workspace
+//     ws[event][slot][good helicity]   (cx<float>, events of one sub-batch)
+// so that the LPE lanes of an event, which hold consecutive helicities, write
+// consecutive addresses (plain coalesced stores; no read-modify-write, no atomics).  A
+// last kernel adds up each flow's slots, forms the colour sum and reduces over
+// helicities as me2_kernel does.  Single precision only.
 
 // Events in a sub-batch: at most nevt (which sizes the grid); when a captured graph reads
 // the batch's event count from device memory, only those left after the sub-batch's
@@ -120,14 +122,25 @@ HME_FN int64_t sub_batch_events(int64_t nevt, const int64_t* nevt_dev, int64_t e
   return nevt;
 }
 
+// Where a piece's partial jamps go: slot `slot` of this lane's (event, helicity) column,
+// written once with a plain store (no other code writes it).
+struct WorkspaceSink {
+  cx<float>* base;
+  int64_t stride;  // entries between consecutive slots (the number of good helicities)
+  HME_FN void put(int slot, cx<float> v) const { base[slot * stride] = v; }
+};
+
 // the per-event table in LDS, built by the event's lanes (as in me2_kernel)
 template <class Proc, int LPE>
 HME_FN void build_table(const double (&p)[Proc::npar][4], const ProcParams& prm, int sub, double* tab) {
   for (int j = sub; j < Proc::nitems; j += LPE) Proc::table_entry(p, prm, j, tab);
 }
 
+#ifndef HME_PIECE_WAVES
+#define HME_PIECE_WAVES 1
+#endif
 template <class Proc, class Chunk, int LPE>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, HME_PIECE_WAVES)
     chunk_kernel(const double* __restrict__ mom, cx<float>* __restrict__ ws, int64_t nevt,
                  const int* __restrict__ goodhel, int ngood, ProcParams prm, const int64_t* __restrict__ nevt_dev,
                  int64_t e0) {
@@ -146,20 +159,10 @@ __global__ void __launch_bounds__(256)
   build_table<Proc, LPE>(p, prm, sub, tab);
   __syncthreads();
   if (ev >= nevt) return;  // no barrier follows
-  cx<float>* w = ws + (size_t)ev * Proc::ncol * ngood;
+  cx<float>* w = ws + (size_t)ev * Proc::nslot * ngood;
   for (int k = sub; k < ngood; k += LPE) {
-    cx<float> jamp[Chunk::nw];
-#pragma unroll
-    for (int c = 0; c < Chunk::nw; ++c) jamp[c] = {0.f, 0.f};
-    Chunk::template amplitudes<float>(prm, (unsigned)goodhel[k], (tab_ptr)tab, jamp);
-#pragma unroll
-    for (int c = 0; c < Chunk::nw; ++c) {
-      cx<float>* dst = w + (size_t)Chunk::words[c] * ngood + k;
-      if (Chunk::fresh[c])
-        *dst = jamp[c];
-      else
-        *dst = *dst + jamp[c];
-    }
+    WorkspaceSink sink{w + k, ngood};
+    Chunk::template amplitudes<float>(prm, (unsigned)goodhel[k], (tab_ptr)tab, sink);
   }
 }
 
@@ -177,12 +180,11 @@ __global__ void __launch_bounds__(256)
   const int64_t ev = ((int64_t)blockIdx.x * 4 + wib) * EPW + lane / LPE;
   const int sub = lane % LPE;
   const int64_t evc = ev < nevt ? ev : nevt - 1;
-  const cx<float>* w = ws + (size_t)evc * Proc::ncol * ngood;
+  const cx<float>* w = ws + (size_t)evc * Proc::nslot * ngood;
   double acc = 0.0;
   for (int k = sub; k < ngood; k += LPE) {
     cx<float> jamp[Proc::ncol];
-#pragma unroll
-    for (int c = 0; c < Proc::ncol; ++c) jamp[c] = w[(size_t)c * ngood + k];
+    Proc::template gather<float, float>(w + k, ngood, jamp);
     const double v = (double)Proc::template colour_sum<float>(jamp);
     if (per_hel && ev < nevt) out[(size_t)ev * ngood + k] = v;
     acc += v;
@@ -194,7 +196,7 @@ __global__ void __launch_bounds__(256)
 
 struct ChunkArgs {
   const double* mom;  // momenta of the sub-batch's first event
-  cx<float>* ws;      // workspace, nevt * ncol * ngood entries
+  cx<float>* ws;      // workspace, nevt * nslot * ngood entries
   int64_t nevt;       // events in the sub-batch
   const int* goodhel;
   int ngood;
@@ -247,11 +249,13 @@ struct ProcInfo {
   int npar, nhel, ncol, ndiag, namp, gs_power;
   double iden, colour_denom, flops_per_hel, flops_per_event;
   int nchunk;  // 0: one kernel; otherwise pieces + colour kernel over a jamp workspace
+  int nslot;   // workspace slots per (event, good helicity) of a process in pieces
 };
 
 template <class Proc> ProcInfo make_info() {
   return ProcInfo{Proc::npar, Proc::nhel, Proc::ncol, Proc::ndiag, Proc::namp, Proc::gs_power,
-                  Proc::iden, Proc::colour_denom, Proc::flops_per_hel, Proc::flops_per_event, Proc::nchunk};
+                  Proc::iden, Proc::colour_denom, Proc::flops_per_hel, Proc::flops_per_event, Proc::nchunk,
+                  Proc::nslot};
 }
 
 // lanes per event: the smallest of 4, 16, 32, 64 that holds all good helicities (64 loops over more)

@@ -45,7 +45,7 @@ hipError_t launch_hel_ggttggg(const double* mom, int nev, const ProcParams& prm,
   int* d_hel = nullptr;
   cx<float>* ws = nullptr;
   hipError_t e = hipMalloc(&d_hel, sizeof hel);
-  if (e == hipSuccess) e = hipMalloc(&ws, (size_t)nev * P7::ncol * P7::nhel * sizeof(cx<float>));
+  if (e == hipSuccess) e = hipMalloc(&ws, (size_t)nev * P7::nslot * P7::nhel * sizeof(cx<float>));
   if (e == hipSuccess) e = hipMemcpy(d_hel, hel, sizeof hel, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = run_pieces(mom, out, nev, nullptr, d_hel, P7::nhel, prm, 1.0, 1, ws, nev, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -133,7 +133,7 @@ def prefetch_units(lines, enable, kits: bool = True):
 
 
 def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chunks: int = 0,
-             file_stem: str = ""):
+             file_stem: str = "", jbudget: int = 32):
     """Emit the process header.
 
     budget: number of off-shell wavefunctions kept live at once, for the double and the
@@ -148,7 +148,7 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
     each emitted as its own struct (returned in info["chunk_headers"]) that adds its terms to
     the jamps of the flows it touches; the main header then holds the table and the colour
     sum only.  Used where one straight-line kernel would be too large to compile and to keep
-    its jamps in registers.
+    its jamps in registers.  jbudget: flows a piece accumulates in registers at once.
     """
     if isinstance(budget, int):
         budget = (budget, budget)
@@ -180,11 +180,16 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
     from .diagrams import schedule
     full_order = schedule(g)
 
-    def emit_schedule(budget, order=None, wmap=None):
+    def emit_schedule(budget, order=None, wmap=None, jbudget=None, partials=None):
         """One amplitude schedule under a live-wavefunction budget; returns the body lines.
 
         order: the amplitude terms to evaluate (default: all, in schedule order);
         wmap: colour flow -> index into the jamp array (default: all flows in basis order).
+        jbudget: if set, at most this many flows are accumulated in registers (jr[]); a flow
+        leaves its register after its last term in `order`, or earlier when the register is
+        needed (the flow whose next term is farthest away: Belady's rule, which gives the
+        fewest partial sums), as a partial sum written by sink.put to a slot of its own;
+        `partials` maps each flow to its slots and counts them ("n").
         """
         lines = []
         flops_exec = 0
@@ -275,6 +280,27 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
                 del live[victim]
 
         jamp_terms = 0
+        jslot = {}  # flow -> register slot (jamp budget mode)
+        jfree = list(range(jbudget or 0))[::-1]
+        wtouch = {}
+        for t, ia in enumerate(order):
+            for w in g.amps[ia].colour.terms:
+                wtouch.setdefault(w, []).append(t)
+        nflush = [0]
+
+        def next_touch(w, t):
+            u = wtouch[w]
+            i = bisect.bisect_right(u, t)
+            return u[i] if i < len(u) else 1 << 30
+
+        def flush(w):
+            slot = jslot.pop(w)
+            jfree.append(slot)
+            partials.setdefault(w, []).append(partials["n"])
+            lines.append(f"    sink.put({partials['n']}, jr[{slot}]);")
+            partials["n"] += 1
+            nflush[0] += 1
+
         for t, ia in enumerate(order):
             now[0] = t
             amp = g.amps[ia]
@@ -299,10 +325,28 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
             lines.append(f"  {{  // diagram {amp.diagram + 1}")
             lines.extend(pre)
             lines.append(f"    const cx<T> a = {call};")
-            for w, c in sorted(amp.colour.terms.items(), key=lambda x: wmap[x[0]]):
-                j = wmap[w]
-                lines.append(f"    jamp[{j}] = jamp[{j}] {_coef_code(c * phase, 'a')};")
-                jamp_terms += 1
+            if jbudget:
+                mine = set(amp.colour.terms)
+                for w, c in sorted(amp.colour.terms.items(), key=lambda x: widx[x[0]]):
+                    code = _coef_code(c * phase, 'a')
+                    if w in jslot:
+                        lines.append(f"    jr[{jslot[w]}] = jr[{jslot[w]}] {code};")
+                    else:
+                        if not jfree:
+                            cands = [x for x in jslot if x not in mine]
+                            flush(max(cands, key=lambda x: next_touch(x, t)))
+                        jslot[w] = jfree.pop()
+                        init = code[2:] if code.startswith("+ ") else "-" + code[2:]
+                        lines.append(f"    jr[{jslot[w]}] = {init};")
+                    jamp_terms += 1
+                for w in sorted(jslot, key=lambda x: widx[x]):
+                    if next_touch(w, t) >= 1 << 30:
+                        flush(w)
+            else:
+                for w, c in sorted(amp.colour.terms.items(), key=lambda x: wmap[x[0]]):
+                    j = wmap[w]
+                    lines.append(f"    jamp[{j}] = jamp[{j}] {_coef_code(c * phase, 'a')};")
+                    jamp_terms += 1
             lines.append("  }")
             for x in list(live):
                 if next_use(x, t) >= 1 << 30:
@@ -310,6 +354,9 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
         flops_exec += 2 * jamp_terms
         ext_name = {"ext_v": "vxxxxx", "ext_o": "oxxxxx", "ext_i": "ixxxxx"}
         flops_dag += 2 * jamp_terms + sum(EXT_FLOPS[ext_name[g.nodes[k].kind]] for k in g.nodes if k[0] == "E")
+        assert not jslot
+        if jbudget:
+            return lines, flops_exec, flops_dag, jamp_terms, nflush[0]
         return lines, flops_exec, flops_dag, jamp_terms
 
     if chunks:
@@ -318,16 +365,13 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
         size = (len(full_order) + K - 1) // K
         pieces = [full_order[c * size:(c + 1) * size] for c in range(K)]
         chunk_out = []
-        seen_words = set()
-        flops_dag_total = 0
+        partials = {"n": 0}
         for c, piece in enumerate(pieces):
             words = sorted({w for i in piece for w in g.amps[i].colour.terms}, key=lambda w: widx[w])
-            wm = {w: j for j, w in enumerate(words)}
-            fresh = [w not in seen_words for w in words]
-            seen_words |= set(words)
-            lines_c, fexec_c, fdag_c, jt_c = emit_schedule(budget[1], piece, wm)
-            chunk_out.append((words, fresh, lines_c, fexec_c, fdag_c, jt_c))
-        assert len(seen_words) == ncol
+            lines_c, fexec_c, fdag_c, jt_c, nfl = emit_schedule(budget[1], piece, None, jbudget, partials)
+            chunk_out.append((words, nfl, lines_c, fexec_c, fdag_c, jt_c))
+        assert set(partials) - {"n"} == set(basis)
+        nslot = partials["n"]
         lines_d = lines_f = []
         flops_exec_d = flops_exec_f = sum(x[3] for x in chunk_out)
         # a wavefunction recomputed by several chunks counts once in the DAG figure
@@ -354,7 +398,7 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
     body_d = finish(lines_d, prefetch[0])
     body_f = finish(lines_f, prefetch[1])
     chunk_headers = []
-    for c, (words, fresh, lines_c, fexec_c, fdag_c, jt_c) in enumerate(chunk_out if chunks else []):
+    for c, (words, nfl, lines_c, fexec_c, fdag_c, jt_c) in enumerate(chunk_out if chunks else []):
         body_c = finish(lines_c, prefetch[1])
         chunk_headers.append(f"""// Generated by paper_2507_21039_amd.gen for {label}, piece {c} of {len(chunk_out)}.  Do not edit.
 // {len(pieces[c])} of the {len(g.amps)} amplitude terms, adding to {len(words)} of the {ncol} colour flows.
@@ -365,17 +409,19 @@ namespace hme {{
 
 struct {name}_c{c} {{
   using Base = {name};
-  static constexpr int nw = {len(words)};  // colour flows this piece adds to
-  static constexpr int words[{len(words)}] = {{{", ".join(str(widx[w]) for w in words)}}};
-  // 1 where no earlier piece adds to the flow (its workspace entry is written, not updated)
-  static constexpr int fresh[{len(words)}] = {{{", ".join(str(int(f)) for f in fresh)}}};
+  static constexpr int nw = {len(words)};       // colour flows this piece adds to
+  static constexpr int nflush = {nfl};  // partial jamps it hands to the sink
+  static constexpr int jbudget = {jbudget};  // flows accumulated in registers at once
   static constexpr double flops_per_hel_executed = {fexec_c};
 
-  // this piece's contributions to the jamps words[] of one helicity (jamp[] zeroed by the caller)
-  template <class T>
-  HME_FN static void amplitudes(const ProcParams& prm, unsigned h, tab_ptr tab, cx<T> (&jamp)[{len(words)}]) {{
+  // This piece's terms of the jamps of one helicity.  Each partial sum of a flow leaves
+  // through sink.put(slot, value), to a workspace slot no other code writes; the colour
+  // kernel adds up the slots of every flow (Base::gather).
+  template <class T, class Sink>
+  HME_FN static void amplitudes(const ProcParams& prm, unsigned h, tab_ptr tab, Sink& sink) {{
     auto hel = [h](int k) {{ return (h >> ({npar - 1} - k) & 1u) ? 1 : -1; }};
     const T mT = T(prm.mT);
+    cx<T> jr[{jbudget}];
 {body_c}
   }}
 }};
@@ -407,13 +453,26 @@ struct {name}_c{c} {{
         cs_flops += 4 * len(terms) + 4
 
     nitems = nq + nd + npar
+    gather_code = ""
     if chunks:
+        gl_lines = []
+        for i, w in enumerate(basis):
+            terms = " + ".join(f"cast<T>(col[{sl} * stride])" for sl in sorted(partials[w]))
+            gl_lines.append(f"    jamp[{i}] = {terms};")
+        gather_code = (
+            "  // the jamps of one helicity from the workspace column `col` (slot s at col[s * stride]):\n"
+            "  // each flow is the sum of its partial slots, added in slot order\n"
+            "  template <class T, class S>\n"
+            f"  HME_FN static void gather(const cx<S>* col, int64_t stride, cx<T> (&jamp)[{ncol}]) {{\n"
+            + "\n".join(gl_lines) + "\n  }\n\n")
         amp_section = (f"  // the amplitude terms are split into {len(chunk_out)} contiguous pieces of the schedule\n"
                        f"  // ({name}_c0 .. {name}_c{len(chunk_out) - 1}); each runs as its own kernel and adds\n"
                        f"  // its terms to the jamps kept in a device workspace between kernels\n"
-                       f"  static constexpr int nchunk = {len(chunk_out)};\n\n")
+                       f"  static constexpr int nchunk = {len(chunk_out)};\n"
+                       f"  static constexpr int nslot = {nslot};  // partial-sum slots per helicity\n\n"
+                       + gather_code)
     else:
-        amp_section = f"""  static constexpr int nchunk = 0;  // one kernel evaluates every amplitude term
+        amp_section = f"""  static constexpr int nchunk = 0, nslot = 0;  // one kernel evaluates every amplitude term
 
   // jamps of one helicity (jamp[] must be zeroed by the caller); the schedule depends on the
   // arithmetic type (budget {budget[0]} / prefetch "{prefetch[0]}" for double, {budget[1]} / "{prefetch[1]}" for float)
@@ -522,7 +581,8 @@ struct {name} {{
                 flops_per_hel_executed_f32=flops_exec_f + cs_flops,
                 flops_colour=cs_flops, flops_table=flops_table, colour_denom=D, numerators=N,
                 jamp_terms=jamp_terms, budget=list(budget), prefetch=list(prefetch), ntab=ntab,
-                nchunk=len(chunk_headers), chunk_headers=chunk_headers)
+                nchunk=len(chunk_headers), nslot=nslot if chunks else 0, jbudget=jbudget if chunks else 0,
+                chunk_headers=chunk_headers)
     return hdr, info
 
 
@@ -554,7 +614,7 @@ struct {name} {{
   static constexpr int ncol = 1;
   static constexpr int ndiag = 2;
   static constexpr int namp = 2;
-  static constexpr int nchunk = 0;
+  static constexpr int nchunk = 0, nslot = 0;
   static constexpr int gs_power = 0;
   static constexpr double iden = 4.0;  // average over the initial helicities
   static constexpr double colour_denom = 1.0;

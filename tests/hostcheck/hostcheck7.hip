@@ -1,7 +1,8 @@
 // Test-only: evaluates the generated g g -> t tbar g g g pieces on the host CPU (all
-// helicities, no filter), adding each piece's jamps into the 120 flows exactly as the
-// piece kernels do through their workspace, so the split can be checked against the
-// oracle without a GPU.  The library never uses this.
+// helicities, no filter): the pieces write their partial jamps to slots, the generated
+// gather adds them up per flow, as the piece and colour kernels do through their
+// workspace, so the split can be checked against the oracle without a GPU.  The
+// library never uses this.
 #include <cstdint>
 #include <string>
 
@@ -23,12 +24,20 @@ namespace {
 using P = hme::P_ggttggg;
 static_assert(P::nchunk == 12, "update the piece list");
 
+// the pieces' partial jamps, one slot each, for one helicity; every slot written once
+template <class T> struct SlotSink {
+  hme::cx<T>* slots;
+  bool* written;
+  void put(int slot, hme::cx<T> v) {
+    if (slot < 0 || slot >= P::nslot || written[slot]) throw "slot out of range or written twice";
+    written[slot] = true;
+    slots[slot] = v;
+  }
+};
+
 template <class C, class T>
-void add_piece(const hme::ProcParams& prm, unsigned h, hme::tab_ptr tab, hme::cx<T> (&jamp)[P::ncol]) {
-  hme::cx<T> part[C::nw];
-  for (auto& j : part) j = {T(0), T(0)};
-  C::template amplitudes<T>(prm, h, tab, part);
-  for (int c = 0; c < C::nw; ++c) jamp[C::words[c]] = C::fresh[c] ? part[c] : jamp[C::words[c]] + part[c];
+void add_piece(const hme::ProcParams& prm, unsigned h, hme::tab_ptr tab, SlotSink<T>& sink) {
+  C::template amplitudes<T>(prm, h, tab, sink);
 }
 
 template <class T>
@@ -44,22 +53,27 @@ void run(const hme::ProcParams& prm, double alpha_s, int64_t nevt, const double*
     for (int j = 0; j < P::nitems; ++j) P::table_entry(p, prm, j, tab);
     double acc = 0;
     for (int h = 0; h < P::nhel; ++h) {
-      hme::cx<T> jamp[P::ncol];
-      // poison: every flow must be written by its first piece before it is read
-      for (auto& j : jamp) j = {T(1e30), T(1e30)};
+      static hme::cx<T> slots[P::nslot];
+      static bool written[P::nslot];
+      for (bool& x : written) x = false;
+      SlotSink<T> sink{slots, written};
       const auto t = (hme::tab_ptr)tab;
-      add_piece<hme::P_ggttggg_c0, T>(prm, h, t, jamp);
-      add_piece<hme::P_ggttggg_c1, T>(prm, h, t, jamp);
-      add_piece<hme::P_ggttggg_c2, T>(prm, h, t, jamp);
-      add_piece<hme::P_ggttggg_c3, T>(prm, h, t, jamp);
-      add_piece<hme::P_ggttggg_c4, T>(prm, h, t, jamp);
-      add_piece<hme::P_ggttggg_c5, T>(prm, h, t, jamp);
-      add_piece<hme::P_ggttggg_c6, T>(prm, h, t, jamp);
-      add_piece<hme::P_ggttggg_c7, T>(prm, h, t, jamp);
-      add_piece<hme::P_ggttggg_c8, T>(prm, h, t, jamp);
-      add_piece<hme::P_ggttggg_c9, T>(prm, h, t, jamp);
-      add_piece<hme::P_ggttggg_c10, T>(prm, h, t, jamp);
-      add_piece<hme::P_ggttggg_c11, T>(prm, h, t, jamp);
+      add_piece<hme::P_ggttggg_c0, T>(prm, h, t, sink);
+      add_piece<hme::P_ggttggg_c1, T>(prm, h, t, sink);
+      add_piece<hme::P_ggttggg_c2, T>(prm, h, t, sink);
+      add_piece<hme::P_ggttggg_c3, T>(prm, h, t, sink);
+      add_piece<hme::P_ggttggg_c4, T>(prm, h, t, sink);
+      add_piece<hme::P_ggttggg_c5, T>(prm, h, t, sink);
+      add_piece<hme::P_ggttggg_c6, T>(prm, h, t, sink);
+      add_piece<hme::P_ggttggg_c7, T>(prm, h, t, sink);
+      add_piece<hme::P_ggttggg_c8, T>(prm, h, t, sink);
+      add_piece<hme::P_ggttggg_c9, T>(prm, h, t, sink);
+      add_piece<hme::P_ggttggg_c10, T>(prm, h, t, sink);
+      add_piece<hme::P_ggttggg_c11, T>(prm, h, t, sink);
+      for (bool x : written)
+        if (!x) throw "slot never written";
+      hme::cx<T> jamp[P::ncol];
+      P::template gather<T, T>(slots, 1, jamp);
       acc += (double)P::template colour_sum<T>(jamp) * norm;
     }
     out[e] = acc;
@@ -73,9 +87,13 @@ extern "C" int hostcheck7_me2(int precision, const double* card, double alpha_s,
   hme::ProcParams prm;
   std::string why;
   if (!hme::derive_params(c, prm, why)) return -1;
-  if (precision == 1)
-    run<float>(prm, alpha_s, nevt, mom, out);
-  else
-    run<double>(prm, alpha_s, nevt, mom, out);
+  try {
+    if (precision == 1)
+      run<float>(prm, alpha_s, nevt, mom, out);
+    else
+      run<double>(prm, alpha_s, nevt, mom, out);
+  } catch (const char*) {
+    return -2;
+  }
   return 0;
 }

@@ -112,23 +112,27 @@ def hostlib7():
 
 
 def test_pieces_cover_every_term_once():
-    """The split of g g -> t tbar g g g: every amplitude term in exactly one piece, every flow
-    written first by exactly one piece."""
+    """The split of g g -> t tbar g g g: every amplitude term in exactly one piece; every
+    workspace slot written by exactly one statement and gathered into exactly one flow."""
     import json
-    info = json.load(open(os.path.join(HERE, "..", "paper_2507_21039_amd", "csrc", "procs", "processes.json")))
-    assert info["ggttggg"]["nchunk"] >= 2 and info["ggttggg"]["ncol"] == 120
     import re
     procs = os.path.join(HERE, "..", "paper_2507_21039_amd", "csrc", "procs")
-    first = []
+    info = json.load(open(os.path.join(procs, "processes.json")))["ggttggg"]
+    assert info["nchunk"] >= 2 and info["ncol"] == 120
     nterms = 0
-    for c in range(info["ggttggg"]["nchunk"]):
+    puts = []
+    for c in range(info["nchunk"]):
         text = open(os.path.join(procs, f"ggttggg_c{c}.h")).read()
         nterms += int(re.search(r"// (\d+) of the 1890 amplitude terms", text).group(1))
-        words = [int(x) for x in re.search(r"words\[\d+\] = \{([^}]*)\}", text).group(1).split(",")]
-        fresh = [int(x) for x in re.search(r"fresh\[\d+\] = \{([^}]*)\}", text).group(1).split(",")]
-        first += [w for w, f in zip(words, fresh) if f]
+        puts += [int(x) for x in re.findall(r"sink\.put\((\d+),", text)]
     assert nterms == 1890
-    assert sorted(first) == list(range(120))
+    assert sorted(puts) == list(range(info["nslot"]))
+    main = open(os.path.join(procs, "ggttggg.h")).read()
+    gathered = {}
+    for flow, rhs in re.findall(r"jamp\[(\d+)\] = (cast<T>\(col.*);", main):
+        gathered[int(flow)] = [int(x) for x in re.findall(r"col\[(\d+) \* stride\]", rhs)]
+    assert sorted(gathered) == list(range(120))
+    assert sorted(x for v in gathered.values() for x in v) == list(range(info["nslot"]))
 
 
 def test_generated_pieces_on_host_match_oracle(hostlib7, card):

@@ -254,6 +254,7 @@ def test_ggttggg_constants(h7):
     q = h7.query()
     assert (q["npar"], q["nhel"], q["ncol"], q["ndiag"], q["iden"]) == (7, 128, 120, 1240, 1536.0)
     assert 0 < q["ngoodhel"] <= 128 and len(h7.good_helicities()) == q["ngoodhel"]
+    assert q["workspace_bytes_per_event"] > 120 * q["ngoodhel"] * 8
 
 
 def test_ggttggg_mixed_fast_accuracy(h7, card):
@@ -268,16 +269,16 @@ def test_ggttggg_mixed_fast_accuracy(h7, card):
 
 
 def test_ggttggg_sub_batches_and_edges(h7, card):
-    """Across the 16384-event sub-batch boundary and at ragged sizes, per-event values are bitwise
+    """Across the 8192-event sub-batch boundary and at ragged sizes, per-event values are bitwise
     those of smaller calls; a few events on both sides of the boundary against the oracle."""
-    n = 16384 + 700
+    n = 8192 + 700
     p = configs.WORKLOADS["ggttggg"].momenta(n)
     print(f"[gpu] ggttggg sub-batches n={n}", flush=True)
     whole = run(h7, p)
     assert np.all(np.isfinite(whole)) and np.all(whole > 0)
-    for a, b in [(0, 1), (1, 64), (16380, 16390), (16383, n)]:
+    for a, b in [(0, 1), (1, 64), (8188, 8198), (8191, n)]:
         assert np.array_equal(run(h7, p[a:b]), whole[a:b]), (a, b)
-    idx = np.array([0, 1, 16382, 16383, 16384, 16385, n - 1])
+    idx = np.array([0, 1, 8190, 8191, 8192, 8193, n - 1])
     ref = oracle.me2(configs.GGTTGGG, p[idx], card, AS)
     assert np.abs(whole[idx] / ref - 1).max() <= 1e-3
 
