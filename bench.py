@@ -27,8 +27,8 @@ PEAK_HBM = 8.0e12
 # (profiles/me2_ggttgg_1M_traffic.md): FETCH_SIZE and WRITE_SIZE in KiB, each scaled by what the
 # counter reads for a plain 256 MiB device copy.  Valid only for the kernel sources it was taken
 # on (sha256 prefix of me2_kernels.h + helas.h + procs/ggttgg.h); otherwise traffic is null.
-TRAFFIC = {"source_sha": "bb7d57f0ca3644f3", "nevt": 1048576,
-           "fetch_kib": 198802.1875, "write_kib": 8192.0, "fetch_factor": 262144 / 131095.0625, "write_factor": 1.0}
+TRAFFIC = {"source_sha": "25e77d958b73d7b2", "nevt": 1048576,
+           "fetch_kib": 198801.75, "write_kib": 8192.0, "fetch_factor": 262144 / 131095.8125, "write_factor": 1.0}
 
 
 def kernel_source_sha() -> str:
@@ -87,7 +87,36 @@ def cpu_baseline(proc, p, gpu_out, card, target_s=12.0):
                 max_rel_diff_vs_gpu=float(rel.max()))
 
 
-def served_leg(card, precision, nwarm=200, ntimed=3000, budget=256 << 20, nstreams=4):
+def ggttggg_leg(card, steps=3, warmup=1):
+    """gg -> ttbar ggg alone (the served mix's largest process): 65536 RAMBO events at 2 TeV, seed 5,
+    MIXED_FAST (the only precision it is built for), timed like the main workload."""
+    import torch
+
+    import oracle
+    import paper_2507_21039_amd as hme
+    from workloads import configs
+    w = configs.WORKLOADS["ggttggg"]
+    p = w.momenta()
+    mom = torch.from_numpy(p).cuda()
+    out = torch.empty(w.nevt, dtype=torch.float64, device="cuda")
+    with hme.Handle(hme.GGTTGGG, card, hme.MIXED_FAST) as h:
+        info = h.query()
+        gpu_s, wall_s = time_steps(h, mom, out, steps, warmup)
+    got = out.cpu().numpy()
+    idx = np.linspace(0, w.nevt - 1, 16).astype(int)
+    ref = oracle.me2(configs.GGTTGGG, p[idx], card)
+    per = gpu_s / steps
+    tflops = info["flops_per_event"] * w.nevt / per / 1e12
+    return {"value": w.nevt * steps / gpu_s, "unit": "events/s", "ms_per_step": per * 1e3, "steps": steps,
+            "workload": f"gg->ttbar ggg, {w.nevt} RAMBO events at sqrt(s)=2 TeV, no cuts, seed 5",
+            "dtype": "f32 vertices/propagators/jamps/colour, f64 externals and sums",
+            "diagrams": 1240, "helicities": 128, "good_helicities": info["ngoodhel"], "colour_flows": 120,
+            "achieved_tflops": tflops, "frac_of_valu_peak": tflops * 1e12 / PEAK_FP32_VALU_UNPACKED,
+            "max_rel_diff_vs_oracle_16_events": float(np.max(np.abs(got[idx] / ref - 1))),
+            "workspace_bytes_per_event": info["workspace_bytes_per_event"]}
+
+
+def served_leg(card, precision, nwarm=200, ntimed=3000, budget=32 << 30, nstreams=4):
     """Poisson request stream (200 requests/s, sizes log-uniform in 256..65536) through the server.
 
     Latency is measured inside the library from hme_submit to the end of the request's batch
@@ -99,7 +128,7 @@ def served_leg(card, precision, nwarm=200, ntimed=3000, budget=256 << 20, nstrea
 
     import paper_2507_21039_amd as hme
     from workloads import configs
-    procs_avail = [configs.GGTT, configs.GGTTG, configs.GGTTGG]
+    procs_avail = [configs.GGTT, configs.GGTTG, configs.GGTTGG, configs.GGTTGGG]
     arrival, procs, nevt, _ = configs.served_requests(nwarm + ntimed, processes=procs_avail)
     w = configs.WORKLOADS["served"]
     pools = {}
@@ -141,8 +170,9 @@ def served_leg(card, precision, nwarm=200, ntimed=3000, budget=256 << 20, nstrea
             "offered_events_per_s": float(nevt[nwarm:].sum() / span), "offered_requests_per_s": float(ntimed / span),
             "wall_s": wall, "batches": int(st["batches"]), "graphs": int(st["graphs"]),
             "precision": hme.PRECISION_NAMES[precision], "hbm_budget_bytes": budget, "streams": nstreams,
-            "processes": "gg->ttbar, gg->ttbar g, gg->ttbar gg (uniform)",
-            "note": "gg->ttbar ggg is not in this build; its share of the mix is spread over the other three"}
+            "processes": "gg->ttbar, gg->ttbar g, gg->ttbar gg, gg->ttbar ggg (uniform)",
+            "offered_events_per_s_by_process": {
+                hme.PROCESS_NAMES[q]: float(nevt[nwarm:][procs[nwarm:] == q].sum() / span) for q in procs_avail}}
 
 
 def main():
@@ -153,6 +183,7 @@ def main():
     ap.add_argument("--nevt", type=int, default=None, help="override the batch size (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-ggttggg", action="store_true")
     ap.add_argument("--pmc", action="store_true",
                     help="counter-collection mode: one FP64 launch, then a plain 256 MiB device copy "
                          "(known traffic, for calibrating FETCH_SIZE / WRITE_SIZE); no JSON line")
@@ -229,8 +260,13 @@ def main():
                    "p99_rel_diff_vs_fp64": float(np.quantile(np.abs(results[name]["out"] / f64["out"] - 1), 0.99))}
             for name, dt in (("mixed_fast", "f32 vertices/propagators/jamps/colour, f64 externals and sums"),
                              ("mixed_paper", "f64 amplitudes and jamps, f32 colour algebra, f64 sums"))},
+        "ggttggg": None,
         "served": None,
     }
+    if not args.no_ggttggg:
+        log("[bench] gg->ttbar ggg (mixed fast)")
+        line["ggttggg"] = ggttggg_leg(card)
+        log(f"[bench] gg->ttbar ggg: {line['ggttggg']['value']:.4g} events/s")
     if not args.no_served:
         log("[bench] served mix (Poisson, 200 requests/s)")
         line["served"] = served_leg(card, hme.MIXED_FAST)
