@@ -61,7 +61,7 @@ def build(verbose: bool = False, jobs: int | None = None, force: bool = True) ->
     from .gen.__main__ import PROCESSES, generate
     infos = generate(os.path.join(CSRC, "procs"))
     for p, n in PIECES.items():
-        if infos[p]["nchunk"] != n or PROCESSES[p][3] != n:
+        if infos[p]["nchunk"] != n or PROCESSES[p]["pieces"] != n:
             raise RuntimeError(f"{p}: generator makes {infos[p]['nchunk']} pieces, build expects {n}")
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(len(SOURCES), max(1, len(os.sched_getaffinity(0))))

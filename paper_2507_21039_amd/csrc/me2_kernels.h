@@ -136,8 +136,11 @@ HME_FN void build_table(const double (&p)[Proc::npar][4], const ProcParams& prm,
   for (int j = sub; j < Proc::nitems; j += LPE) Proc::table_entry(p, prm, j, tab);
 }
 
+// Pieces are compiled for 2 waves per SIMD (at most 256 VGPRs): the generator's budgets keep
+// them within it or a few registers above, which the compiler then spills; one wave per SIMD
+// with AGPRs costs far more (measured: 1.1-1.3 ms against 0.63-0.8 ms per 8,192 events).
 #ifndef HME_PIECE_WAVES
-#define HME_PIECE_WAVES 1
+#define HME_PIECE_WAVES 2
 #endif
 template <class Proc, class Chunk, int LPE>
 __global__ void __launch_bounds__(256, HME_PIECE_WAVES)

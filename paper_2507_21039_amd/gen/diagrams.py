@@ -337,3 +337,54 @@ def schedule(g: Graph) -> list:
         done |= nodes_of[i]
         live = {k for k in (live | nodes_of[i]) if pending[k] > 0}
     return order
+
+
+def schedule_cached(g: Graph, node_cost: dict, cache: int, flow_regs: int = 0, flow_cost: float = 0.0) -> list:
+    """Order the amplitude terms for a kernel that keeps only `cache` off-shell wavefunctions.
+
+    Greedy: repeatedly take the amplitude term whose evaluation is cheapest given what an
+    LRU model of the registers holds: the cost of computing every wavefunction of its
+    closure that is not held (node_cost[kind]), plus flow_cost for every colour flow it
+    adds to that is not among the `flow_regs` most recently used flows (a new partial sum
+    when jamps are accumulated in a bounded set of registers).  The emitter then evicts
+    with Belady's rule on the order chosen here.  Returns indices into g.amps.
+    """
+    from collections import OrderedDict
+    closures = []
+    for a in g.amps:
+        s, stack = set(), list(a.args)
+        while stack:
+            k = stack.pop()
+            if k in s or k[0] == "E":
+                continue
+            s.add(k)
+            stack.extend(g.nodes[k].args)
+        closures.append(s)
+    cost = {k: node_cost[n.kind] for k, n in g.nodes.items() if k[0] != "E"}
+    flows = [set(a.colour.terms) for a in g.amps]
+    held, regs = OrderedDict(), OrderedDict()
+    remaining = set(range(len(g.amps)))
+    order = []
+    while remaining:
+        best = None
+        for i in remaining:
+            c = sum(cost[k] for k in closures[i] if k not in held)
+            if flow_regs:
+                c += flow_cost * sum(1 for w in flows[i] if w not in regs)
+            if best is None or (c, i) < best:
+                best = (c, i)
+        i = best[1]
+        order.append(i)
+        remaining.discard(i)
+        for k in closures[i]:
+            held[k] = True
+            held.move_to_end(k)
+        while len(held) > cache:
+            held.popitem(last=False)
+        if flow_regs:
+            for w in flows[i]:
+                regs[w] = True
+                regs.move_to_end(w)
+            while len(regs) > flow_regs:
+                regs.popitem(last=False)
+    return order

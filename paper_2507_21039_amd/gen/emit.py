@@ -133,7 +133,7 @@ def prefetch_units(lines, enable, kits: bool = True):
 
 
 def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chunks: int = 0,
-             file_stem: str = "", jbudget: int = 32):
+             file_stem: str = "", jbudget: int = 32, order=None):
     """Emit the process header.
 
     budget: number of off-shell wavefunctions kept live at once, for the double and the
@@ -144,6 +144,9 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
     denominators read one unit ahead) or "all" (kits too).  The defaults are the fastest
     measured on MI355X for g g -> t tbar g g: budget 4 without prefetch keeps the FP64
     kernel at 2 waves per SIMD; FP32 gains more from hiding LDS latency.
+    order: the amplitude order, either one for both precisions or a pair (double, float); each
+    is None (diagrams.schedule), a list of amplitude indices, or {"cache": n, "flow_cost": c}
+    for diagrams.schedule_cached with that LRU model size and cost of a new partial jamp.
     chunks: if nonzero, cut the single-precision schedule into that many contiguous pieces,
     each emitted as its own struct (returned in info["chunk_headers"]) that adds its terms to
     the jamps of the flows it touches; the main header then holds the table and the colour
@@ -177,8 +180,21 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
             didx[mask] = (len(didx), massive)
         return f"dv<T>(tab, DOFF + {didx[mask][0]})"
 
-    from .diagrams import schedule
-    full_order = schedule(g)
+    from .diagrams import schedule, schedule_cached
+    node_cost = {kind: FLOPS[NODE_FLOPS[kind]] for kind in NODE_FLOPS}
+
+    def pick_order(spec):
+        if spec is None:
+            return schedule(g)
+        if isinstance(spec, dict):  # cache-aware schedule: LRU model size, cost of a new partial sum
+            fc = spec.get("flow_cost", 0.0)
+            return schedule_cached(g, node_cost, spec["cache"], jbudget if fc else 0, fc)
+        return list(spec)
+
+    if not (isinstance(order, tuple) and len(order) == 2 and all(x is None or isinstance(x, dict) for x in order)):
+        order = (order, order)
+    order_d, order_f = pick_order(order[0]), pick_order(order[1])
+    full_order = order_f
 
     def emit_schedule(budget, order=None, wmap=None, jbudget=None, partials=None):
         """One amplitude schedule under a live-wavefunction budget; returns the body lines.
@@ -378,8 +394,8 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
         flops_dag = emit_schedule(budget[1])[2]
         jamp_terms = sum(x[5] for x in chunk_out)
     else:
-        lines_d, flops_exec_d, flops_dag, jamp_terms = emit_schedule(budget[0])
-        lines_f, flops_exec_f, _, _ = emit_schedule(budget[1])
+        lines_d, flops_exec_d, flops_dag, jamp_terms = emit_schedule(budget[0], order_d)
+        lines_f, flops_exec_f, _, _ = emit_schedule(budget[1], order_f)
 
     nq, nd = len(qidx), len(didx)
     ext = [k for k in range(npar)]
