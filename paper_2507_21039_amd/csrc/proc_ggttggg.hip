@@ -11,6 +11,9 @@ static_assert(sizeof(chunks_ggttggg) / sizeof(chunks_ggttggg[0]) == P7::nchunk, 
 
 ProcInfo info_ggttggg() { return make_info<P7>(); }
 
+// the 120 x 120 colour sum on the matrix cores (bf16 splits, FP32 accumulation)
+constexpr int kColourOnMatrixCores = 1;
+
 // All pieces, then the colour sum, for consecutive sub-batches of ws_events events.  nevt
 // sizes the launches; with nevt_dev set (a captured graph) the kernels take the batch's
 // event count from device memory and sub-batches past its end do nothing.
@@ -25,7 +28,7 @@ static hipError_t run_pieces(const double* mom, double* out, int64_t nevt, const
       if (e != hipSuccess) return e;
     }
     const hipError_t e = launch_colour<P7>(ws, out + (per_hel ? e0 * ngood : e0), n, ngood, norm, per_hel,
-                                           nevt_dev, e0, s);
+                                           nevt_dev, e0, s, kColourOnMatrixCores);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

@@ -469,6 +469,8 @@ struct {name}_c{c} {{
         cs_flops += 4 * len(terms) + 4
 
     nitems = nq + nd + npar
+    numer_list = ", ".join(str(N[i][j]) for i in range(ncol) for j in range(ncol))
+    assert all(abs(N[i][j]) < 32768 for i in range(ncol) for j in range(ncol))
     gather_code = ""
     if chunks:
         gl_lines = []
@@ -582,7 +584,10 @@ struct {name} {{
     }}
   }}
 
-{amp_section}  // sum over colour flows of conj(jamp) C jamp times colour_denom
+{amp_section}  // the colour matrix times colour_denom (integer numerators, row-major, symmetric)
+  static constexpr short numer[{ncol * ncol}] = {{{numer_list}}};
+
+  // sum over colour flows of conj(jamp) C jamp times colour_denom
   template <class T> HME_FN static T colour_sum(const cx<T> (&jamp)[{ncol}]) {{
     T s = 0;
 {chr(10).join(cs)}
