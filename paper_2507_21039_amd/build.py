@@ -29,10 +29,10 @@ DEPS = {
     "hme.cpp": _KERNEL_DEPS + ["params.h", "../../include/hme.h"],
     "server.hip": ["../../include/hme.h"],
     **{f"proc_{p}.hip": _KERNEL_DEPS + [f"procs/{p}.h"] for p in _PROCS},
-    **{f"procs/{p}_c{c}.hip": _KERNEL_DEPS + [f"procs/{p}.h", f"procs/{p}_c{c}.h"]
+    **{f"procs/{p}_c{c}.hip": _KERNEL_DEPS + ["piece_kernels.h", f"procs/{p}.h", f"procs/{p}_c{c}.h"]
        for p, n in PIECES.items() for c in range(n)},
 }
-DEPS["proc_ggttggg.hip"] = DEPS["proc_ggttggg.hip"] + ["procs/ggttggg_chunks.h"]
+DEPS["proc_ggttggg.hip"] = DEPS["proc_ggttggg.hip"] + ["piece_kernels.h", "procs/ggttggg_chunks.h"]
 
 
 def hipcc() -> str:

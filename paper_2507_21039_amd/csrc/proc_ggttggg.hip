@@ -1,6 +1,6 @@
 // g g -> t tbar g g g: the helicity filter, the colour kernel and the sequence of
 // piece kernels (each piece in its own generated translation unit).
-#include "me2_kernels.h"
+#include "piece_kernels.h"
 #include "procs/ggttggg.h"
 #include "procs/ggttggg_chunks.h"
 

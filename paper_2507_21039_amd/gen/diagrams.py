@@ -361,7 +361,11 @@ def schedule_cached(g: Graph, node_cost: dict, cache: int, flow_regs: int = 0, f
             stack.extend(g.nodes[k].args)
         closures.append(s)
     cost = {k: node_cost[n.kind] for k, n in g.nodes.items() if k[0] != "E"}
-    flows = [set(a.colour.terms) for a in g.amps]
+    # fixed iteration orders (node creation order, flow order of the colour terms), so the
+    # schedule does not depend on Python's hash seed
+    rank = {k: i for i, k in enumerate(g.nodes)}
+    closures = [sorted(c, key=rank.__getitem__) for c in closures]
+    flows = [list(a.colour.terms) for a in g.amps]
     held, regs = OrderedDict(), OrderedDict()
     remaining = set(range(len(g.amps)))
     order = []

@@ -145,3 +145,21 @@ def test_generated_pieces_on_host_match_oracle(hostlib7, card):
         assert hostlib7.hostcheck7_me2(prec, card.ctypes.data_as(dp), 0.118, len(p), p.ctypes.data_as(dp),
                                        out.ctypes.data_as(dp)) == 0
         assert np.abs(out / ref - 1).max() <= tol, prec
+
+
+def test_generation_does_not_depend_on_hash_seed():
+    """The generated code is a function of the process alone (no set-iteration order leaks in)."""
+    import sys
+    code = ("import sys, hashlib; sys.path.insert(0, %r)\n"
+            "from paper_2507_21039_amd.gen import diagrams, emit\n"
+            "from paper_2507_21039_amd.gen.__main__ import PROCESSES\n"
+            "g = diagrams.build_graph(2)\n"
+            "h, info = emit.emit_qcd('P', g, 'x', **PROCESSES['ggttgg']['opts'])\n"
+            "h2, _ = emit.emit_qcd('P', g, 'x', order=(None, {'cache': 20, 'flow_cost': 50.0}), chunks=4)\n"
+            "print(hashlib.sha256((h + h2).encode()).hexdigest())\n") % os.path.join(HERE, "..")
+    outs = []
+    for seed in ("1", "2"):
+        env = dict(os.environ, PYTHONHASHSEED=seed)
+        outs.append(subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                                   check=True).stdout)
+    assert outs[0] == outs[1]
