@@ -20,15 +20,34 @@ import numpy as np
 
 METRIC = "|M|^2 events/s on 1 MI355X (gg→tt̄gg, FP64 vs mixed); p50/p99 served latency"
 PEAK_FP64_VALU = 78.6e12  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
-PEAK_FP32_VALU_UNPACKED = 78.6e12  # same lanes and rate; packed FP32 is not used
+PEAK_FP32_VALU = 157.3e12  # published FP32 vector peak (twice the FP64 rate)
 PEAK_HBM = 8.0e12
 
 # HBM traffic of one FP64 gg -> ttbar gg launch (1,048,576 events) from rocprofv3 counters
 # (profiles/me2_ggttgg_1M_traffic.md): FETCH_SIZE and WRITE_SIZE in KiB, each scaled by what the
 # counter reads for a plain 256 MiB device copy.  Valid only for the kernel sources it was taken
 # on (sha256 prefix of me2_kernels.h + helas.h + procs/ggttgg.h); otherwise traffic is null.
-TRAFFIC = {"source_sha": "25e77d958b73d7b2", "nevt": 1048576,
-           "fetch_kib": 198801.75, "write_kib": 8192.0, "fetch_factor": 262144 / 131095.8125, "write_factor": 1.0}
+TRAFFIC = {"source_sha": "aae00a7eafa999ea", "nevt": 1048576,
+           "fetch_kib": 198688.875, "write_kib": 8192.0, "fetch_factor": 262144 / 131089.0625, "write_factor": 1.0}
+
+# VALU instruction counters of the same launches (profiles/me2_ggttgg_1M_valu_counters.md), wave
+# instructions summed over the device: FLOPs = 64 lanes x (2 FMA + ADD + MUL + TRANS).
+COUNTERS = {
+    "source_sha": "aae00a7eafa999ea", "nevt": 1048576,
+    "fp64": {"FMA_F64": 12922650624, "ADD_F64": 7019167744, "MUL_F64": 10643046400, "TRANS_F64": 39845888,
+             "VALU": 32933675008},
+    "mixed_fast": {"FMA_F32": 9913237504, "ADD_F32": 5906628608, "MUL_F32": 8154775552, "TRANS_F32": 0,
+                   "FMA_F64": 322961408, "ADD_F64": 17825792, "MUL_F64": 104857600, "TRANS_F64": 39845888,
+                   "VALU": 28672262144},
+}
+
+
+def counter_flops(mode: str, nevt: int):
+    """FLOPs per launch from the VALU counters, or None if they were taken on other sources."""
+    if kernel_source_sha() != COUNTERS["source_sha"] or nevt != COUNTERS["nevt"]:
+        return None
+    c = COUNTERS[mode]
+    return 64.0 * sum(2 * v if k.startswith("FMA") else v for k, v in c.items() if k != "VALU")
 
 
 def kernel_source_sha() -> str:
@@ -111,7 +130,7 @@ def ggttggg_leg(card, steps=3, warmup=1):
             "workload": f"gg->ttbar ggg, {w.nevt} RAMBO events at sqrt(s)=2 TeV, no cuts, seed 5",
             "dtype": "f32 vertices/propagators/jamps/colour, f64 externals and sums",
             "diagrams": 1240, "helicities": 128, "good_helicities": info["ngoodhel"], "colour_flows": 120,
-            "achieved_tflops": tflops, "frac_of_valu_peak": tflops * 1e12 / PEAK_FP32_VALU_UNPACKED,
+            "achieved_tflops": tflops, "frac_of_valu_peak": tflops * 1e12 / PEAK_FP32_VALU,
             "max_rel_diff_vs_oracle_16_events": float(np.max(np.abs(got[idx] / ref - 1))),
             "workspace_bytes_per_event": info["workspace_bytes_per_event"]}
 
@@ -185,8 +204,9 @@ def main():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-ggttggg", action="store_true")
     ap.add_argument("--pmc", action="store_true",
-                    help="counter-collection mode: one FP64 launch, then a plain 256 MiB device copy "
-                         "(known traffic, for calibrating FETCH_SIZE / WRITE_SIZE); no JSON line")
+                    help="counter-collection mode: one FP64 and one MIXED_FAST gg->ttbar gg launch, one "
+                         "8192-event gg->ttbar ggg call, then a plain 256 MiB device copy (known traffic, "
+                         "for calibrating FETCH_SIZE / WRITE_SIZE); no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); events are independent and "
@@ -206,13 +226,21 @@ def main():
     mom = torch.from_numpy(p).cuda()
     out = torch.empty(nevt, dtype=torch.float64, device="cuda")
     if args.pmc:
+        # one launch of each kernel whose counters are quoted, then a copy of known size
         with hme.Handle(hme.GGTTGG, card, hme.FP64) as h:
             h.compute(mom, out)
+        with hme.Handle(hme.GGTTGG, card, hme.MIXED_FAST) as h:
+            h.compute(mom, out)
+        w7 = configs.WORKLOADS["ggttggg"]
+        mom7 = torch.from_numpy(w7.momenta(8192)).cuda()
+        with hme.Handle(hme.GGTTGGG, card, hme.MIXED_FAST) as h:
+            h.compute(mom7)
         src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")  # 256 MiB
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        log("[bench] pmc mode: 1 FP64 launch + 256 MiB copy done")
+        log("[bench] pmc mode: FP64 and MIXED_FAST gg->ttbar gg launches, one 8192-event gg->ttbar ggg "
+            "call, 256 MiB copy done")
         return
     results = {}
     for prec, name in ((hme.FP64, "fp64"), (hme.MIXED_FAST, "mixed_fast"), (hme.MIXED_PAPER, "mixed_paper")):
@@ -231,6 +259,9 @@ def main():
 
     f64 = results["fp64"]
     achieved = f64["flops_per_event"] * nevt / (f64["ms_per_step"] / 1e3)
+    cf = counter_flops("fp64", nevt)
+    counter_achieved = cf / (f64["ms_per_step"] / 1e3) if cf else None
+    cf_fast = counter_flops("mixed_fast", nevt)
     line = {
         "metric": METRIC,
         "value": f64["value"],
@@ -251,15 +282,23 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": measured_traffic(nevt),
                      "traffic_unit": "bytes per launch (HBM, counter-based)",
-                     "algorithmic_bytes": 200 * nevt, "flops_per_event": f64["flops_per_event"]},
+                     "algorithmic_bytes": 200 * nevt, "flops_per_event": f64["flops_per_event"],
+                     "counter_achieved": counter_achieved / 1e12 if counter_achieved else None,
+                     "counter_frac": counter_achieved / PEAK_FP64_VALU if counter_achieved else None,
+                     "counter_note": "executed FLOPs from SQ_INSTS_VALU_{FMA,ADD,MUL,TRANS}_F64, recomputed "
+                                     "wavefunctions included"},
         "mixed": {
             name: {"value": results[name]["value"], "ms_per_step": results[name]["ms_per_step"], "dtype": dt,
                    "achieved_tflops": results[name]["achieved_tflops"],
-                   "frac_of_valu_peak": results[name]["achieved_tflops"] * 1e12 / PEAK_FP32_VALU_UNPACKED,
+                   "frac_of_valu_peak": results[name]["achieved_tflops"] * 1e12 / peak,
+                   "valu_peak_tflops": peak / 1e12,
+                   "counter_achieved_tflops": (cf_fast / (results[name]["ms_per_step"] / 1e3) / 1e12
+                                               if name == "mixed_fast" and cf_fast else None),
                    "max_rel_diff_vs_fp64": float(np.max(np.abs(results[name]["out"] / f64["out"] - 1))),
                    "p99_rel_diff_vs_fp64": float(np.quantile(np.abs(results[name]["out"] / f64["out"] - 1), 0.99))}
-            for name, dt in (("mixed_fast", "f32 vertices/propagators/jamps/colour, f64 externals and sums"),
-                             ("mixed_paper", "f64 amplitudes and jamps, f32 colour algebra, f64 sums"))},
+            for name, dt, peak in (
+                ("mixed_fast", "f32 vertices/propagators/jamps/colour, f64 externals and sums", PEAK_FP32_VALU),
+                ("mixed_paper", "f64 amplitudes and jamps, f32 colour algebra, f64 sums", PEAK_FP64_VALU))},
         "ggttggg": None,
         "served": None,
     }
