@@ -31,8 +31,10 @@ HME_FN void load_event(const double* __restrict__ mom, int64_t ev, double (&p)[P
     for (int mu = 0; mu < 4; ++mu) p[k][mu] = src[k * 4 + mu];
 }
 
+template <class T> constexpr int me2_min_waves() { return sizeof(T) == 4 ? 3 : 2; }
+
 template <class Proc, class T, int LPE>
-__global__ void __launch_bounds__(256, 2)
+__global__ void __launch_bounds__(256, me2_min_waves<T>())
     me2_kernel(const double* __restrict__ mom, double* __restrict__ out, int64_t nevt,
                const int* __restrict__ goodhel, int ngood, ProcParams prm, double norm, int colour_f32,
                const int64_t* __restrict__ nevt_dev) {
@@ -147,12 +149,15 @@ template <class Proc, class T, int LPE> hipError_t launch_lpe(const LaunchArgs& 
 
 template <class Proc, class T> hipError_t launch_me2(const LaunchArgs& a) {
   // processes with 64 or more helicities always fill whole wavefronts (idle lanes are masked)
-  if constexpr (Proc::nhel >= 64) return launch_lpe<Proc, T, 64>(a);
-  switch (lanes_per_event(a.ngood)) {
-    case 4: return launch_lpe<Proc, T, 4>(a);
-    case 16: return launch_lpe<Proc, T, 16>(a);
-    case 32: return launch_lpe<Proc, T, 32>(a);
-    default: return launch_lpe<Proc, T, 64>(a);
+  if constexpr (Proc::nhel >= 64) {
+    return launch_lpe<Proc, T, 64>(a);
+  } else {
+    switch (lanes_per_event(a.ngood)) {
+      case 4: return launch_lpe<Proc, T, 4>(a);
+      case 16: return launch_lpe<Proc, T, 16>(a);
+      case 32: return launch_lpe<Proc, T, 32>(a);
+      default: return launch_lpe<Proc, T, 64>(a);
+    }
   }
 }
 
