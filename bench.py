@@ -27,18 +27,18 @@ PEAK_HBM = 8.0e12
 # (profiles/me2_ggttgg_1M_traffic.md): FETCH_SIZE and WRITE_SIZE in KiB, each scaled by what the
 # counter reads for a plain 256 MiB device copy.  Valid only for the kernel sources it was taken
 # on (sha256 prefix of me2_kernels.h + helas.h + procs/ggttgg.h); otherwise traffic is null.
-TRAFFIC = {"source_sha": "aae00a7eafa999ea", "nevt": 1048576,
-           "fetch_kib": 198688.875, "write_kib": 8192.0, "fetch_factor": 262144 / 131089.0625, "write_factor": 1.0}
+TRAFFIC = {"source_sha": "95e268091fb7a4c5", "nevt": 1048576,
+           "fetch_kib": 198685.1875, "write_kib": 8192.0, "fetch_factor": 262144 / 131088.5625, "write_factor": 1.0}
 
 # VALU instruction counters of the same launches (profiles/me2_ggttgg_1M_valu_counters.md), wave
 # instructions summed over the device: FLOPs = 64 lanes x (2 FMA + ADD + MUL + TRANS).
 COUNTERS = {
-    "source_sha": "aae00a7eafa999ea", "nevt": 1048576,
+    "source_sha": "95e268091fb7a4c5", "nevt": 1048576,
     "fp64": {"FMA_F64": 12922650624, "ADD_F64": 7019167744, "MUL_F64": 10643046400, "TRANS_F64": 39845888,
              "VALU": 32933675008},
-    "mixed_fast": {"FMA_F32": 9913237504, "ADD_F32": 5906628608, "MUL_F32": 8154775552, "TRANS_F32": 0,
+    "mixed_fast": {"FMA_F32": 10462691328, "ADD_F32": 6093275136, "MUL_F32": 8568963072, "TRANS_F32": 0,
                    "FMA_F64": 322961408, "ADD_F64": 17825792, "MUL_F64": 104857600, "TRANS_F64": 39845888,
-                   "VALU": 28672262144},
+                   "VALU": 30100422656},
 }
 
 
