@@ -26,35 +26,44 @@ PEAK_HBM = 8.0e12
 # HBM traffic of one FP64 gg -> ttbar gg launch (1,048,576 events) from rocprofv3 counters
 # (profiles/me2_ggttgg_1M_traffic.md): FETCH_SIZE and WRITE_SIZE in KiB, each scaled by what the
 # counter reads for a plain 256 MiB device copy.  Valid only for the kernel sources it was taken
-# on (sha256 prefix of me2_kernels.h + helas.h + procs/ggttgg.h); otherwise traffic is null.
-TRAFFIC = {"source_sha": "95e268091fb7a4c5", "nevt": 1048576,
-           "fetch_kib": 198685.1875, "write_kib": 8192.0, "fetch_factor": 262144 / 131088.5625, "write_factor": 1.0}
+# on (sha256 prefix of me2_kernels.h + colour_mfma.h + helas.h + procs/ggttgg.h); otherwise
+# traffic is null.
+TRAFFIC = {"source_sha": "79f35659eaaec3ca", "nevt": 1048576,
+           "fetch_kib": 198692.4375, "write_kib": 8192.0, "fetch_factor": 262144 / 131088.6875, "write_factor": 1.0}
 
-# VALU instruction counters of the same launches (profiles/me2_ggttgg_1M_valu_counters.md), wave
-# instructions summed over the device: FLOPs = 64 lanes x (2 FMA + ADD + MUL + TRANS).
+# VALU and MFMA instruction counters of the same launches (profiles/me2_ggttgg_1M_valu_counters.md),
+# wave instructions summed over the device: FLOPs = 64 lanes x (2 FMA + ADD + MUL + TRANS) plus
+# 512 per MFMA "MOPS" unit (the counter's own scale).
 COUNTERS = {
-    "source_sha": "95e268091fb7a4c5", "nevt": 1048576,
+    "source_sha": "79f35659eaaec3ca", "nevt": 1048576,
     "fp64": {"FMA_F64": 12922650624, "ADD_F64": 7019167744, "MUL_F64": 10643046400, "TRANS_F64": 39845888,
              "VALU": 32933675008},
-    "mixed_fast": {"FMA_F32": 10462691328, "ADD_F32": 6093275136, "MUL_F32": 8568963072, "TRANS_F32": 0,
+    "mixed_fast": {"FMA_F32": 9925820416, "ADD_F32": 6207569920, "MUL_F32": 8492417024, "TRANS_F32": 0,
                    "FMA_F64": 322961408, "ADD_F64": 17825792, "MUL_F64": 104857600, "TRANS_F64": 39845888,
-                   "VALU": 30100422656},
+                   "MFMA_MOPS_BF16": 2684354560, "VALU": 30227300352},
 }
 
 
 def counter_flops(mode: str, nevt: int):
-    """FLOPs per launch from the VALU counters, or None if they were taken on other sources."""
+    """Vector-ALU FLOPs per launch from the counters, or None if they were taken on other sources."""
     if kernel_source_sha() != COUNTERS["source_sha"] or nevt != COUNTERS["nevt"]:
         return None
     c = COUNTERS[mode]
-    return 64.0 * sum(2 * v if k.startswith("FMA") else v for k, v in c.items() if k != "VALU")
+    return 64.0 * sum(2 * v if k.startswith("FMA") else v for k, v in c.items() if k[:4] in ("FMA_", "ADD_", "MUL_", "TRAN"))
+
+
+def counter_mfma_flops(mode: str, nevt: int):
+    """Matrix-core FLOPs per launch from the MFMA counters (bf16 operand splits included), or None."""
+    if kernel_source_sha() != COUNTERS["source_sha"] or nevt != COUNTERS["nevt"]:
+        return None
+    return 512.0 * sum(v for k, v in COUNTERS[mode].items() if k.startswith("MFMA"))
 
 
 def kernel_source_sha() -> str:
     import hashlib
     root = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2507_21039_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("me2_kernels.h", "helas.h", "procs/ggttgg.h"):
+    for f in ("me2_kernels.h", "colour_mfma.h", "helas.h", "procs/ggttgg.h"):
         with open(os.path.join(root, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -128,7 +137,8 @@ def ggttggg_leg(card, steps=3, warmup=1):
     tflops = info["flops_per_event"] * w.nevt / per / 1e12
     return {"value": w.nevt * steps / gpu_s, "unit": "events/s", "ms_per_step": per * 1e3, "steps": steps,
             "workload": f"gg->ttbar ggg, {w.nevt} RAMBO events at sqrt(s)=2 TeV, no cuts, seed 5",
-            "dtype": "f32 vertices/propagators/jamps/colour, f64 externals and sums",
+            "dtype": "f32 vertices/propagators/jamps, bf16x3-split MFMA colour sum with f32 accumulation, "
+                     "f64 externals and sums",
             "diagrams": 1240, "helicities": 128, "good_helicities": info["ngoodhel"], "colour_flows": 120,
             "achieved_tflops": tflops, "frac_of_valu_peak": tflops * 1e12 / PEAK_FP32_VALU,
             "max_rel_diff_vs_oracle_16_events": float(np.max(np.abs(got[idx] / ref - 1))),
@@ -262,6 +272,7 @@ def main():
     cf = counter_flops("fp64", nevt)
     counter_achieved = cf / (f64["ms_per_step"] / 1e3) if cf else None
     cf_fast = counter_flops("mixed_fast", nevt)
+    mf_fast = counter_mfma_flops("mixed_fast", nevt)
     line = {
         "metric": METRIC,
         "value": f64["value"],
@@ -294,10 +305,13 @@ def main():
                    "valu_peak_tflops": peak / 1e12,
                    "counter_achieved_tflops": (cf_fast / (results[name]["ms_per_step"] / 1e3) / 1e12
                                                if name == "mixed_fast" and cf_fast else None),
+                   "counter_mfma_tflops": (mf_fast / (results[name]["ms_per_step"] / 1e3) / 1e12
+                                           if name == "mixed_fast" and mf_fast else None),
                    "max_rel_diff_vs_fp64": float(np.max(np.abs(results[name]["out"] / f64["out"] - 1))),
                    "p99_rel_diff_vs_fp64": float(np.quantile(np.abs(results[name]["out"] / f64["out"] - 1), 0.99))}
             for name, dt, peak in (
-                ("mixed_fast", "f32 vertices/propagators/jamps/colour, f64 externals and sums", PEAK_FP32_VALU),
+                ("mixed_fast", "f32 vertices/propagators/jamps, bf16x3-split MFMA colour sum with f32 accumulation, "
+                           "f64 externals and sums", PEAK_FP32_VALU),
                 ("mixed_paper", "f64 amplitudes and jamps, f32 colour algebra, f64 sums", PEAK_FP64_VALU))},
         "ggttggg": None,
         "served": None,

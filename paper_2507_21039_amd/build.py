@@ -19,7 +19,7 @@ ARCH = "gfx950"
 # -packed-fp32-ops keeps the compiler from emitting packed FP32 VALU instructions.
 HIPFLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wall", "-Wno-unused-variable",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-_KERNEL_DEPS = ["me2_kernels.h", "helas.h", "process.h"]
+_KERNEL_DEPS = ["me2_kernels.h", "colour_mfma.h", "helas.h", "process.h"]
 _PROCS = ("eemumu", "ggtt", "ggttg", "ggttgg", "ggttggg")
 # g g -> t tbar g g g runs as pieces, one generated translation unit each
 PIECES = {"ggttggg": 12}

@@ -17,6 +17,7 @@
 
 #include <cstdint>
 
+#include "colour_mfma.h"
 #include "helas.h"
 #include "process.h"
 
@@ -42,6 +43,11 @@ __global__ void __launch_bounds__(256, me2_min_waves<T>())
   constexpr int EPB = 256 / LPE;  // events per block
   // per-event table of momentum sums and propagator denominators, shared by the event's lanes
   __shared__ double table[EPB * (Proc::ntab > 0 ? Proc::ntab : 1)];
+  // with single-precision amplitudes, the colour sums of processes with 24 or more flows run
+  // on the matrix cores (one event per wavefront, the 64 lanes are 64 helicity columns)
+  constexpr bool kMfmaColour = LPE == 64 && Proc::ncol >= 24 && sizeof(T) == 4;
+  __shared__ __attribute__((aligned(16))) __bf16 cnh[kMfmaColour ? ColourTiles<Proc>::words : 8];
+  __shared__ __attribute__((aligned(16))) __bf16 cnl[kMfmaColour ? ColourTiles<Proc>::words : 8];
   const int lane = threadIdx.x & 63;
   // the event count comes from device memory when a captured graph launches a batch of
   // varying size with a fixed grid; blocks past the end leave at once
@@ -57,20 +63,37 @@ __global__ void __launch_bounds__(256, me2_min_waves<T>())
   load_event<Proc>(mom, evc, p);
   double* tab = table + (threadIdx.x / LPE) * Proc::ntab;
   for (int j = sub; j < Proc::nitems; j += LPE) Proc::table_entry(p, prm, j, tab);
+  if constexpr (kMfmaColour) colour_tiles_fill<Proc>(cnh, cnl, threadIdx.x, 256);
   __syncthreads();
   double acc = 0.0;
-  for (int k = sub; k < ngood; k += LPE) {
-    cx<T> jamp[Proc::ncol];
+  if constexpr (kMfmaColour) {
+    // every lane runs every pass (the matrix cores take the whole wavefront); a lane past the
+    // last good helicity evaluates the last one again and drops its result (each helicity
+    // column of the product depends on that lane's jamps only)
+    for (int g = 0; g < ngood; g += 64) {
+      const int k = g + sub;
+      const bool valid = k < ngood;
+      cx<T> jamp[Proc::ncol];
 #pragma unroll
-    for (int c = 0; c < Proc::ncol; ++c) jamp[c] = {T(0), T(0)};
-    Proc::template amplitudes<T>(p, prm, (unsigned)goodhel[k], (tab_ptr)tab, jamp);
-    if (colour_f32) {  // wave-uniform: the colour algebra in single precision
-      cx<float> jf[Proc::ncol];
+      for (int c = 0; c < Proc::ncol; ++c) jamp[c] = {T(0), T(0)};
+      Proc::template amplitudes<T>(p, prm, (unsigned)goodhel[valid ? k : ngood - 1], (tab_ptr)tab, jamp);
+      const float s = colour_sum_wave<Proc>(jamp, NumerLds<Proc>{(const HME_LDS __bf16*)cnh, (const HME_LDS __bf16*)cnl});
+      acc += valid ? (double)s : 0.0;
+    }
+  } else {
+    for (int k = sub; k < ngood; k += LPE) {
+      cx<T> jamp[Proc::ncol];
 #pragma unroll
-      for (int c = 0; c < Proc::ncol; ++c) jf[c] = cast<float>(jamp[c]);
-      acc += (double)Proc::template colour_sum<float>(jf);
-    } else {
-      acc += (double)Proc::template colour_sum<T>(jamp);
+      for (int c = 0; c < Proc::ncol; ++c) jamp[c] = {T(0), T(0)};
+      Proc::template amplitudes<T>(p, prm, (unsigned)goodhel[k], (tab_ptr)tab, jamp);
+      if (colour_f32) {  // wave-uniform: the colour algebra in single precision
+        cx<float> jf[Proc::ncol];
+#pragma unroll
+        for (int c = 0; c < Proc::ncol; ++c) jf[c] = cast<float>(jamp[c]);
+        acc += (double)Proc::template colour_sum<float>(jf);
+      } else {
+        acc += (double)Proc::template colour_sum<T>(jamp);
+      }
     }
   }
 #pragma unroll
