@@ -109,6 +109,46 @@ int hme_destroy(hme_handle* h);
 /* Message describing the calling thread's most recent failure ("" if none). */
 const char* hme_last_error(void);
 
+/* ------------------------------------------------------------------ phase space
+ * Flat phase-space points on the device (RAMBO: Kleiss, Stirling, Ellis, Comput. Phys.
+ * Commun. 40 (1986) 359), the sampling of the paper's standalone application (section
+ * "Standalone application"), so that generation and |M|^2 both stay on the GPU.
+ *
+ * hme_rambo writes nevt events [nevt][npar][4] (E, px, py, pz in GeV) for `process` into the
+ * caller's device buffer `momenta` (8-byte aligned), on the current device, asynchronously on
+ * `hip_stream`: two massless partons along +z and -z with sqrt_s / 2 each, then the final
+ * state (top mass card->mT for the top pair of the QCD processes, massless otherwise).
+ * Event i (numbered from first_event) draws from Philox4x32-10 (Salmon et al., SC'11) with
+ * key (seed mod 2^32, 0x52414D42) and counter (i mod 2^32, i / 2^32, attempt, 2 j + b) for
+ * final-state particle j: each counter gives two doubles (27 + 26 bits of two words each,
+ * plus half an ulp) used as cos(theta), phi and the two factors of the exponential energy.
+ * An event the cut rejects moves on to attempt + 1, so every event depends on (seed, i)
+ * alone; after 10000 rejected attempts its final-state momenta and weight are NaN.
+ * With HME_CUT_NO_RETRY or-ed into `cut` every event keeps its first attempt, and a
+ * rejected one gets weight 0 (unbiased flat Monte Carlo with cuts).
+ * weights (device, may be NULL): the phase-space weight of each point in GeV^(2n-4) for n
+ * final-state particles, (2 pi)^(4-3n) (pi/2)^(n-1) s^(n-2) / ((n-1)! (n-2)!) for massless
+ * ones, times xi^(2n-3) prod_j (|k_j| / E_j) sqrt_s / sum_j (|k_j|^2 / E_j) with massive ones
+ * (xi: the common rescaling of the three-momenta).
+ * cut: HME_CUT_NONE; HME_CUT_GLUON_PT: transverse momentum of final-state particle 2 (the
+ * first gluon) above cut_value; HME_CUT_GLUON_DR: Delta R (pseudorapidity, azimuth) of
+ * final-state particles 2 and 3 above cut_value.  A cut on gluons that the process lacks
+ * accepts every point.
+ * Returns HME_E_ARG for an unknown process or cut, nevt < 0, sqrt_s not above the final-state
+ * masses, or a NULL / misaligned buffer with nevt > 0. */
+enum hme_cut { HME_CUT_NONE = 0, HME_CUT_GLUON_PT = 1, HME_CUT_GLUON_DR = 2, HME_CUT_NO_RETRY = 0x100 };
+
+int hme_rambo(int process, const hme_sm_card* card, double sqrt_s, uint64_t seed, int64_t first_event, int64_t nevt,
+              int cut, double cut_value, double* momenta, double* weights, void* hip_stream);
+
+/* out[0] = sum_i weights[i] me2[i], out[1] = sum_i (weights[i] me2[i])^2 over nevt events, all
+ * three device buffers of doubles, asynchronously on `hip_stream` (one workgroup, a fixed
+ * order of additions: the same inputs give the same bits).  With the weights of hme_rambo
+ * and |M|^2 of hme_compute, the flat Monte Carlo cross section is out[0] / (2 s nevt) in
+ * GeV^-2, its statistical error sqrt(out[1] / nevt - (out[0] / nevt)^2) / sqrt(nevt) / (2 s).
+ * Returns HME_E_ARG for nevt < 0 or a NULL / misaligned buffer. */
+int hme_weighted_sum(const double* me2, const double* weights, int64_t nevt, double* out, void* hip_stream);
+
 /* ------------------------------------------------------------------ serving
  * A persistent request loop over every process of the library on one device
  * (the paper's multi-event interface and gridpack workers, section "Event

@@ -159,3 +159,23 @@ def iden(process: int) -> float:
     if lib().oracle_iden(process, _dp(out)) != 0:
         raise ValueError("bad process")
     return float(out[0])
+
+
+GEV2_TO_PB = 0.3893793721e9  # (hbar c)^2 in GeV^2 pb
+
+
+def cross_section(me2_values, weights, sqrt_s: float):
+    """Flat Monte Carlo cross section and its statistical error, both in pb.
+
+    sigma = (1 / (2 s)) (1 / N) sum_i w_i |M_i|^2: the flux factor of massless
+    colliding partons times the mean over N phase-space points of weight times
+    |M|^2 (points that fail the cuts count with weight 0), as the paper's
+    standalone application integrates over flat phase space (section
+    "Standalone application").  Summed in extended precision.
+    """
+    v = np.asarray(weights, dtype=np.longdouble) * np.asarray(me2_values, dtype=np.longdouble)
+    n = v.size
+    flux = 2.0 * sqrt_s * sqrt_s
+    mean = v.sum() / n
+    var = max((v * v).sum() / n - mean * mean, 0.0)
+    return float(mean / flux * GEV2_TO_PB), float(np.sqrt(var / n) / flux * GEV2_TO_PB)

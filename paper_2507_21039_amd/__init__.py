@@ -20,11 +20,14 @@ NPAR = {EEMUMU: 4, GGTT: 4, GGTTG: 5, GGTTGG: 6, GGTTGGG: 7}
 PROCESS_NAMES = {EEMUMU: "e+e- -> mu+mu-", GGTT: "gg -> ttbar", GGTTG: "gg -> ttbar g", GGTTGG: "gg -> ttbar gg",
                  GGTTGGG: "gg -> ttbar ggg"}
 
+CUT_NONE, CUT_GLUON_PT, CUT_GLUON_DR, CUT_NO_RETRY = 0, 1, 2, 0x100
+GEV2_TO_PB = 0.3893793721e9  # (hbar c)^2 in GeV^2 pb
+
 HME_OK, HME_E_ARG, HME_E_HIP, HME_E_OOM, HME_E_BUDGET, HME_E_TIMEOUT, HME_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 
 EXPORTED = ("hme_create", "hme_compute", "hme_query", "hme_good_helicities", "hme_destroy", "hme_last_error",
             "hme_server_create", "hme_submit", "hme_wait", "hme_wait_timed", "hme_server_stats_get",
-            "hme_server_destroy")
+            "hme_server_destroy", "hme_rambo", "hme_weighted_sum")
 
 
 class SmCard(ctypes.Structure):
@@ -81,9 +84,12 @@ def lib():
         L.hme_wait_timed.argtypes = [vp, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
         L.hme_server_stats_get.argtypes = [vp, ctypes.POINTER(ServerStats)]
         L.hme_server_destroy.argtypes = [vp]
+        L.hme_rambo.argtypes = [ctypes.c_int, ctypes.POINTER(SmCard), ctypes.c_double, ctypes.c_uint64, ctypes.c_int64,
+                                ctypes.c_int64, ctypes.c_int, ctypes.c_double, vp, vp, vp]
+        L.hme_weighted_sum.argtypes = [vp, vp, ctypes.c_int64, vp, vp]
         for name in ("hme_create", "hme_compute", "hme_query", "hme_good_helicities", "hme_destroy",
                      "hme_server_create", "hme_submit", "hme_wait", "hme_wait_timed", "hme_server_stats_get",
-                     "hme_server_destroy"):
+                     "hme_server_destroy", "hme_rambo", "hme_weighted_sum"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -104,6 +110,67 @@ def card_struct(card) -> SmCard:
     if isinstance(card, dict):
         return SmCard(card["mZ"], card["wZ"], card["alpha_inv"], card["Gf"], card["mT"], card["wT"])
     return SmCard(*[float(x) for x in card])
+
+
+def rambo_ptr(process: int, card, sqrt_s: float, seed: int, first_event: int, nevt: int, cut: int,
+              cut_value: float, momenta_ptr: int, weights_ptr: int = 0, stream_ptr: int = 0):
+    _check(lib().hme_rambo(process, ctypes.byref(card_struct(card)), float(sqrt_s), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                           int(first_event), int(nevt), int(cut), float(cut_value), ctypes.c_void_p(momenta_ptr),
+                           ctypes.c_void_p(weights_ptr), ctypes.c_void_p(stream_ptr)))
+
+
+def _f64_gpu(t, n, what):
+    import torch
+    if t.device.type != "cuda" or t.dtype != torch.float64 or not t.is_contiguous() or t.numel() < n:
+        raise ValueError(f"{what} must be a contiguous float64 GPU tensor with at least {n} elements")
+
+
+def rambo(process: int, card, sqrt_s: float, seed: int, nevt: int, first_event: int = 0, cut: int = CUT_NONE,
+          cut_value: float = 0.0, out=None, weights=None, device=None, stream=None):
+    """Phase-space points on the GPU (hme_rambo).
+
+    Returns momenta [nevt, npar, 4] (float64, on `device`, default cuda) and, when `weights`
+    is True or a tensor, also their phase-space weights [nevt].
+    """
+    import torch
+    dev = torch.device(device) if device is not None else (out.device if out is not None else torch.device("cuda"))
+    shape = (int(nevt), NPAR[process], 4)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float64, device=dev)
+    _f64_gpu(out, shape[0] * shape[1] * 4, "out")
+    want_w = weights is not None and weights is not False
+    if weights is True:
+        weights = torch.empty(shape[0], dtype=torch.float64, device=out.device)
+    if want_w:
+        _f64_gpu(weights, shape[0], "weights")
+    s = stream if stream is not None else torch.cuda.current_stream(out.device)
+    with torch.cuda.device(out.device):
+        rambo_ptr(process, card, sqrt_s, seed, first_event, nevt, cut, cut_value, out.data_ptr(),
+                  weights.data_ptr() if want_w else 0, s.cuda_stream)
+    return (out, weights) if want_w else out
+
+
+def weighted_sum(me2, weights, stream=None):
+    """(sum w |M|^2, sum (w |M|^2)^2) over the events (hme_weighted_sum), as a float64 GPU tensor [2]."""
+    import torch
+    n = me2.numel()
+    _f64_gpu(me2, n, "me2")
+    _f64_gpu(weights, n, "weights")
+    out = torch.empty(2, dtype=torch.float64, device=me2.device)
+    s = stream if stream is not None else torch.cuda.current_stream(me2.device)
+    with torch.cuda.device(me2.device):
+        _check(lib().hme_weighted_sum(ctypes.c_void_p(me2.data_ptr()), ctypes.c_void_p(weights.data_ptr()), n,
+                                      ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(s.cuda_stream)))
+    return out
+
+
+def cross_section_pb(sums, nevt: int, sqrt_s: float):
+    """Flat Monte Carlo cross section and its error in pb from weighted_sum's two sums."""
+    s1, s2 = float(sums[0]), float(sums[1])
+    flux = 2.0 * sqrt_s * sqrt_s
+    mean = s1 / nevt
+    var = max(s2 / nevt - mean * mean, 0.0)
+    return mean / flux * GEV2_TO_PB, (var / nevt) ** 0.5 / flux * GEV2_TO_PB
 
 
 class Handle:

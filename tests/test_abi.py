@@ -41,3 +41,25 @@ def test_argument_errors_without_gpu():
     assert L.hme_destroy(None) == hme.HME_OK
     info = hme.Info()
     assert L.hme_query(None, ctypes.byref(info)) == hme.HME_E_ARG
+
+
+@pytest.mark.skipif(not os.path.exists(hme.LIB_PATH), reason="libhme.so not built")
+def test_phase_space_argument_errors_without_gpu():
+    L = hme.lib()
+    card = hme.card_struct((91.188, 2.441, 132.5, 1.16639e-5, 173.0, 0.0))
+    buf = ctypes.c_void_p(8)  # never dereferenced: every call below fails its checks first
+    assert L.hme_rambo(9, ctypes.byref(card), 1000.0, 1, 0, 10, 0, 0.0, buf, None, None) == hme.HME_E_ARG
+    assert L.hme_rambo(1, None, 1000.0, 1, 0, 10, 0, 0.0, buf, None, None) == hme.HME_E_ARG
+    assert L.hme_rambo(1, ctypes.byref(card), 1000.0, 1, 0, -1, 0, 0.0, buf, None, None) == hme.HME_E_ARG
+    assert L.hme_rambo(1, ctypes.byref(card), 1000.0, 1, 0, 10, 3, 0.0, buf, None, None) == hme.HME_E_ARG
+    assert "cut" in hme.last_error()
+    assert L.hme_rambo(1, ctypes.byref(card), 300.0, 1, 0, 10, 0, 0.0, buf, None, None) == hme.HME_E_ARG
+    assert "sqrt_s" in hme.last_error()
+    assert L.hme_rambo(1, ctypes.byref(card), 1000.0, 1, 0, 10, 0, 0.0, None, None, None) == hme.HME_E_ARG
+    assert L.hme_rambo(1, ctypes.byref(card), 1000.0, 1, 0, 10, 0, 0.0, ctypes.c_void_p(12), None,
+                       None) == hme.HME_E_ARG
+    # e+e- -> mu+mu- has massless final states: any positive energy is above threshold
+    assert L.hme_rambo(0, ctypes.byref(card), 100.0, 1, 0, 0, 0, 0.0, None, None, None) == hme.HME_OK
+    assert L.hme_weighted_sum(buf, buf, -1, buf, None) == hme.HME_E_ARG
+    assert L.hme_weighted_sum(buf, buf, 10, None, None) == hme.HME_E_ARG
+    assert L.hme_weighted_sum(None, buf, 10, buf, None) == hme.HME_E_ARG

@@ -55,6 +55,11 @@ def _cut_gluon_dr(p):
     return rambo.delta_r(p[:, 2], p[:, 3]) > 0.4
 
 
+# the same cuts as codes of the on-device generator: (kind, value); kinds 1 = pT of the
+# first final-state gluon, 2 = Delta R of the first two final-state gluons
+CUT_CODES = {"none": (0, 0.0), "pT(g) > 20 GeV": (1, 20.0), "dR(g,g) > 0.4": (2, 0.4)}
+
+
 @dataclass
 class Workload:
     name: str
@@ -66,10 +71,12 @@ class Workload:
     cut_text: str = "none"
     extra: dict = field(default_factory=dict)
 
-    def momenta(self, nevt: int | None = None, first_event: int = 0, mT: float = SM_CARD["mT"]):
+    def momenta(self, nevt: int | None = None, first_event: int = 0, mT: float = SM_CARD["mT"],
+                retry: bool = True, with_weight: bool = False):
         n = self.nevt if nevt is None else nevt
         return rambo.generate(n, self.sqrt_s, [0.0, 0.0], final_masses(self.process, mT),
-                              self.seed, self.cut, first_event=first_event)
+                              self.seed, self.cut, first_event=first_event, retry=retry,
+                              with_weight=with_weight)
 
 
 WORKLOADS = {

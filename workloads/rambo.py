@@ -15,6 +15,8 @@ the next attempt, so every event is independent of batch size and order.
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 from .philox import philox4x32, uniform_pairs
@@ -67,21 +69,34 @@ def rambo_massless(u: np.ndarray, sqrt_s: float, nout: int) -> np.ndarray:
     return p
 
 
-def put_on_shell(p: np.ndarray, masses, sqrt_s: float) -> np.ndarray:
+def massless_volume(n: int, s: float) -> float:
+    """Volume of massless n-body phase space at invariant mass squared s (the RAMBO paper):
+    (2 pi)^(4-3n) (pi/2)^(n-1) s^(n-2) / ((n-1)! (n-2)!), with (2 pi)^4 delta^4 and
+    d^3p / ((2 pi)^3 2E) per particle in the measure."""
+    return ((2 * math.pi) ** (4 - 3 * n) * (math.pi / 2) ** (n - 1) * s ** (n - 2)
+            / (math.factorial(n - 1) * math.factorial(n - 2)))
+
+
+def put_on_shell(p: np.ndarray, masses, sqrt_s: float, with_weight: bool = False):
     """Rescale massless momenta [nevt, nout, 4] so that particle j has mass masses[j].
 
     Solves sum_j sqrt(m_j^2 + xi^2 E_j^2) = sqrt_s for xi by Newton iteration
     to extended-precision rounding, then k_j = (sqrt(m_j^2 + xi^2 E_j^2), xi * p_j).
+    With with_weight, also returns the phase-space weight of each point: the massless
+    volume times xi^(2n-3) prod_j |k_j| / k_j^0 * sqrt_s / sum_j |k_j|^2 / k_j^0.
     """
     m = np.asarray(masses, dtype=np.longdouble)[None, :]
     p = np.asarray(p, dtype=np.longdouble)
+    n = p.shape[1]
     if np.sum(m) >= sqrt_s:
         raise ValueError("sum of final-state masses exceeds sqrt(s)")
     P2 = p[..., 1] ** 2 + p[..., 2] ** 2 + p[..., 3] ** 2
+    w0 = massless_volume(n, sqrt_s * sqrt_s)
     if not np.any(m > 0):
         k = p.copy()
         k[..., 0] = np.sqrt(P2)
-        return k.astype(np.float64)
+        k = k.astype(np.float64)
+        return (k, np.full(p.shape[0], w0)) if with_weight else k
     E = np.sqrt(P2)
     xi = np.full(p.shape[0], np.sqrt(max(0.0, 1.0 - float(np.sum(m) / sqrt_s) ** 2)), dtype=np.longdouble)
     for _ in range(200):
@@ -95,7 +110,12 @@ def put_on_shell(p: np.ndarray, masses, sqrt_s: float) -> np.ndarray:
     k = np.empty_like(p)
     k[..., 1:] = xi[:, None, None] * p[..., 1:]
     k[..., 0] = np.sqrt(m * m + (xi * xi)[:, None] * P2)
-    return k.astype(np.float64)
+    if not with_weight:
+        return k.astype(np.float64)
+    kabs = xi[:, None] * E
+    w = (w0 * xi ** (2 * n - 3) * np.prod(kabs / k[..., 0], axis=1) * sqrt_s
+         / np.sum(kabs * kabs / k[..., 0], axis=1))
+    return k.astype(np.float64), w.astype(np.float64)
 
 
 def pseudorapidity(p: np.ndarray) -> np.ndarray:
@@ -115,13 +135,16 @@ def delta_r(pa: np.ndarray, pb: np.ndarray) -> np.ndarray:
 
 
 def generate(nevt: int, sqrt_s: float, in_masses, out_masses, seed: int, cut=None,
-             first_event: int = 0, max_attempts: int = 10000) -> np.ndarray:
+             first_event: int = 0, max_attempts: int = 10000, retry: bool = True,
+             with_weight: bool = False):
     """Generate events [nevt, nin + nout, 4] (E, px, py, pz) in GeV.
 
     The two incoming partons are massless and collide along the z axis at
     sqrt_s / 2 each: parton 1 moves along +z, parton 2 along -z.
     ``cut`` maps final-state momenta [n, nout, 4] to a boolean mask of accepted
-    events.  Event numbers run from ``first_event``.
+    events.  Event numbers run from ``first_event``.  With ``retry`` False every
+    event keeps its first attempt and a rejected one gets weight 0.  With
+    ``with_weight`` returns (momenta, phase-space weights [nevt]).
     """
     if any(m != 0 for m in in_masses):
         raise ValueError("only massless incoming partons are supported")
@@ -129,6 +152,7 @@ def generate(nevt: int, sqrt_s: float, in_masses, out_masses, seed: int, cut=Non
     nin = len(in_masses)
     ev_idx = np.arange(first_event, first_event + nevt, dtype=np.int64)
     out = np.empty((nevt, nin + nout, 4), dtype=np.float64)
+    wgt = np.empty(nevt, dtype=np.float64)
     half = 0.5 * sqrt_s
     out[:, 0] = (half, 0.0, 0.0, half)
     out[:, 1] = (half, 0.0, 0.0, -half)
@@ -137,14 +161,19 @@ def generate(nevt: int, sqrt_s: float, in_masses, out_masses, seed: int, cut=Non
     nblocks = 2 * nout  # 4 uniforms per particle, 2 uniforms per Philox call
     while todo.size:
         u = _uniforms(seed, ev_idx[todo], attempt[todo], nblocks)
-        p = put_on_shell(rambo_massless(u, sqrt_s, nout), out_masses, sqrt_s)
+        p, w = put_on_shell(rambo_massless(u, sqrt_s, nout), out_masses, sqrt_s, with_weight=True)
         ok = np.ones(todo.size, dtype=bool) if cut is None else np.asarray(cut(p), dtype=bool)
+        if not retry:
+            out[todo, nin:] = p
+            wgt[todo] = np.where(ok, w, 0.0)
+            break
         out[todo[ok], nin:] = p[ok]
+        wgt[todo[ok]] = w[ok]
         attempt[todo[~ok]] += 1
         todo = todo[~ok]
         if todo.size and attempt[todo].min() >= max_attempts:
             raise RuntimeError("cut acceptance too low")
-    return out
+    return (out, wgt) if with_weight else out
 
 
 def acceptance(nevt: int, sqrt_s: float, out_masses, seed: int, cut) -> float:
