@@ -145,6 +145,50 @@ def ggttggg_leg(card, steps=3, warmup=1):
             "workspace_bytes_per_event": info["workspace_bytes_per_event"]}
 
 
+def e2e_leg(card, steps=5, warmup=2):
+    """Flat Monte Carlo on the device for gg -> ttbar gg at 2^20 points per step: RAMBO points
+    (Delta R cut as zero weight), FP64 |M|^2, weighted sum; each stage timed with events on the
+    stream it runs on."""
+    import torch
+
+    import paper_2507_21039_amd as hme
+    from workloads import configs
+    w = configs.WORKLOADS["ggttgg"]
+    kind, value = configs.CUT_CODES[w.cut_text]
+    n = w.nevt
+    stream = torch.cuda.current_stream()
+    mom = torch.empty((n, hme.NPAR[w.process], 4), dtype=torch.float64, device="cuda")
+    wt = torch.empty(n, dtype=torch.float64, device="cuda")
+    me = torch.empty(n, dtype=torch.float64, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    t = np.zeros(3)
+    sums = []
+    with hme.Handle(w.process, card, hme.FP64) as h:
+        for step in range(warmup + steps):
+            first = step * n
+            ev[0].record(stream)
+            hme.rambo(w.process, card, w.sqrt_s, w.seed, n, first, kind | hme.CUT_NO_RETRY, value, out=mom,
+                      weights=wt, stream=stream)
+            ev[1].record(stream)
+            h.compute(mom, me, 0.118, stream)
+            ev[2].record(stream)
+            sums.append(hme.weighted_sum(me, wt, stream))
+            ev[3].record(stream)
+            torch.cuda.synchronize()
+            if step >= warmup:
+                t += [ev[i].elapsed_time(ev[i + 1]) / 1e3 for i in range(3)]
+    tot = np.sum([x.cpu().numpy() for x in sums], axis=0)
+    sigma, err = hme.cross_section_pb(tot, n * (warmup + steps), w.sqrt_s)
+    per = t / steps
+    rambo_bytes = n * (hme.NPAR[w.process] * 4 + 1) * 8
+    return {"value": n / per.sum(), "unit": "events/s", "steps": steps, "nevt_per_step": n,
+            "workload": f"gg->ttbar gg flat Monte Carlo at sqrt(s)=2 TeV, dR(g,g)>0.4 as zero weight, seed 4, "
+                        f"event numbers 0..{n * (warmup + steps) - 1}",
+            "ms_rambo": per[0] * 1e3, "ms_me2": per[1] * 1e3, "ms_sum": per[2] * 1e3,
+            "rambo_written_gbps": rambo_bytes / per[0] / 1e9,
+            "sigma_pb": sigma, "sigma_err_pb": err, "points": n * (warmup + steps)}
+
+
 def served_leg(card, precision, nwarm=200, ntimed=3000, budget=32 << 30, nstreams=4):
     """Poisson request stream (200 requests/s, sizes log-uniform in 256..65536) through the server.
 
@@ -213,6 +257,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-ggttggg", action="store_true")
+    ap.add_argument("--no-e2e", action="store_true")
     ap.add_argument("--pmc", action="store_true",
                     help="counter-collection mode: one FP64 and one MIXED_FAST gg->ttbar gg launch, one "
                          "8192-event gg->ttbar ggg call, then a plain 256 MiB device copy (known traffic, "
@@ -314,12 +359,17 @@ def main():
                            "f64 externals and sums", PEAK_FP32_VALU),
                 ("mixed_paper", "f64 amplitudes and jamps, f32 colour algebra, f64 sums", PEAK_FP64_VALU))},
         "ggttggg": None,
+        "e2e": None,
         "served": None,
     }
     if not args.no_ggttggg:
         log("[bench] gg->ttbar ggg (mixed fast)")
         line["ggttggg"] = ggttggg_leg(card)
         log(f"[bench] gg->ttbar ggg: {line['ggttggg']['value']:.4g} events/s")
+    if not args.no_e2e:
+        log("[bench] end-to-end flat Monte Carlo (device RAMBO + FP64 |M|^2 + sum)")
+        line["e2e"] = e2e_leg(card)
+        log(f"[bench] e2e: {line['e2e']['value']:.4g} events/s, rambo {line['e2e']['ms_rambo']:.3f} ms")
     if not args.no_served:
         log("[bench] served mix (Poisson, 200 requests/s)")
         line["served"] = served_leg(card, hme.MIXED_FAST)

@@ -109,6 +109,23 @@ int hme_destroy(hme_handle* h);
 /* Message describing the calling thread's most recent failure ("" if none). */
 const char* hme_last_error(void);
 
+/* Same as hme_compute, and also picks one helicity and one colour flow per event, the
+ * information an event generator keeps with each unweighted event (the paper's section
+ * "Event generation interface": the Bridge returns them with |M|^2).
+ * rnd_hel, rnd_col: device arrays of nevt uniform numbers in [0, 1) supplied by the caller.
+ * sel_hel[i]: the chosen helicity index (numbered as in hme_good_helicities): the first good
+ *   helicity, in increasing index order, at which the running sum of |M_h|^2 exceeds
+ *   rnd_hel[i] times their total (probability |M_h|^2 / sum_h |M_h|^2).
+ * sel_col[i]: the chosen colour flow c (flows are the orderings of the gluons along the quark
+ *   line, particle order, in lexicographic order; 0 for e+e- -> mu+mu-): the first flow at
+ *   which the running sum of W_c = sum_h |J_c,h|^2 (squared colour-flow amplitudes summed over
+ *   the good helicities) exceeds rnd_col[i] times their total.
+ * me2 is bitwise the output of hme_compute.  Device buffers: me2, rnd_* 8-byte aligned,
+ * sel_* 4-byte aligned; asynchronous on hip_stream.  Returns HME_E_UNSUPPORTED for
+ * HME_GGTTGGG (evaluated in pieces), otherwise as hme_compute. */
+int hme_compute_select(hme_handle* h, double alpha_s, int64_t nevt, const double* momenta, const double* rnd_hel,
+                       const double* rnd_col, double* me2, int* sel_hel, int* sel_col, void* hip_stream);
+
 /* ------------------------------------------------------------------ phase space
  * Flat phase-space points on the device (RAMBO: Kleiss, Stirling, Ellis, Comput. Phys.
  * Commun. 40 (1986) 359), the sampling of the paper's standalone application (section

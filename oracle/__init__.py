@@ -51,6 +51,8 @@ def lib():
                 f.restype = ctypes.c_int
             L.oracle_colour_matrix.argtypes = [ctypes.c_int, dp]
             L.oracle_partial_amps.argtypes = [ctypes.c_int, dp, dp, ip, ctypes.c_int, dp]
+            L.oracle_partial_amps_hel.argtypes = [ctypes.c_int, dp, dp, ip, dp]
+            L.oracle_me2_hel.argtypes = [ctypes.c_int, dp, ctypes.c_double, dp, dp]
             L.oracle_dressed_amp.argtypes = [ctypes.c_int, dp, dp, ip, ip, ctypes.c_int, ctypes.c_int,
                                              ctypes.c_int, ctypes.c_int, dp]
             L.oracle_external.argtypes = [ctypes.c_int, dp, ctypes.c_double, ctypes.c_int, dp]
@@ -107,6 +109,30 @@ def partial_amps(momentum, card, spins, gauge_leg: int = -1) -> np.ndarray:
     sp = np.ascontiguousarray(spins, dtype=np.int32)
     out = np.empty(2 * math.factorial(npar - 2), dtype=np.float64)
     if lib().oracle_partial_amps(npar, _dp(card), _dp(mom), _ip(sp), gauge_leg, _dp(out)) != 0:
+        raise ValueError("bad arguments")
+    return out[0::2] + 1j * out[1::2]
+
+
+def me2_hel(process: int, momentum, card, alpha_s: float = 0.118) -> np.ndarray:
+    """|M_h|^2 of every helicity configuration of one event (physical helicities), normalised so
+    that they sum to me2; index h has bit npar-1-k set when particle k has helicity +1."""
+    mom = np.ascontiguousarray(momentum, dtype=np.float64)
+    card = np.ascontiguousarray(card, dtype=np.float64)
+    out = np.empty(1 << NPAR[process], dtype=np.float64)
+    if mom.shape != (NPAR[process], 4) or lib().oracle_me2_hel(process, _dp(card), float(alpha_s), _dp(mom),
+                                                               _dp(out)) != 0:
+        raise ValueError("bad arguments")
+    return out
+
+
+def partial_amps_hel(momentum, card, spins) -> np.ndarray:
+    """Colour-ordered partial amplitudes (g_s = 1) for physical helicities spins[k] in {0: -1, 1: +1}."""
+    import math
+    mom = np.ascontiguousarray(momentum, dtype=np.float64)
+    card = np.ascontiguousarray(card, dtype=np.float64)
+    sp = np.ascontiguousarray(spins, dtype=np.int32)
+    out = np.empty(2 * math.factorial(mom.shape[0] - 2), dtype=np.float64)
+    if lib().oracle_partial_amps_hel(mom.shape[0], _dp(card), _dp(mom), _ip(sp), _dp(out)) != 0:
         raise ValueError("bad arguments")
     return out[0::2] + 1j * out[1::2]
 

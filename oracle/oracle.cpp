@@ -184,6 +184,18 @@ template <class R> V4<R> lin_pol(const R* k, int s) {
   return V4<R>{cx<R>(0), cx<R>(-sp), cx<R>(cp), cx<R>(0)};
 }
 
+// Helicity polarisation of a massless vector boson with momentum k, physical helicity lam:
+// (e1 + i lam e2) / sqrt(2) up to a phase (e1, e2, k-hat right-handed), conjugated for an
+// outgoing boson.  |M_h|^2 of one helicity configuration does not depend on the phases.
+template <class R> V4<R> hel_pol(const R* k, int lam, bool outgoing) {
+  const V4<R> e1 = lin_pol(k, 0), e2 = lin_pol(k, 1);
+  const cx<R> c(0, outgoing ? -R(lam) : R(lam));
+  const R r = 1 / std::sqrt(R(2));
+  V4<R> e;
+  for (int mu = 0; mu < 4; ++mu) e[mu] = (e1[mu] + c * e2[mu]) * r;
+  return e;
+}
+
 // -------------------------------------------------------------------- SU(3)
 
 template <class R> struct SU3 {
@@ -252,7 +264,8 @@ template <class R> Couplings<R> make_couplings(const double* card) {
 
 // Particles: 1 e+ (incoming), 2 e- (incoming), 3 mu+ (outgoing), 4 mu- (outgoing).
 // Vertices from L = -e Q psibar A-slash psi - e/(sw cw) psibar Z-slash (T3 P_L - Q sw^2) psi, Q = -1.
-template <class R> R me2_eemumu(const R* mom, const Couplings<R>& cp) {
+// per_hel (optional): |M_h|^2 / 4 of each helicity configuration, index sum_k [h_k = +1] 2^(3 - k).
+template <class R> R me2_eemumu(const R* mom, const Couplings<R>& cp, R* per_hel = nullptr) {
   const Dirac<R>& d = dirac<R>();
   const cx<R> I(0, 1);
   const R* p1 = mom;
@@ -312,6 +325,7 @@ template <class R> R me2_eemumu(const R* mom, const Couplings<R>& cp) {
           }
           amp += -I * (gg - qm * qe / (cp.mZ * cp.mZ)) / dz;
           sum += std::norm(amp);
+          if (per_hel) per_hel[((h1 > 0) << 3) | ((h2 > 0) << 2) | ((h3 > 0) << 1) | (h4 > 0)] = std::norm(amp) / 4;
         }
   return sum / 4;  // average over the 2 x 2 initial helicities
 }
@@ -705,7 +719,10 @@ double iden_of(int proc) {
 // Build the external states of g g -> t tbar + gluons for one spin configuration.
 // Particles: 0, 1 incoming gluons; 2 top; 3 antitop; 4.. outgoing gluons.
 // spins[k] in {0, 1}: linear polarisation index for gluons, helicity (2 s - 1) for quarks.
-template <class R> QcdLegs<R> qcd_legs(const R* mom, int npar, R mT, const int* spins, int gauge_leg) {
+// spins[k] in {0, 1}: linear polarisation e1 / e2 for gluons (helicity_basis false) or helicity
+// -1 / +1 (true); helicity -1 / +1 for the top and antitop.
+template <class R> QcdLegs<R> qcd_legs(const R* mom, int npar, R mT, const int* spins, int gauge_leg,
+                                       bool helicity_basis = false) {
   QcdLegs<R> L;
   L.mT = mT;
   L.n = npar - 2;
@@ -718,6 +735,8 @@ template <class R> QcdLegs<R> qcd_legs(const R* mom, int npar, R mT, const int* 
     if (g == gauge_leg) {
       // Ward-identity check: polarisation replaced by the gluon momentum
       L.eps[g] = real4<R>(p);
+    } else if (helicity_basis) {
+      L.eps[g] = hel_pol(p, 2 * spins[k] - 1, k >= 2);
     } else {
       L.eps[g] = lin_pol(p, spins[k]);  // real, so conjugation for outgoing gluons is trivial
     }
@@ -864,6 +883,64 @@ int oracle_me2(int proc, const double* card, double alpha_s, int64_t nevt, const
 int oracle_me2_ld(int proc, const double* card, double alpha_s, int64_t nevt, const double* mom, double* out,
                   int mode, int nthreads) {
   return me2_batch<long double>(proc, card, alpha_s, nevt, mom, out, mode, nthreads);
+}
+
+// |M_h|^2 of each helicity configuration of one event, normalised as oracle_me2 (they sum to it):
+// physical helicities (circular gluon polarisations), out[h] for h = sum_k [h_k = +1] 2^(npar-1-k),
+// k = 0 .. npar-1 in particle order.  out has 2^npar entries.
+int oracle_me2_hel(int proc, const double* card, double alpha_s, const double* mom, double* out) {
+  const int npar = npar_of(proc);
+  if (npar < 0 || proc == P_GGGG || !card || !mom || !out) return -1;
+  Couplings<double> cp = make_couplings<double>(card);
+  if (proc == P_EEMUMU) {
+    me2_eemumu(mom, cp, out);
+    return 0;
+  }
+  const double pi = std::acos(-1.0);
+  const int n = npar - 2;
+  double coup = 1;
+  for (int i = 0; i < n; ++i) coup *= 4 * pi * alpha_s;
+  const double iden = iden_of(proc);
+  const std::vector<double>& C = colour_matrix_cached<double>(n);
+  std::vector<std::vector<int>> perms;
+  std::vector<int> p(n);
+  std::iota(p.begin(), p.end(), 0);
+  do perms.push_back(p); while (std::next_permutation(p.begin(), p.end()));
+  const int np = (int)perms.size();
+  std::vector<cx<double>> A(np);
+  int spins[8];
+  for (int h = 0; h < (1 << npar); ++h) {
+    for (int k = 0; k < npar; ++k) spins[k] = (h >> (npar - 1 - k)) & 1;
+    QcdLegs<double> L = qcd_legs(mom, npar, cp.mT, spins, -1, true);
+    for (int s = 0; s < np; ++s) A[s] = ordered_amp(L, perms[s].data());
+    double m2 = 0;
+    for (int s = 0; s < np; ++s) {
+      cx<double> row = 0;
+      for (int t = 0; t < np; ++t) row += C[(size_t)s * np + t] * std::conj(A[t]);
+      m2 += (A[s] * row).real();
+    }
+    out[h] = coup * m2 / iden;
+  }
+  return 0;
+}
+
+// Colour-ordered partial amplitudes in the helicity basis (as oracle_partial_amps with circular
+// gluon polarisations), spins[k] in {0, 1} for helicity -1 / +1.
+int oracle_partial_amps_hel(int npar, const double* card, const double* mom, const int* spins, double* out) {
+  if (npar < 4 || npar > 7 || !mom || !spins || !out) return -1;
+  Couplings<double> cp = make_couplings<double>(card);
+  QcdLegs<double> L = qcd_legs(mom, npar, cp.mT, spins, -1, true);
+  const int n = npar - 2;
+  std::vector<int> p(n);
+  std::iota(p.begin(), p.end(), 0);
+  int s = 0;
+  do {
+    cx<double> a = ordered_amp(L, p.data());
+    out[2 * s] = a.real();
+    out[2 * s + 1] = a.imag();
+    ++s;
+  } while (std::next_permutation(p.begin(), p.end()));
+  return 0;
 }
 
 // Colour matrix for n gluons on a quark line, orderings in lexicographic order; out is (n!)^2.

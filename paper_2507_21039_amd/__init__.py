@@ -27,7 +27,7 @@ HME_OK, HME_E_ARG, HME_E_HIP, HME_E_OOM, HME_E_BUDGET, HME_E_TIMEOUT, HME_E_UNSU
 
 EXPORTED = ("hme_create", "hme_compute", "hme_query", "hme_good_helicities", "hme_destroy", "hme_last_error",
             "hme_server_create", "hme_submit", "hme_wait", "hme_wait_timed", "hme_server_stats_get",
-            "hme_server_destroy", "hme_rambo", "hme_weighted_sum")
+            "hme_server_destroy", "hme_rambo", "hme_weighted_sum", "hme_compute_select")
 
 
 class SmCard(ctypes.Structure):
@@ -87,9 +87,10 @@ def lib():
         L.hme_rambo.argtypes = [ctypes.c_int, ctypes.POINTER(SmCard), ctypes.c_double, ctypes.c_uint64, ctypes.c_int64,
                                 ctypes.c_int64, ctypes.c_int, ctypes.c_double, vp, vp, vp]
         L.hme_weighted_sum.argtypes = [vp, vp, ctypes.c_int64, vp, vp]
+        L.hme_compute_select.argtypes = [vp, ctypes.c_double, ctypes.c_int64, vp, vp, vp, vp, vp, vp, vp]
         for name in ("hme_create", "hme_compute", "hme_query", "hme_good_helicities", "hme_destroy",
                      "hme_server_create", "hme_submit", "hme_wait", "hme_wait_timed", "hme_server_stats_get",
-                     "hme_server_destroy", "hme_rambo", "hme_weighted_sum"):
+                     "hme_server_destroy", "hme_rambo", "hme_weighted_sum", "hme_compute_select"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -200,6 +201,32 @@ class Handle:
         s = stream if stream is not None else torch.cuda.current_stream(momenta.device)
         self.compute_ptr(alpha_s, n, momenta.data_ptr(), out.data_ptr(), s.cuda_stream)
         return out
+
+    def compute_select(self, momenta, rnd_hel, rnd_col, alpha_s: float = 0.118, stream=None):
+        """|M|^2 plus one helicity and one colour flow per event (hme_compute_select).
+
+        rnd_hel, rnd_col: float64 GPU tensors [nevt] of uniforms in [0, 1).
+        Returns (me2 float64 [nevt], sel_hel int32 [nevt], sel_col int32 [nevt]).
+        """
+        import torch
+        if momenta.device.type != "cuda" or momenta.dtype != torch.float64 or not momenta.is_contiguous():
+            raise ValueError("momenta must be a contiguous float64 GPU tensor")
+        if momenta.dim() != 3 or momenta.shape[1] != NPAR[self.process] or momenta.shape[2] != 4:
+            raise ValueError(f"momenta must be [nevt, {NPAR[self.process]}, 4]")
+        n = momenta.shape[0]
+        for t, what in ((rnd_hel, "rnd_hel"), (rnd_col, "rnd_col")):
+            _f64_gpu(t, n, what)
+            if t.device != momenta.device:
+                raise ValueError(f"{what} must be on the momenta's device")
+        out = torch.empty(n, dtype=torch.float64, device=momenta.device)
+        sh = torch.empty(n, dtype=torch.int32, device=momenta.device)
+        sc = torch.empty(n, dtype=torch.int32, device=momenta.device)
+        s = stream if stream is not None else torch.cuda.current_stream(momenta.device)
+        _check(lib().hme_compute_select(self._h, float(alpha_s), n, ctypes.c_void_p(momenta.data_ptr()),
+                                        ctypes.c_void_p(rnd_hel.data_ptr()), ctypes.c_void_p(rnd_col.data_ptr()),
+                                        ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(sh.data_ptr()),
+                                        ctypes.c_void_p(sc.data_ptr()), ctypes.c_void_p(s.cuda_stream)))
+        return out, sh, sc
 
     def query(self) -> dict:
         info = Info()

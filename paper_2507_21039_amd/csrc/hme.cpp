@@ -252,10 +252,16 @@ int64_t handle_ws_bytes_per_event(const hme_handle* h) {
 }
 
 hipError_t launch_for_handle(const hme_handle* h, int64_t nevt_grid, const int64_t* nevt_dev, const double* mom,
-                             double* out, double norm, hipStream_t s, void* ws, int64_t ws_events) {
+                             double* out, double norm, hipStream_t s, void* ws, int64_t ws_events,
+                             const SelectArgs& sel) {
   LaunchArgs a{mom, out, nevt_grid, h->d_goodhel, (int)h->goodhel.size(), h->prm, norm, s,
-               h->precision == HME_MIXED_PAPER ? 1 : 0, nevt_dev, ws, ws_events};
+               h->precision == HME_MIXED_PAPER ? 1 : 0, nevt_dev, ws, ws_events, sel};
   return kProcs[h->process].me2(a, h->precision);
+}
+
+hipError_t launch_for_handle(const hme_handle* h, int64_t nevt_grid, const int64_t* nevt_dev, const double* mom,
+                             double* out, double norm, hipStream_t s, void* ws, int64_t ws_events) {
+  return launch_for_handle(h, nevt_grid, nevt_dev, mom, out, norm, s, ws, ws_events, SelectArgs{});
 }
 
 }  // namespace hme
@@ -289,6 +295,29 @@ int hme_compute(hme_handle* h, double alpha_s, int64_t nevt, const double* momen
     if (e == hipSuccess) e = ef;
   }
   if (e != hipSuccess) return hip_fail(e, "hme_compute: launch");
+  return HME_OK;
+}
+
+int hme_compute_select(hme_handle* h, double alpha_s, int64_t nevt, const double* momenta, const double* rnd_hel,
+                       const double* rnd_col, double* me2, int* sel_hel, int* sel_col, void* hip_stream) {
+  if (!h) return fail(HME_E_ARG, "hme_compute_select: handle is NULL");
+  if (nevt < 0) return fail(HME_E_ARG, "hme_compute_select: nevt < 0");
+  if (hme::handle_chunked(h))
+    return fail(HME_E_UNSUPPORTED, "hme_compute_select: not available for a process evaluated in pieces");
+  if (nevt == 0) return HME_OK;
+  if (!momenta || !me2 || !rnd_hel || !rnd_col || !sel_hel || !sel_col)
+    return fail(HME_E_ARG, "hme_compute_select: NULL buffer");
+  if (((reinterpret_cast<uintptr_t>(momenta) | reinterpret_cast<uintptr_t>(me2) | reinterpret_cast<uintptr_t>(rnd_hel) |
+        reinterpret_cast<uintptr_t>(rnd_col)) & 7u) ||
+      ((reinterpret_cast<uintptr_t>(sel_hel) | reinterpret_cast<uintptr_t>(sel_col)) & 3u))
+    return fail(HME_E_ARG, "hme_compute_select: misaligned buffer");
+  if (!(alpha_s > 0)) return fail(HME_E_ARG, "hme_compute_select: alpha_s must be positive");
+  DeviceGuard guard(h->device);
+  if (guard.err != hipSuccess) return hip_fail(guard.err, "hme_compute_select: hipSetDevice");
+  hme::SelectArgs sel{rnd_hel, rnd_col, sel_hel, sel_col};
+  const hipError_t e = hme::launch_for_handle(h, nevt, nullptr, momenta, me2, hme::handle_norm(h, alpha_s),
+                                              static_cast<hipStream_t>(hip_stream), nullptr, 0, sel);
+  if (e != hipSuccess) return hip_fail(e, "hme_compute_select: launch");
   return HME_OK;
 }
 

@@ -34,11 +34,69 @@ HME_FN void load_event(const double* __restrict__ mom, int64_t ev, double (&p)[P
 
 template <class T> constexpr int me2_min_waves() { return sizeof(T) == 4 ? 3 : 2; }
 
+// Per-event choice of one helicity and one colour flow from caller-supplied uniform numbers
+// (the information an event generator keeps with each event; section "Event generation
+// interface").  Helicity: the first good helicity, in increasing index order, whose running
+// sum of |M_h|^2 exceeds rnd_hel x sum_h |M_h|^2.  Colour flow: the first flow whose running
+// sum of W_c = sum_h |J_c,h|^2 exceeds rnd_col x sum_c W_c.
+struct SelectArgs {
+  const double* rnd_hel = nullptr;
+  const double* rnd_col = nullptr;
+  int* sel_hel = nullptr;
+  int* sel_col = nullptr;
+};
+
+// The event's LPE lanes (an aligned segment of the wavefront) hold one helicity each; lanes
+// past the last good helicity pass valid = false.  Every lane of the segment must call this.
 template <class Proc, class T, int LPE>
+HME_FN void choose_helicity_and_flow(const cx<T> (&jamp)[Proc::ncol], bool valid, double mh, int sub, int64_t ev,
+                                     int64_t evc, int64_t nevt, const int* __restrict__ goodhel, int ngood,
+                                     const SelectArgs& sel) {
+  // inclusive running sum of |M_h|^2 over the segment, in good-helicity order
+  double cum = valid ? mh : 0.0;
+#pragma unroll
+  for (int d = 1; d < LPE; d <<= 1) {
+    const double t = __shfl_up(cum, d, LPE);
+    if (sub >= d) cum += t;
+  }
+  const double total = __shfl(cum, LPE - 1, LPE);
+  const double target_h = sel.rnd_hel[evc] * total;
+  const uint64_t over = __ballot(valid && cum > target_h);
+  const int base = (int)(threadIdx.x & 63) - sub;
+  const uint64_t seg = (~0ull >> (64 - LPE)) << base;
+  const uint64_t hit = over & seg;
+  const int kh = hit ? __builtin_ctzll(hit) - base : ngood - 1;
+  // colour-flow weights summed over the segment's helicities
+  double wtot = 0.0;
+#pragma unroll
+  for (int c = 0; c < Proc::ncol; ++c)
+    wtot += valid ? (double)jamp[c].r * (double)jamp[c].r + (double)jamp[c].i * (double)jamp[c].i : 0.0;
+#pragma unroll
+  for (int off = LPE / 2; off > 0; off >>= 1) wtot += __shfl_xor(wtot, off, 64);
+  const double target_c = sel.rnd_col[evc] * wtot;
+  double cum_c = 0.0;
+  int kc = -1, last = 0;
+#pragma unroll
+  for (int c = 0; c < Proc::ncol; ++c) {
+    double w = valid ? (double)jamp[c].r * (double)jamp[c].r + (double)jamp[c].i * (double)jamp[c].i : 0.0;
+#pragma unroll
+    for (int off = LPE / 2; off > 0; off >>= 1) w += __shfl_xor(w, off, 64);
+    cum_c += w;
+    if (kc < 0 && cum_c > target_c) kc = c;
+    if (w > 0) last = c;
+  }
+  if (kc < 0) kc = last;  // rounding left the target at or above the last running sum
+  if (sub == 0 && ev < nevt) {
+    sel.sel_hel[ev] = goodhel[kh];
+    sel.sel_col[ev] = kc;
+  }
+}
+
+template <class Proc, class T, int LPE, bool Select = false>
 __global__ void __launch_bounds__(256, me2_min_waves<T>())
     me2_kernel(const double* __restrict__ mom, double* __restrict__ out, int64_t nevt,
                const int* __restrict__ goodhel, int ngood, ProcParams prm, double norm, int colour_f32,
-               const int64_t* __restrict__ nevt_dev) {
+               const int64_t* __restrict__ nevt_dev, SelectArgs sel) {
   constexpr int EPW = 64 / LPE;   // events per wavefront
   constexpr int EPB = 256 / LPE;  // events per block
   // per-event table of momentum sums and propagator denominators, shared by the event's lanes
@@ -66,7 +124,28 @@ __global__ void __launch_bounds__(256, me2_min_waves<T>())
   if constexpr (kMfmaColour) colour_tiles_fill<Proc>(cnh, cnl, threadIdx.x, 256);
   __syncthreads();
   double acc = 0.0;
-  if constexpr (kMfmaColour) {
+  if constexpr (Select) {
+    // one helicity per lane (the launcher checks ngood <= LPE); every lane runs, a lane past
+    // the last good helicity evaluates the last one again and contributes zero
+    const bool valid = sub < ngood;
+    cx<T> jamp[Proc::ncol];
+#pragma unroll
+    for (int c = 0; c < Proc::ncol; ++c) jamp[c] = {T(0), T(0)};
+    Proc::template amplitudes<T>(p, prm, (unsigned)goodhel[valid ? sub : ngood - 1], (tab_ptr)tab, jamp);
+    double mh;
+    if constexpr (kMfmaColour) {
+      mh = (double)colour_sum_wave<Proc>(jamp, NumerLds<Proc>{(const HME_LDS __bf16*)cnh, (const HME_LDS __bf16*)cnl});
+    } else if (colour_f32) {
+      cx<float> jf[Proc::ncol];
+#pragma unroll
+      for (int c = 0; c < Proc::ncol; ++c) jf[c] = cast<float>(jamp[c]);
+      mh = (double)Proc::template colour_sum<float>(jf);
+    } else {
+      mh = (double)Proc::template colour_sum<T>(jamp);
+    }
+    acc = valid ? mh : 0.0;
+    choose_helicity_and_flow<Proc, T, LPE>(jamp, valid, mh, sub, ev, evc, nevt, goodhel, ngood, sel);
+  } else if constexpr (kMfmaColour) {
     // every lane runs every pass (the matrix cores take the whole wavefront); a lane past the
     // last good helicity evaluates the last one again and drops its result (each helicity
     // column of the product depends on that lane's jamps only)
@@ -137,6 +216,7 @@ struct LaunchArgs {
   const int64_t* nevt_dev = nullptr;  // if set, the kernel reads the event count here (nevt sizes the grid)
   void* ws = nullptr;                 // jamp workspace of a process evaluated in pieces
   int64_t ws_events = 0;              // events the workspace holds (the sub-batch size)
+  SelectArgs sel{};                   // helicity / colour-flow choice (sel.sel_hel == nullptr: none)
 };
 
 struct ProcInfo {
@@ -165,8 +245,14 @@ template <class Proc, class T, int LPE> hipError_t launch_lpe(const LaunchArgs& 
   constexpr int EPB = threads / LPE;  // events per block
   const int64_t blocks = (a.nevt + EPB - 1) / EPB;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  me2_kernel<Proc, T, LPE><<<dim3((unsigned)blocks), dim3(threads), 0, a.stream>>>(
-      a.mom, a.out, a.nevt, a.goodhel, a.ngood, a.prm, a.norm, a.colour_f32, a.nevt_dev);
+  if (a.sel.sel_hel) {
+    if (a.ngood > LPE) return hipErrorInvalidValue;  // the choice needs one helicity per lane
+    me2_kernel<Proc, T, LPE, true><<<dim3((unsigned)blocks), dim3(threads), 0, a.stream>>>(
+        a.mom, a.out, a.nevt, a.goodhel, a.ngood, a.prm, a.norm, a.colour_f32, a.nevt_dev, a.sel);
+  } else {
+    me2_kernel<Proc, T, LPE, false><<<dim3((unsigned)blocks), dim3(threads), 0, a.stream>>>(
+        a.mom, a.out, a.nevt, a.goodhel, a.ngood, a.prm, a.norm, a.colour_f32, a.nevt_dev, a.sel);
+  }
   return hipGetLastError();
 }
 

@@ -191,7 +191,20 @@ __global__ void __launch_bounds__(kSumThreads)
                         double* __restrict__ out) {
   __shared__ double part[2][kSumThreads / 64];
   double s1 = 0, s2 = 0;
-  for (int64_t i = threadIdx.x; i < nevt; i += kSumThreads) {
+  // eight loads in flight per thread before the (sequential, fixed-order) additions
+  constexpr int kBatch = 8;
+  int64_t i = threadIdx.x;
+  for (; i + (kBatch - 1) * kSumThreads < nevt; i += kBatch * kSumThreads) {
+    double v[kBatch];
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) v[b] = weight[i + b * kSumThreads] * me2[i + b * kSumThreads];
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      s1 += v[b];
+      s2 += v[b] * v[b];
+    }
+  }
+  for (; i < nevt; i += kSumThreads) {
     const double v = weight[i] * me2[i];
     s1 += v;
     s2 += v * v;

@@ -34,7 +34,34 @@ void run(const hme::ProcParams& prm, double alpha_s, int64_t nevt, const double*
     out[e] = acc;
   }
 }
+template <class Proc>
+void jamps(const hme::ProcParams& prm, const double* mom, int h, double* out) {
+  double p[Proc::npar][4];
+  for (int k = 0; k < Proc::npar; ++k)
+    for (int mu = 0; mu < 4; ++mu) p[k][mu] = mom[k * 4 + mu];
+  double tab[Proc::ntab > 0 ? Proc::ntab : 1];
+  for (int j = 0; j < Proc::nitems; ++j) Proc::table_entry(p, prm, j, tab);
+  hme::cx<double> jamp[Proc::ncol];
+  for (auto& j : jamp) j = {0.0, 0.0};
+  Proc::template amplitudes<double>(p, prm, (unsigned)h, (hme::tab_ptr)tab, jamp);
+  for (int c = 0; c < Proc::ncol; ++c) out[2 * c] = jamp[c].r, out[2 * c + 1] = jamp[c].i;
+}
 }  // namespace
+
+// the colour-flow amplitudes (jamps, FP64) of one event and one helicity
+extern "C" int hostcheck_jamps(int process, const double* card, const double* mom, int h, double* out) {
+  hme_sm_card c{card[0], card[1], card[2], card[3], card[4], card[5]};
+  hme::ProcParams prm;
+  std::string why;
+  if (!hme::derive_params(c, prm, why)) return -1;
+  switch (process) {
+    case 1: jamps<hme::P_ggtt>(prm, mom, h, out); break;
+    case 2: jamps<hme::P_ggttg>(prm, mom, h, out); break;
+    case 3: jamps<hme::P_ggttgg>(prm, mom, h, out); break;
+    default: return -1;
+  }
+  return 0;
+}
 
 extern "C" int hostcheck_me2(int process, int precision, const double* card, double alpha_s, int64_t nevt,
                              const double* mom, double* out, double* per_hel) {

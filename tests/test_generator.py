@@ -60,6 +60,7 @@ def _hostlib():
     L = ctypes.CDLL(HOSTLIB)
     dp = ctypes.POINTER(ctypes.c_double)
     L.hostcheck_me2.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_double, ctypes.c_int64, dp, dp, dp]
+    L.hostcheck_jamps.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, dp]
     return L
 
 
@@ -163,3 +164,45 @@ def test_generation_does_not_depend_on_hash_seed():
         outs.append(subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
                                    check=True).stdout)
     assert outs[0] == outs[1]
+
+
+@pytest.mark.parametrize("proc,key,npar", [(0, "eemumu", 4), (1, "ggtt", 4), (2, "ggttg", 5), (3, "ggttgg", 6)])
+def test_generated_helicities_match_oracle_helicity_basis(hostlib, card, proc, key, npar):
+    """Each helicity's |M_h|^2 of the generated code equals the oracle's physical-helicity value
+    (index bit npar-1-k set for helicity +1 of particle k): helicity labels, not just their sum."""
+    dp = ctypes.POINTER(ctypes.c_double)
+    p = np.ascontiguousarray(configs.WORKLOADS[key].momenta(4))
+    nhel = 1 << npar
+    out, per_hel = np.empty(len(p)), np.empty(len(p) * nhel)
+    assert hostlib.hostcheck_me2(proc, 0, card.ctypes.data_as(dp), 0.118, len(p), p.ctypes.data_as(dp),
+                                 out.ctypes.data_as(dp), per_hel.ctypes.data_as(dp)) == 0
+    per_hel = per_hel.reshape(len(p), nhel)
+    for e in range(len(p)):
+        ref = oracle.me2_hel(proc, p[e], card, 0.118)
+        assert np.abs(per_hel[e] - ref).max() <= 1e-13 * ref.sum()
+
+
+@pytest.mark.parametrize("proc,key,npar", [(1, "ggtt", 4), (2, "ggttg", 5), (3, "ggttgg", 6)])
+def test_generated_flows_match_oracle_orderings(hostlib, card, proc, key, npar):
+    """Jamp c of the generated code is the oracle's colour-ordered amplitude for the c-th
+    lexicographic ordering of the gluons, up to one factor common to all flows."""
+    dp = ctypes.POINTER(ctypes.c_double)
+    ncol = math.factorial(npar - 2)
+    p = np.ascontiguousarray(configs.WORKLOADS[key].momenta(2)[1])
+    pairs = []
+    for h in range(1 << npar):
+        out = np.empty(2 * ncol)
+        assert hostlib.hostcheck_jamps(proc, card.ctypes.data_as(dp), p.ctypes.data_as(dp), h,
+                                       out.ctypes.data_as(dp)) == 0
+        A = oracle.partial_amps_hel(p, card, [(h >> (npar - 1 - k)) & 1 for k in range(npar)])
+        pairs.append((out[0::2] + 1j * out[1::2], A))
+    top = max(np.abs(A).max() for _, A in pairs)
+    checked = 0
+    for J, A in pairs:
+        big = np.abs(A) > 1e-6 * top  # vanishing helicities hold rounding noise only
+        if not big.any():
+            continue
+        ratio = np.abs(J[big]) ** 2 / np.abs(A[big]) ** 2
+        assert np.abs(ratio / ratio[0] - 1).max() <= 1e-9
+        checked += 1
+    assert checked >= (1 << npar) // 2

@@ -235,3 +235,55 @@ def test_colour_matrix_identities():
         # rational with a small denominator
         num = C * 4 * 3 ** (n - 1)
         assert np.abs(num - np.round(num)).max() <= 1e-9
+
+
+@pytest.mark.parametrize("proc,key,nevt", [(oracle.EEMUMU, "eemumu", 20), (oracle.GGTT, "ggtt", 20),
+                                           (oracle.GGTTG, "ggttg", 10), (oracle.GGTTGG, "ggttgg", 4)])
+def test_helicity_basis_sums_to_linear_basis(card, proc, key, nevt):
+    """Circular gluon polarisations summed over helicities give the linear-polarisation sum."""
+    p = configs.WORKLOADS[key].momenta(nevt)
+    tot = oracle.me2(proc, p, card, AS)
+    for e in range(nevt):
+        assert oracle.me2_hel(proc, p[e], card, AS).sum() == pytest.approx(tot[e], rel=1e-13)
+
+
+def test_eemumu_helicity_closed_form(card):
+    """Massless e+e- -> mu+mu-: only opposite helicities on each fermion line survive; with
+    bit 3-k for particle k (e+, e-, mu+, mu-) set for helicity +1, index 10 is (e-_L, mu-_L),
+    5 (e-_R, mu-_R), 9 (e-_L, mu-_R), 6 (e-_R, mu-_L), with values e^4 |A_ij|^2 u^2 or t^2."""
+    p = configs.WORKLOADS["eemumu"].momenta(50)
+    ew = oracle.ew(card)
+    sw2, cw2, e = ew["sw2"], ew["cw2"], ew["e"]
+    mZ, wZ = card[0], card[1]
+    gL, gR = -0.5 + sw2, sw2
+    for ev in p:
+        hel = oracle.me2_hel(oracle.EEMUMU, ev, card)
+        s = mdot(ev[0] + ev[1], ev[0] + ev[1])
+        t = mdot(ev[1] - ev[3], ev[1] - ev[3])
+        u = mdot(ev[1] - ev[2], ev[1] - ev[2])
+        A = lambda gi, gj: 1 / s + gi * gj / (sw2 * cw2) / (s - mZ ** 2 + 1j * mZ * wZ)
+        want = np.zeros(16)
+        want[10] = e ** 4 * abs(A(gL, gL)) ** 2 * u ** 2
+        want[5] = e ** 4 * abs(A(gR, gR)) ** 2 * u ** 2
+        want[9] = e ** 4 * abs(A(gL, gR)) ** 2 * t ** 2
+        want[6] = e ** 4 * abs(A(gR, gL)) ** 2 * t ** 2
+        assert np.abs(hel - want).max() <= 1e-13 * want.sum()
+
+
+def test_ggtt_helicity_selection_rules():
+    """Massless quarks: helicity is conserved along the quark line and the two incoming gluons
+    need opposite helicities (all-outgoing MHV counting), so only 4 of 16 configurations
+    survive; two-to-two kinematics is planar, so flipping every helicity leaves |M_h|^2."""
+    card0 = configs.card_array(dict(mT=0.0))
+    p = configs.WORKLOADS["ggtt"].momenta(30, mT=0.0)
+    allowed = {0b0101, 0b0110, 0b1001, 0b1010}
+    for ev in p:
+        hel = oracle.me2_hel(oracle.GGTT, ev, card0, AS)
+        for h in range(16):
+            if h not in allowed:
+                assert hel[h] <= 1e-26 * hel.sum()
+        assert min(hel[h] for h in allowed) > 1e-6 * hel.sum()
+    card = configs.card_array()
+    for ev in configs.WORKLOADS["ggtt"].momenta(30):
+        hel = oracle.me2_hel(oracle.GGTT, ev, card, AS)
+        assert np.abs(hel - hel[::-1]).max() <= 1e-13 * hel.sum()

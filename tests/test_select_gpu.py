@@ -1,0 +1,136 @@
+"""GPU parity of the per-event helicity and colour-flow choice (hme_compute_select, C ABI).
+
+Reference: the oracle's |M_h|^2 in the physical-helicity basis (oracle.me2_hel) and its
+colour-ordered amplitudes summed over all spin states (oracle.partial_amps, a basis-
+independent sum), with the running-sum rule stated in include/hme.h.  The choice is an
+integer decided by floating point: the GPU's pick k is accepted when the oracle's running
+sums bracket the target, sum_{j<k} w_j <= r W + tol W and sum_{j<=k} w_j >= r W - tol W with
+w_k > 0; tol = 1e-10 for FP64 (both sides differ by rounding only), 1e-5 with the
+single-precision colour sum and 1e-3 with single-precision amplitudes (the |M|^2 gates).
+In FP64 every pick must also equal the oracle's own.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2507_21039_amd as hme
+from workloads import configs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+CASES = [("eemumu", hme.EEMUMU, 3001), ("ggtt", hme.GGTT, 3001), ("ggttg", hme.GGTTG, 1001),
+         ("ggttgg", hme.GGTTGG, 257)]
+TOL = {hme.FP64: 1e-10, hme.MIXED_PAPER: 1e-5, hme.MIXED_FAST: 1e-3}
+AS = 0.118
+
+
+@pytest.fixture(scope="module")
+def card():
+    return configs.card_array()
+
+
+_ref_cache = {}
+
+
+def reference(key, proc, nevt, card):
+    """Momenta, uniforms and the oracle's per-event helicity and flow weights."""
+    if key not in _ref_cache:
+        p = configs.WORKLOADS[key].momenta(nevt, first_event=1000)
+        rng = np.random.default_rng(17)
+        r_hel, r_col = rng.random(nevt), rng.random(nevt)
+        r_hel[:2] = r_col[:2] = [0.0, np.nextafter(1.0, 0.0)]  # both ends of [0, 1)
+        npar = hme.NPAR[proc]
+        mh = np.array([oracle.me2_hel(proc, ev, card, AS) for ev in p])
+        if proc == hme.EEMUMU:
+            W = np.ones((nevt, 1))
+        else:
+            W = np.zeros((nevt, math.factorial(npar - 2)))
+            for e, ev in enumerate(p):
+                for cfg in range(1 << npar):
+                    W[e] += np.abs(oracle.partial_amps(ev, card, [(cfg >> k) & 1 for k in range(npar)])) ** 2
+        _ref_cache[key] = (p, r_hel, r_col, mh, W)
+    return _ref_cache[key]
+
+
+def first_over(w, r):
+    cum = np.cumsum(w)
+    return int(np.argmax(cum > r * cum[-1]))
+
+
+def bracketed(w, r, k, tol):
+    cum = np.cumsum(w)
+    tot = cum[-1]
+    before = cum[k - 1] if k > 0 else 0.0
+    return w[k] > 0 and before <= r * tot + tol * tot and cum[k] >= r * tot - tol * tot
+
+
+@pytest.mark.parametrize("prec", [hme.FP64, hme.MIXED_FAST, hme.MIXED_PAPER])
+@pytest.mark.parametrize("key,proc,nevt", CASES)
+def test_selection_matches_oracle(card, key, proc, nevt, prec):
+    p, r_hel, r_col, mh, W = reference(key, proc, nevt, card)
+    print(f"[gpu] select {key} nevt={nevt} precision={prec}", flush=True)
+    with hme.Handle(proc, card, prec) as h:
+        good = np.array(h.good_helicities())
+        mom = torch.from_numpy(p).cuda()
+        me_plain = h.compute(mom, alpha_s=AS)
+        me, sh, sc = h.compute_select(mom, torch.from_numpy(r_hel).cuda(), torch.from_numpy(r_col).cuda(), AS)
+        torch.cuda.synchronize()
+    me, sh, sc = me.cpu().numpy(), sh.cpu().numpy(), sc.cpu().numpy()
+    assert np.array_equal(me, me_plain.cpu().numpy())  # the choice leaves |M|^2 bitwise unchanged
+    pos = {int(g): i for i, g in enumerate(good)}
+    tol = TOL[prec]
+    same_h = same_c = 0
+    for e in range(nevt):
+        assert int(sh[e]) in pos, (e, sh[e])
+        kh = pos[int(sh[e])]
+        w = mh[e][good]
+        assert bracketed(w, r_hel[e], kh, tol), (e, kh, first_over(w, r_hel[e]))
+        same_h += kh == first_over(w, r_hel[e])
+        assert 0 <= sc[e] < W.shape[1]
+        assert bracketed(W[e], r_col[e], int(sc[e]), tol), (e, sc[e], first_over(W[e], r_col[e]))
+        same_c += int(sc[e]) == first_over(W[e], r_col[e])
+    if prec == hme.FP64:
+        assert same_h == nevt and same_c == nevt
+    # the ends of [0, 1): the first and the last helicity / flow of nonzero weight
+    assert pos[int(sh[0])] == int(np.flatnonzero(mh[0][good] > 0)[0])
+    assert pos[int(sh[1])] == int(np.flatnonzero(mh[1][good] > 0)[-1])
+
+
+def test_selection_full_size_sampled(card):
+    """gg -> ttbar gg at 2^20 events in FP64, in the benchmark's launch configuration."""
+    w = configs.WORKLOADS["ggttgg"]
+    kind, value = configs.CUT_CODES[w.cut_text]
+    print(f"[gpu] select full size {w.nevt}", flush=True)
+    mom = hme.rambo(w.process, card, w.sqrt_s, w.seed, w.nevt, 0, kind, value)
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    r_hel = torch.rand(w.nevt, dtype=torch.float64, device="cuda", generator=gen)
+    r_col = torch.rand(w.nevt, dtype=torch.float64, device="cuda", generator=gen)
+    with hme.Handle(w.process, card, hme.FP64) as h:
+        good = np.array(h.good_helicities())
+        me, sh, sc = h.compute_select(mom, r_hel, r_col, AS)
+        torch.cuda.synchronize()
+    idx = torch.from_numpy(np.sort(np.random.default_rng(9).choice(w.nevt, 24, replace=False))).cuda()
+    p = mom[idx].cpu().numpy()
+    rh, rc = r_hel[idx].cpu().numpy(), r_col[idx].cpu().numpy()
+    sh, sc = sh[idx].cpu().numpy(), sc[idx].cpu().numpy()
+    pos = {int(g): i for i, g in enumerate(good)}
+    for e in range(len(p)):
+        mh = oracle.me2_hel(w.process, p[e], card, AS)[good]
+        assert pos[int(sh[e])] == first_over(mh, rh[e])
+        Wc = np.zeros(24)
+        for cfg in range(64):
+            Wc += np.abs(oracle.partial_amps(p[e], card, [(cfg >> k) & 1 for k in range(6)])) ** 2
+        assert int(sc[e]) == first_over(Wc, rc[e])
+
+
+def test_selection_unsupported_for_pieces(card):
+    with hme.Handle(hme.GGTTGGG, card, hme.MIXED_FAST) as h:
+        mom = torch.zeros((4, 7, 4), dtype=torch.float64, device="cuda")
+        r = torch.zeros(4, dtype=torch.float64, device="cuda")
+        with pytest.raises(hme.HmeError) as err:
+            h.compute_select(mom, r, r)
+        assert err.value.code == hme.HME_E_UNSUPPORTED
