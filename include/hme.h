@@ -121,8 +121,7 @@ const char* hme_last_error(void);
  *   which the running sum of W_c = sum_h |J_c,h|^2 (squared colour-flow amplitudes summed over
  *   the good helicities) exceeds rnd_col[i] times their total.
  * me2 is bitwise the output of hme_compute.  Device buffers: me2, rnd_* 8-byte aligned,
- * sel_* 4-byte aligned; asynchronous on hip_stream.  Returns HME_E_UNSUPPORTED for
- * HME_GGTTGGG (evaluated in pieces), otherwise as hme_compute. */
+ * sel_* 4-byte aligned; asynchronous on hip_stream.  Errors as hme_compute. */
 int hme_compute_select(hme_handle* h, double alpha_s, int64_t nevt, const double* momenta, const double* rnd_hel,
                        const double* rnd_col, double* me2, int* sel_hel, int* sel_col, void* hip_stream);
 

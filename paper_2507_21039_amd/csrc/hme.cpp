@@ -268,16 +268,11 @@ hipError_t launch_for_handle(const hme_handle* h, int64_t nevt_grid, const int64
 
 extern "C" {
 
-int hme_compute(hme_handle* h, double alpha_s, int64_t nevt, const double* momenta, double* me2, void* hip_stream) {
-  if (!h) return fail(HME_E_ARG, "hme_compute: handle is NULL");
-  if (nevt < 0) return fail(HME_E_ARG, "hme_compute: nevt < 0");
-  if (nevt == 0) return HME_OK;
-  if (!momenta || !me2) return fail(HME_E_ARG, "hme_compute: NULL momenta or me2");
-  if ((reinterpret_cast<uintptr_t>(momenta) | reinterpret_cast<uintptr_t>(me2)) & 7u)
-    return fail(HME_E_ARG, "hme_compute: pointers must be 8-byte aligned");
-  if (!(alpha_s > 0)) return fail(HME_E_ARG, "hme_compute: alpha_s must be positive");
+static int compute_impl(const char* who, hme_handle* h, double alpha_s, int64_t nevt, const double* momenta,
+                        double* me2, void* hip_stream, const hme::SelectArgs& sel) {
+  const std::string w(who);
   DeviceGuard guard(h->device);
-  if (guard.err != hipSuccess) return hip_fail(guard.err, "hme_compute: hipSetDevice");
+  if (guard.err != hipSuccess) return hip_fail(guard.err, (w + ": hipSetDevice").c_str());
   const auto stream = static_cast<hipStream_t>(hip_stream);
   void* ws = nullptr;
   int64_t ws_events = 0;
@@ -287,23 +282,33 @@ int hme_compute(hme_handle* h, double alpha_s, int64_t nevt, const double* momen
     ws_events = nevt < hme::kChunkSubBatch ? nevt : hme::kChunkSubBatch;
     const size_t bytes = (size_t)ws_events * (size_t)hme::handle_ws_bytes_per_event(h);
     if ((e = hipMallocAsync(&ws, bytes, stream)) != hipSuccess)
-      return fail(HME_E_OOM, std::string("hme_compute: workspace: ") + hipGetErrorString(e));
+      return fail(HME_E_OOM, w + ": workspace: " + hipGetErrorString(e));
   }
-  e = hme::launch_for_handle(h, nevt, nullptr, momenta, me2, hme::handle_norm(h, alpha_s), stream, ws, ws_events);
+  e = hme::launch_for_handle(h, nevt, nullptr, momenta, me2, hme::handle_norm(h, alpha_s), stream, ws, ws_events,
+                             sel);
   if (ws) {
     const hipError_t ef = hipFreeAsync(ws, stream);
     if (e == hipSuccess) e = ef;
   }
-  if (e != hipSuccess) return hip_fail(e, "hme_compute: launch");
+  if (e != hipSuccess) return hip_fail(e, (w + ": launch").c_str());
   return HME_OK;
+}
+
+int hme_compute(hme_handle* h, double alpha_s, int64_t nevt, const double* momenta, double* me2, void* hip_stream) {
+  if (!h) return fail(HME_E_ARG, "hme_compute: handle is NULL");
+  if (nevt < 0) return fail(HME_E_ARG, "hme_compute: nevt < 0");
+  if (nevt == 0) return HME_OK;
+  if (!momenta || !me2) return fail(HME_E_ARG, "hme_compute: NULL momenta or me2");
+  if ((reinterpret_cast<uintptr_t>(momenta) | reinterpret_cast<uintptr_t>(me2)) & 7u)
+    return fail(HME_E_ARG, "hme_compute: pointers must be 8-byte aligned");
+  if (!(alpha_s > 0)) return fail(HME_E_ARG, "hme_compute: alpha_s must be positive");
+  return compute_impl("hme_compute", h, alpha_s, nevt, momenta, me2, hip_stream, hme::SelectArgs{});
 }
 
 int hme_compute_select(hme_handle* h, double alpha_s, int64_t nevt, const double* momenta, const double* rnd_hel,
                        const double* rnd_col, double* me2, int* sel_hel, int* sel_col, void* hip_stream) {
   if (!h) return fail(HME_E_ARG, "hme_compute_select: handle is NULL");
   if (nevt < 0) return fail(HME_E_ARG, "hme_compute_select: nevt < 0");
-  if (hme::handle_chunked(h))
-    return fail(HME_E_UNSUPPORTED, "hme_compute_select: not available for a process evaluated in pieces");
   if (nevt == 0) return HME_OK;
   if (!momenta || !me2 || !rnd_hel || !rnd_col || !sel_hel || !sel_col)
     return fail(HME_E_ARG, "hme_compute_select: NULL buffer");
@@ -312,13 +317,8 @@ int hme_compute_select(hme_handle* h, double alpha_s, int64_t nevt, const double
       ((reinterpret_cast<uintptr_t>(sel_hel) | reinterpret_cast<uintptr_t>(sel_col)) & 3u))
     return fail(HME_E_ARG, "hme_compute_select: misaligned buffer");
   if (!(alpha_s > 0)) return fail(HME_E_ARG, "hme_compute_select: alpha_s must be positive");
-  DeviceGuard guard(h->device);
-  if (guard.err != hipSuccess) return hip_fail(guard.err, "hme_compute_select: hipSetDevice");
-  hme::SelectArgs sel{rnd_hel, rnd_col, sel_hel, sel_col};
-  const hipError_t e = hme::launch_for_handle(h, nevt, nullptr, momenta, me2, hme::handle_norm(h, alpha_s),
-                                              static_cast<hipStream_t>(hip_stream), nullptr, 0, sel);
-  if (e != hipSuccess) return hip_fail(e, "hme_compute_select: launch");
-  return HME_OK;
+  return compute_impl("hme_compute_select", h, alpha_s, nevt, momenta, me2, hip_stream,
+                      hme::SelectArgs{rnd_hel, rnd_col, sel_hel, sel_col});
 }
 
 int hme_query(const hme_handle* h, hme_info* info) {

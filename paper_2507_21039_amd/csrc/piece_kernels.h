@@ -113,13 +113,20 @@ __global__ void __launch_bounds__(256)
   if (!per_hel && sub == 0 && ev < nevt) out[ev] = acc * norm;
 }
 
-template <class Proc>
+// Select: also picks one helicity and one colour flow per event (the rule of
+// choose_helicity_and_flow, with up to NPASS helicities per lane): |M_h|^2 of each pass is
+// kept in registers, the flow weights sum_h |J_c,h|^2 are reduced over the wavefront flow by
+// flow and accumulated in LDS.  sel's pointers are offset to the sub-batch's first event.
+template <class Proc, bool Select = false>
 __global__ void __launch_bounds__(256)
     colour_mfma_kernel(const cx<float>* __restrict__ ws, double* __restrict__ out, int64_t nevt, int ngood,
-                       double norm, int per_hel, const int64_t* __restrict__ nevt_dev, int64_t e0) {
+                       double norm, int per_hel, const int64_t* __restrict__ nevt_dev, int64_t e0,
+                       const int* __restrict__ goodhel, SelectArgs sel) {
   constexpr int NCOL = Proc::ncol;
+  constexpr int NPASS = (Proc::nhel + 63) / 64;
   __shared__ __attribute__((aligned(16))) __bf16 nh[ColourTiles<Proc>::words];
   __shared__ __attribute__((aligned(16))) __bf16 nl[ColourTiles<Proc>::words];
+  __shared__ double wflow[Select ? 4 : 1][Select ? NCOL : 1];
   nevt = sub_batch_events(nevt, nevt_dev, e0);
   if ((int64_t)blockIdx.x * 4 >= nevt) return;  // uniform per block
   colour_tiles_fill<Proc>(nh, nl, threadIdx.x, 256);
@@ -130,6 +137,10 @@ __global__ void __launch_bounds__(256)
   if (ev >= nevt) return;  // wave-uniform; no barrier follows
   const cx<float>* w = ws + (size_t)ev * Proc::nslot * ngood;
   double acc = 0.0;
+  [[maybe_unused]] double mpass[Select ? NPASS : 1];
+  if constexpr (Select) {
+    for (int c = lane; c < NCOL; c += 64) wflow[wib][c] = 0.0;
+  }
   for (int g = 0; g < ngood; g += 64) {
     const int k = g + lane;
     const bool valid = k < ngood;
@@ -142,6 +153,67 @@ __global__ void __launch_bounds__(256)
     const float s = colour_sum_wave<Proc>(jamp, NumerLds<Proc>{(const HME_LDS __bf16*)nh, (const HME_LDS __bf16*)nl});
     if (per_hel && valid) out[(size_t)ev * ngood + k] = (double)s;
     acc += valid ? (double)s : 0.0;
+    if constexpr (Select) {
+#pragma unroll
+      for (int q = 0; q < NPASS; ++q)
+        if (q == g / 64) mpass[q] = valid ? (double)s : 0.0;
+      // flow weights: reduce |J_c|^2 over the wavefront, one lane accumulates flow c in LDS
+      // (invalid lanes hold zero jamps)
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c) {
+        double v = (double)jamp[c].r * (double)jamp[c].r + (double)jamp[c].i * (double)jamp[c].i;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == (c & 63)) wflow[wib][c] += v;
+      }
+    }
+  }
+  if constexpr (Select) {
+    const int npass = (ngood + 63) / 64;
+    for (int q = npass; q < NPASS; ++q) mpass[q] = 0.0;
+    // helicity: total, then a running sum over the passes in good-helicity order
+    double tot = 0.0;
+#pragma unroll
+    for (int q = 0; q < NPASS; ++q) tot += mpass[q];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off, 64);
+    const double target_h = sel.rnd_hel[ev] * tot;
+    double carry = 0.0;
+    int kh = -1;
+#pragma unroll
+    for (int q = 0; q < NPASS; ++q) {
+      double cum = mpass[q];
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const double t = __shfl_up(cum, d, 64);
+        if (lane >= d) cum += t;
+      }
+      cum += carry;
+      const uint64_t hit = __ballot(q * 64 + lane < ngood && cum > target_h);
+      if (kh < 0 && hit) kh = q * 64 + __builtin_ctzll(hit);
+      carry = __shfl(cum, 63, 64);
+    }
+    if (kh < 0) kh = ngood - 1;
+    // colour flow: lane 0 runs over the LDS weights in flow order (each written by lane c & 63
+    // of this wavefront: a wave-level barrier orders the writes before the reads)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane == 0) {
+      double wtot = 0.0;
+      for (int c = 0; c < NCOL; ++c) wtot += wflow[wib][c];
+      const double target_c = sel.rnd_col[ev] * wtot;
+      double cum = 0.0;
+      int kc = -1, last = 0;
+      for (int c = 0; c < NCOL; ++c) {
+        const double v = wflow[wib][c];
+        cum += v;
+        if (kc < 0 && cum > target_c) kc = c;
+        if (v > 0) last = c;
+      }
+      sel.sel_hel[ev] = goodhel[kh];
+      sel.sel_col[ev] = kc < 0 ? last : kc;
+    }
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
@@ -174,14 +246,20 @@ template <class Proc, class Chunk> hipError_t launch_chunk(const ChunkArgs& a) {
 // colour sum of the workspace: on the matrix cores (mfma != 0) or on the vector ALUs
 template <class Proc>
 hipError_t launch_colour(const cx<float>* ws, double* out, int64_t nevt, int ngood, double norm, int per_hel,
-                         const int64_t* nevt_dev, int64_t e0, hipStream_t s, int mfma) {
+                         const int64_t* nevt_dev, int64_t e0, hipStream_t s, int mfma, const int* goodhel = nullptr,
+                         const SelectArgs& sel = SelectArgs{}) {
   constexpr int LPE = chunk_lpe<Proc>(), EPB = 256 / LPE;
   const int64_t blocks = (nevt + EPB - 1) / EPB;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  if (sel.sel_hel && (!mfma || per_hel || !goodhel || ngood > Proc::nhel)) return hipErrorInvalidValue;
   if (mfma) {
     static_assert(LPE == 64, "the matrix-core colour sum takes one event per wavefront");
-    colour_mfma_kernel<Proc><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(ws, out, nevt, ngood, norm, per_hel,
-                                                                           nevt_dev, e0);
+    if (sel.sel_hel)
+      colour_mfma_kernel<Proc, true><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(ws, out, nevt, ngood, norm, per_hel,
+                                                                                   nevt_dev, e0, goodhel, sel);
+    else
+      colour_mfma_kernel<Proc, false><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(ws, out, nevt, ngood, norm,
+                                                                                    per_hel, nevt_dev, e0, goodhel, sel);
   } else {
     colour_kernel<Proc, LPE><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(ws, out, nevt, ngood, norm, per_hel,
                                                                            nevt_dev, e0);

@@ -19,7 +19,7 @@ constexpr int kColourOnMatrixCores = 1;
 // event count from device memory and sub-batches past its end do nothing.
 static hipError_t run_pieces(const double* mom, double* out, int64_t nevt, const int64_t* nevt_dev,
                              const int* goodhel, int ngood, const ProcParams& prm, double norm, int per_hel,
-                             cx<float>* ws, int64_t ws_events, hipStream_t s) {
+                             cx<float>* ws, int64_t ws_events, hipStream_t s, const SelectArgs& sel = SelectArgs{}) {
   for (int64_t e0 = 0; e0 < nevt; e0 += ws_events) {
     const int64_t n = nevt - e0 < ws_events ? nevt - e0 : ws_events;
     const ChunkArgs c{mom + e0 * P7::npar * 4, ws, n, goodhel, ngood, prm, s, nevt_dev, e0};
@@ -27,8 +27,10 @@ static hipError_t run_pieces(const double* mom, double* out, int64_t nevt, const
       const hipError_t e = chunks_ggttggg[k](c);
       if (e != hipSuccess) return e;
     }
+    SelectArgs sub{};
+    if (sel.sel_hel) sub = SelectArgs{sel.rnd_hel + e0, sel.rnd_col + e0, sel.sel_hel + e0, sel.sel_col + e0};
     const hipError_t e = launch_colour<P7>(ws, out + (per_hel ? e0 * ngood : e0), n, ngood, norm, per_hel,
-                                           nevt_dev, e0, s, kColourOnMatrixCores);
+                                           nevt_dev, e0, s, kColourOnMatrixCores, goodhel, sub);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -38,7 +40,7 @@ static hipError_t run_pieces(const double* mom, double* out, int64_t nevt, const
 hipError_t launch_me2_ggttggg(const LaunchArgs& a, int precision) {
   if (precision != 1 || !a.ws || a.ws_events <= 0) return hipErrorInvalidValue;
   return run_pieces(a.mom, a.out, a.nevt, a.nevt_dev, a.goodhel, a.ngood, a.prm, a.norm, 0,
-                    static_cast<cx<float>*>(a.ws), a.ws_events, a.stream);
+                    static_cast<cx<float>*>(a.ws), a.ws_events, a.stream, a.sel);
 }
 
 // |M_h|^2 of every helicity for nev events (set-up only; synchronous, own workspace)
