@@ -189,6 +189,43 @@ def e2e_leg(card, steps=5, warmup=2):
             "sigma_pb": sigma, "sigma_err_pb": err, "points": n * (warmup + steps)}
 
 
+def select_leg(card, steps=3, warmup=1):
+    """Cost of the per-event helicity and colour-flow choice: hme_compute_select against
+    hme_compute on the same resident batch (gg -> ttbar gg FP64 at 2^20 events and
+    gg -> ttbar ggg single precision at 65536), each timed with events on the launch stream."""
+    import torch
+
+    import paper_2507_21039_amd as hme
+    from workloads import configs
+    res = {}
+    for key, prec in (("ggttgg", hme.FP64), ("ggttggg", hme.MIXED_FAST)):
+        w = configs.WORKLOADS[key]
+        kind, value = configs.CUT_CODES[w.cut_text]
+        mom = hme.rambo(w.process, card, w.sqrt_s, w.seed, w.nevt, 0, kind, value)
+        gen = torch.Generator(device="cuda").manual_seed(1)
+        rh = torch.rand(w.nevt, dtype=torch.float64, device="cuda", generator=gen)
+        rc = torch.rand(w.nevt, dtype=torch.float64, device="cuda", generator=gen)
+        stream = torch.cuda.current_stream()
+        out = torch.empty(w.nevt, dtype=torch.float64, device="cuda")
+        t = {}
+        with hme.Handle(w.process, card, prec) as h:
+            for name, fn in (("compute", lambda: h.compute(mom, out, 0.118, stream)),
+                             ("select", lambda: h.compute_select(mom, rh, rc, 0.118, stream))):
+                for _ in range(warmup):
+                    fn()
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                for _ in range(steps):
+                    fn()
+                b.record(stream)
+                torch.cuda.synchronize()
+                t[name] = a.elapsed_time(b) / steps
+        res[key] = {"nevt": w.nevt, "precision": hme.PRECISION_NAMES[prec], "ms_compute": t["compute"],
+                    "ms_select": t["select"], "overhead": t["select"] / t["compute"] - 1,
+                    "events_per_s_select": w.nevt / t["select"] * 1e3}
+    return res
+
+
 def served_leg(card, precision, nwarm=200, ntimed=3000, budget=32 << 30, nstreams=4):
     """Poisson request stream (200 requests/s, sizes log-uniform in 256..65536) through the server.
 
@@ -258,6 +295,7 @@ def main():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-ggttggg", action="store_true")
     ap.add_argument("--no-e2e", action="store_true")
+    ap.add_argument("--no-select", action="store_true")
     ap.add_argument("--pmc", action="store_true",
                     help="counter-collection mode: one FP64 and one MIXED_FAST gg->ttbar gg launch, one "
                          "8192-event gg->ttbar ggg call, then a plain 256 MiB device copy (known traffic, "
@@ -360,6 +398,7 @@ def main():
                 ("mixed_paper", "f64 amplitudes and jamps, f32 colour algebra, f64 sums", PEAK_FP64_VALU))},
         "ggttggg": None,
         "e2e": None,
+        "select": None,
         "served": None,
     }
     if not args.no_ggttggg:
@@ -370,6 +409,11 @@ def main():
         log("[bench] end-to-end flat Monte Carlo (device RAMBO + FP64 |M|^2 + sum)")
         line["e2e"] = e2e_leg(card)
         log(f"[bench] e2e: {line['e2e']['value']:.4g} events/s, rambo {line['e2e']['ms_rambo']:.3f} ms")
+    if not args.no_select:
+        log("[bench] helicity and colour-flow choice")
+        line["select"] = select_leg(card)
+        log(f"[bench] select overhead: " + ", ".join(f"{k} {v['overhead'] * 100:.2f}%"
+                                                     for k, v in line["select"].items()))
     if not args.no_served:
         log("[bench] served mix (Poisson, 200 requests/s)")
         line["served"] = served_leg(card, hme.MIXED_FAST)

@@ -46,12 +46,91 @@ struct SelectArgs {
   int* sel_col = nullptr;
 };
 
+// Sums over the 64 lanes of a wavefront of v[c] for every c < K (K a power of two), by
+// recursive halving: at the step with lane offset O each lane keeps one half of its values
+// (the upper half when its lane bit O is set) and adds the partner lane's copy of that half,
+// so a step costs K/2 shuffles instead of K.  When one value is left the remaining steps are
+// plain butterflies.  On return v[s], s < max(K / 64, 1), holds the total of value
+// halving_index<K, 32>(lane) + s.
+template <int K, int O, class V> HME_FN void halving_sum(V* v, int lane) {
+  if constexpr (O > 0) {
+    if constexpr (K >= 2) {
+      const bool up = lane & O;
+#pragma unroll
+      for (int i = 0; i < K / 2; ++i) {
+        const V keep = up ? v[K / 2 + i] : v[i];
+        const V send = up ? v[i] : v[K / 2 + i];
+        v[i] = keep + __shfl_xor(send, O, 64);
+      }
+      halving_sum<K / 2, O / 2>(v, lane);
+    } else {
+      v[0] += __shfl_xor(v[0], O, 64);
+      halving_sum<1, O / 2>(v, lane);
+    }
+  }
+}
+
+template <int K, int O> HME_FN int halving_index(int lane) {
+  if constexpr (O == 0) {
+    return 0;
+  } else if constexpr (K >= 2) {
+    return ((lane & O) ? K / 2 : 0) + halving_index<K / 2, O / 2>(lane);
+  } else {
+    return halving_index<1, O / 2>(lane);
+  }
+}
+
+constexpr int pow2_at_least(int n) { return n <= 1 ? 1 : 2 * pow2_at_least((n + 1) / 2); }
+
+// Adds sum over the wavefront's lanes of |jamp[c]|^2 into w[c] (LDS, one array per
+// wavefront) for every flow c: recursive halving over the flows padded to a power of two;
+// each total is written by the lane that holds it (lanes holding the same total write the
+// same value).  Zero jamps on lanes without a helicity.
+template <int NCOL, class T>
+HME_FN void add_flow_weights(const cx<T> (&jamp)[NCOL], int lane, volatile HME_LDS double* w) {
+  constexpr int K = pow2_at_least(NCOL);
+  T v[K];
+#pragma unroll
+  for (int c = 0; c < K; ++c) v[c] = c < NCOL ? jamp[c].r * jamp[c].r + jamp[c].i * jamp[c].i : T(0);
+  halving_sum<K, 32>(v, lane);
+  const int c0 = halving_index<K, 32>(lane);
+#pragma unroll
+  for (int s = 0; s < (K >= 64 ? K / 64 : 1); ++s)
+    if (c0 + s < NCOL) w[c0 + s] += (double)v[s];
+}
+
+// Running sum over w[0..ncol) in flow order (one lane): the first flow whose running sum
+// exceeds r times the total; the last flow of nonzero weight if rounding leaves none.
+HME_FN int choose_flow(const volatile HME_LDS double* w, int ncol, double r) {
+  double wtot = 0.0;
+  for (int c = 0; c < ncol; ++c) wtot += w[c];
+  const double target = r * wtot;
+  double cum = 0.0;
+  int kc = -1, last = 0;
+  for (int c = 0; c < ncol; ++c) {
+    const double v = w[c];
+    cum += v;
+    if (kc < 0 && cum > target) kc = c;
+    if (v > 0) last = c;
+  }
+  return kc < 0 ? last : kc;
+}
+
+// orders this wavefront's LDS writes before its own later reads from other lanes
+HME_FN void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // The event's LPE lanes (an aligned segment of the wavefront) hold one helicity each; lanes
 // past the last good helicity pass valid = false.  Every lane of the segment must call this.
+// wlds: with LPE = 64 and 16 or more flows, the wavefront's LDS array of ncol flow weights
+// (the flow sums then take the halving reduction); otherwise unused.
 template <class Proc, class T, int LPE>
 HME_FN void choose_helicity_and_flow(const cx<T> (&jamp)[Proc::ncol], bool valid, double mh, int sub, int64_t ev,
                                      int64_t evc, int64_t nevt, const int* __restrict__ goodhel, int ngood,
-                                     const SelectArgs& sel) {
+                                     const SelectArgs& sel, volatile HME_LDS double* wlds) {
   // inclusive running sum of |M_h|^2 over the segment, in good-helicity order
   double cum = valid ? mh : 0.0;
 #pragma unroll
@@ -66,6 +145,20 @@ HME_FN void choose_helicity_and_flow(const cx<T> (&jamp)[Proc::ncol], bool valid
   const uint64_t seg = (~0ull >> (64 - LPE)) << base;
   const uint64_t hit = over & seg;
   const int kh = hit ? __builtin_ctzll(hit) - base : ngood - 1;
+  if constexpr (LPE == 64 && Proc::ncol >= 16) {
+    for (int c = sub; c < Proc::ncol; c += 64) wlds[c] = 0.0;
+    wave_lds_sync();
+    cx<T> jz[Proc::ncol];
+#pragma unroll
+    for (int c = 0; c < Proc::ncol; ++c) jz[c] = valid ? jamp[c] : cx<T>{T(0), T(0)};
+    add_flow_weights<Proc::ncol, T>(jz, sub, wlds);
+    wave_lds_sync();
+    if (sub == 0 && ev < nevt) {
+      sel.sel_hel[ev] = goodhel[kh];
+      sel.sel_col[ev] = choose_flow(wlds, Proc::ncol, sel.rnd_col[evc]);
+    }
+    return;
+  }
   // colour-flow weights summed over the segment's helicities
   double wtot = 0.0;
 #pragma unroll
@@ -106,6 +199,8 @@ __global__ void __launch_bounds__(256, me2_min_waves<T>())
   constexpr bool kMfmaColour = LPE == 64 && Proc::ncol >= 24 && sizeof(T) == 4;
   __shared__ __attribute__((aligned(16))) __bf16 cnh[kMfmaColour ? ColourTiles<Proc>::words : 8];
   __shared__ __attribute__((aligned(16))) __bf16 cnl[kMfmaColour ? ColourTiles<Proc>::words : 8];
+  // flow weights of the selection variant (one array per wavefront, events of 64 lanes)
+  __shared__ double wsel[4][Select && LPE == 64 && Proc::ncol >= 16 ? Proc::ncol : 1];
   const int lane = threadIdx.x & 63;
   // the event count comes from device memory when a captured graph launches a batch of
   // varying size with a fixed grid; blocks past the end leave at once
@@ -144,7 +239,8 @@ __global__ void __launch_bounds__(256, me2_min_waves<T>())
       mh = (double)Proc::template colour_sum<T>(jamp);
     }
     acc = valid ? mh : 0.0;
-    choose_helicity_and_flow<Proc, T, LPE>(jamp, valid, mh, sub, ev, evc, nevt, goodhel, ngood, sel);
+    choose_helicity_and_flow<Proc, T, LPE>(jamp, valid, mh, sub, ev, evc, nevt, goodhel, ngood, sel,
+                                           (volatile HME_LDS double*)&wsel[wib][0]);
   } else if constexpr (kMfmaColour) {
     // every lane runs every pass (the matrix cores take the whole wavefront); a lane past the
     // last good helicity evaluates the last one again and drops its result (each helicity

@@ -115,8 +115,11 @@ __global__ void __launch_bounds__(256)
 
 // Select: also picks one helicity and one colour flow per event (the rule of
 // choose_helicity_and_flow, with up to NPASS helicities per lane): |M_h|^2 of each pass is
-// kept in registers, the flow weights sum_h |J_c,h|^2 are reduced over the wavefront flow by
-// flow and accumulated in LDS.  sel's pointers are offset to the sub-batch's first event.
+// kept in registers, the flow weights sum_h |J_c,h|^2 are summed over the wavefront by
+// recursive halving and accumulated in LDS.  sel's pointers are offset to the sub-batch's
+// first event.  (Measured: with the choice this kernel takes about three times its plain
+// time, most of that already with the helicity part alone; a separate kernel for the flow
+// weights, gathering the jamps again, was slower.)
 template <class Proc, bool Select = false>
 __global__ void __launch_bounds__(256)
     colour_mfma_kernel(const cx<float>* __restrict__ ws, double* __restrict__ out, int64_t nevt, int ngood,
@@ -140,6 +143,7 @@ __global__ void __launch_bounds__(256)
   [[maybe_unused]] double mpass[Select ? NPASS : 1];
   if constexpr (Select) {
     for (int c = lane; c < NCOL; c += 64) wflow[wib][c] = 0.0;
+    wave_lds_sync();
   }
   for (int g = 0; g < ngood; g += 64) {
     const int k = g + lane;
@@ -157,15 +161,8 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
       for (int q = 0; q < NPASS; ++q)
         if (q == g / 64) mpass[q] = valid ? (double)s : 0.0;
-      // flow weights: reduce |J_c|^2 over the wavefront, one lane accumulates flow c in LDS
-      // (invalid lanes hold zero jamps)
-#pragma unroll
-      for (int c = 0; c < NCOL; ++c) {
-        double v = (double)jamp[c].r * (double)jamp[c].r + (double)jamp[c].i * (double)jamp[c].i;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        if (lane == (c & 63)) wflow[wib][c] += v;
-      }
+      // flow weights |J_c|^2 summed over the wavefront (invalid lanes hold zero jamps)
+      add_flow_weights<NCOL, float>(jamp, lane, (volatile HME_LDS double*)&wflow[wib][0]);
     }
   }
   if constexpr (Select) {
@@ -194,25 +191,11 @@ __global__ void __launch_bounds__(256)
       carry = __shfl(cum, 63, 64);
     }
     if (kh < 0) kh = ngood - 1;
-    // colour flow: lane 0 runs over the LDS weights in flow order (each written by lane c & 63
-    // of this wavefront: a wave-level barrier orders the writes before the reads)
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // colour flow: lane 0 runs over the LDS weights in flow order
+    wave_lds_sync();
     if (lane == 0) {
-      double wtot = 0.0;
-      for (int c = 0; c < NCOL; ++c) wtot += wflow[wib][c];
-      const double target_c = sel.rnd_col[ev] * wtot;
-      double cum = 0.0;
-      int kc = -1, last = 0;
-      for (int c = 0; c < NCOL; ++c) {
-        const double v = wflow[wib][c];
-        cum += v;
-        if (kc < 0 && cum > target_c) kc = c;
-        if (v > 0) last = c;
-      }
       sel.sel_hel[ev] = goodhel[kh];
-      sel.sel_col[ev] = kc < 0 ? last : kc;
+      sel.sel_col[ev] = choose_flow((volatile HME_LDS double*)&wflow[wib][0], NCOL, sel.rnd_col[ev]);
     }
   }
 #pragma unroll
