@@ -28,14 +28,14 @@ PEAK_HBM = 8.0e12
 # counter reads for a plain 256 MiB device copy.  Valid only for the kernel sources it was taken
 # on (sha256 prefix of me2_kernels.h + colour_mfma.h + helas.h + procs/ggttgg.h); otherwise
 # traffic is null.
-TRAFFIC = {"source_sha": "79f35659eaaec3ca", "nevt": 1048576,
-           "fetch_kib": 198692.4375, "write_kib": 8192.0, "fetch_factor": 262144 / 131088.6875, "write_factor": 1.0}
+TRAFFIC = {"source_sha": "ae2a13a1dbed4c0c", "nevt": 1048576,
+           "fetch_kib": 198688.875, "write_kib": 8192.0, "fetch_factor": 262144 / 131089.0, "write_factor": 1.0}
 
 # VALU and MFMA instruction counters of the same launches (profiles/me2_ggttgg_1M_valu_counters.md),
 # wave instructions summed over the device: FLOPs = 64 lanes x (2 FMA + ADD + MUL + TRANS) plus
 # 512 per MFMA "MOPS" unit (the counter's own scale).
 COUNTERS = {
-    "source_sha": "79f35659eaaec3ca", "nevt": 1048576,
+    "source_sha": "ae2a13a1dbed4c0c", "nevt": 1048576,
     "fp64": {"FMA_F64": 12922650624, "ADD_F64": 7019167744, "MUL_F64": 10643046400, "TRANS_F64": 39845888,
              "VALU": 32933675008},
     "mixed_fast": {"FMA_F32": 9925820416, "ADD_F32": 6207569920, "MUL_F32": 8492417024, "TRANS_F32": 0,
