@@ -190,8 +190,8 @@ def e2e_leg(card, steps=5, warmup=2):
 
 
 def select_leg(card, steps=3, warmup=1):
-    """Cost of the per-event helicity and colour-flow choice: hme_compute_select against
-    hme_compute on the same resident batch (gg -> ttbar gg FP64 at 2^20 events and
+    """Cost of the per-event helicity and colour-flow choice (hme_compute_select) and of a
+    strong coupling per event (hme_compute_alphas) against hme_compute on the same resident batch (gg -> ttbar gg FP64 at 2^20 events and
     gg -> ttbar ggg single precision at 65536), each timed with events on the launch stream."""
     import torch
 
@@ -209,8 +209,10 @@ def select_leg(card, steps=3, warmup=1):
         out = torch.empty(w.nevt, dtype=torch.float64, device="cuda")
         t = {}
         with hme.Handle(w.process, card, prec) as h:
+            alphas = 0.1 + 0.05 * rh  # one strong coupling per event
             for name, fn in (("compute", lambda: h.compute(mom, out, 0.118, stream)),
-                             ("select", lambda: h.compute_select(mom, rh, rc, 0.118, stream))):
+                             ("select", lambda: h.compute_select(mom, rh, rc, 0.118, stream)),
+                             ("alphas", lambda: h.compute_alphas(mom, alphas, out, stream))):
                 for _ in range(warmup):
                     fn()
                 a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -222,6 +224,7 @@ def select_leg(card, steps=3, warmup=1):
                 t[name] = a.elapsed_time(b) / steps
         res[key] = {"nevt": w.nevt, "precision": hme.PRECISION_NAMES[prec], "ms_compute": t["compute"],
                     "ms_select": t["select"], "overhead": t["select"] / t["compute"] - 1,
+                    "ms_per_event_alpha_s": t["alphas"], "overhead_per_event_alpha_s": t["alphas"] / t["compute"] - 1,
                     "events_per_s_select": w.nevt / t["select"] * 1e3}
     return res
 

@@ -109,6 +109,14 @@ int hme_destroy(hme_handle* h);
 /* Message describing the calling thread's most recent failure ("" if none). */
 const char* hme_last_error(void);
 
+/* Same as hme_compute with a strong coupling per event (running alpha_s evaluated by the
+ * caller at each event's scale): alpha_s is a device array of nevt doubles (8-byte aligned).
+ * Event i gets |M|^2 computed with g_s = 1 times (4 pi alpha_s[i])^(n/2) for a g_s^n
+ * coupling factor of |M|^2 (equal to hme_compute at that scalar alpha_s up to the rounding
+ * of the last product).  Values of alpha_s[i] are not checked.  Errors as hme_compute. */
+int hme_compute_alphas(hme_handle* h, const double* alpha_s, int64_t nevt, const double* momenta, double* me2,
+                       void* hip_stream);
+
 /* Same as hme_compute, and also picks one helicity and one colour flow per event, the
  * information an event generator keeps with each unweighted event (the paper's section
  * "Event generation interface": the Bridge returns them with |M|^2).

@@ -27,7 +27,7 @@ HME_OK, HME_E_ARG, HME_E_HIP, HME_E_OOM, HME_E_BUDGET, HME_E_TIMEOUT, HME_E_UNSU
 
 EXPORTED = ("hme_create", "hme_compute", "hme_query", "hme_good_helicities", "hme_destroy", "hme_last_error",
             "hme_server_create", "hme_submit", "hme_wait", "hme_wait_timed", "hme_server_stats_get",
-            "hme_server_destroy", "hme_rambo", "hme_weighted_sum", "hme_compute_select")
+            "hme_server_destroy", "hme_rambo", "hme_weighted_sum", "hme_compute_select", "hme_compute_alphas")
 
 
 class SmCard(ctypes.Structure):
@@ -88,9 +88,11 @@ def lib():
                                 ctypes.c_int64, ctypes.c_int, ctypes.c_double, vp, vp, vp]
         L.hme_weighted_sum.argtypes = [vp, vp, ctypes.c_int64, vp, vp]
         L.hme_compute_select.argtypes = [vp, ctypes.c_double, ctypes.c_int64, vp, vp, vp, vp, vp, vp, vp]
+        L.hme_compute_alphas.argtypes = [vp, vp, ctypes.c_int64, vp, vp, vp]
         for name in ("hme_create", "hme_compute", "hme_query", "hme_good_helicities", "hme_destroy",
                      "hme_server_create", "hme_submit", "hme_wait", "hme_wait_timed", "hme_server_stats_get",
-                     "hme_server_destroy", "hme_rambo", "hme_weighted_sum", "hme_compute_select"):
+                     "hme_server_destroy", "hme_rambo", "hme_weighted_sum", "hme_compute_select",
+                     "hme_compute_alphas"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -200,6 +202,24 @@ class Handle:
             raise ValueError("out must be a contiguous float64 tensor on the momenta's device")
         s = stream if stream is not None else torch.cuda.current_stream(momenta.device)
         self.compute_ptr(alpha_s, n, momenta.data_ptr(), out.data_ptr(), s.cuda_stream)
+        return out
+
+    def compute_alphas(self, momenta, alpha_s, out=None, stream=None):
+        """|M|^2 with one alpha_s per event (hme_compute_alphas); alpha_s: float64 GPU tensor [nevt]."""
+        import torch
+        if momenta.device.type != "cuda" or momenta.dtype != torch.float64 or not momenta.is_contiguous():
+            raise ValueError("momenta must be a contiguous float64 GPU tensor")
+        if momenta.dim() != 3 or momenta.shape[1] != NPAR[self.process] or momenta.shape[2] != 4:
+            raise ValueError(f"momenta must be [nevt, {NPAR[self.process]}, 4]")
+        n = momenta.shape[0]
+        _f64_gpu(alpha_s, n, "alpha_s")
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=momenta.device)
+        _f64_gpu(out, n, "out")
+        s = stream if stream is not None else torch.cuda.current_stream(momenta.device)
+        _check(lib().hme_compute_alphas(self._h, ctypes.c_void_p(alpha_s.data_ptr()), n,
+                                        ctypes.c_void_p(momenta.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                        ctypes.c_void_p(s.cuda_stream)))
         return out
 
     def compute_select(self, momenta, rnd_hel, rnd_col, alpha_s: float = 0.118, stream=None):

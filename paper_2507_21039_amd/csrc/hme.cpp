@@ -234,6 +234,24 @@ int hme_create(int process, const hme_sm_card* card, int precision, int device, 
 
 namespace hme {
 
+// me2[i] *= (4 pi alpha_s[i])^power, one thread per event
+__global__ void __launch_bounds__(256)
+    alpha_scale_kernel(double* __restrict__ me2, const double* __restrict__ alpha_s, int64_t nevt, int power) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nevt) return;
+  const double gs2 = 4 * 3.14159265358979323846 * alpha_s[i];
+  double f = 1.0;
+  for (int k = 0; k < power; ++k) f *= gs2;
+  me2[i] *= f;
+}
+
+hipError_t launch_alpha_scale(double* me2, const double* alpha_s, int64_t nevt, int power, hipStream_t s) {
+  const int64_t blocks = (nevt + 255) / 256;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  alpha_scale_kernel<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(me2, alpha_s, nevt, power);
+  return hipGetLastError();
+}
+
 double handle_norm(const hme_handle* h, double alpha_s) {
   const double pi = 3.14159265358979323846;
   const double gs2 = 4 * pi * alpha_s;
@@ -268,7 +286,7 @@ hipError_t launch_for_handle(const hme_handle* h, int64_t nevt_grid, const int64
 
 extern "C" {
 
-static int compute_impl(const char* who, hme_handle* h, double alpha_s, int64_t nevt, const double* momenta,
+static int compute_impl(const char* who, hme_handle* h, double norm, int64_t nevt, const double* momenta,
                         double* me2, void* hip_stream, const hme::SelectArgs& sel) {
   const std::string w(who);
   DeviceGuard guard(h->device);
@@ -284,8 +302,7 @@ static int compute_impl(const char* who, hme_handle* h, double alpha_s, int64_t 
     if ((e = hipMallocAsync(&ws, bytes, stream)) != hipSuccess)
       return fail(HME_E_OOM, w + ": workspace: " + hipGetErrorString(e));
   }
-  e = hme::launch_for_handle(h, nevt, nullptr, momenta, me2, hme::handle_norm(h, alpha_s), stream, ws, ws_events,
-                             sel);
+  e = hme::launch_for_handle(h, nevt, nullptr, momenta, me2, norm, stream, ws, ws_events, sel);
   if (ws) {
     const hipError_t ef = hipFreeAsync(ws, stream);
     if (e == hipSuccess) e = ef;
@@ -302,7 +319,27 @@ int hme_compute(hme_handle* h, double alpha_s, int64_t nevt, const double* momen
   if ((reinterpret_cast<uintptr_t>(momenta) | reinterpret_cast<uintptr_t>(me2)) & 7u)
     return fail(HME_E_ARG, "hme_compute: pointers must be 8-byte aligned");
   if (!(alpha_s > 0)) return fail(HME_E_ARG, "hme_compute: alpha_s must be positive");
-  return compute_impl("hme_compute", h, alpha_s, nevt, momenta, me2, hip_stream, hme::SelectArgs{});
+  return compute_impl("hme_compute", h, hme::handle_norm(h, alpha_s), nevt, momenta, me2, hip_stream,
+                      hme::SelectArgs{});
+}
+
+int hme_compute_alphas(hme_handle* h, const double* alpha_s, int64_t nevt, const double* momenta, double* me2,
+                       void* hip_stream) {
+  if (!h) return fail(HME_E_ARG, "hme_compute_alphas: handle is NULL");
+  if (nevt < 0) return fail(HME_E_ARG, "hme_compute_alphas: nevt < 0");
+  if (nevt == 0) return HME_OK;
+  if (!momenta || !me2 || !alpha_s) return fail(HME_E_ARG, "hme_compute_alphas: NULL buffer");
+  if ((reinterpret_cast<uintptr_t>(momenta) | reinterpret_cast<uintptr_t>(me2) | reinterpret_cast<uintptr_t>(alpha_s)) &
+      7u)
+    return fail(HME_E_ARG, "hme_compute_alphas: pointers must be 8-byte aligned");
+  // |M|^2 without the coupling (g_s = 1), then each event times (4 pi alpha_s[i])^(power / 2)
+  const int rc = compute_impl("hme_compute_alphas", h, 1.0 / (h->info.iden * h->info.colour_denom), nevt, momenta,
+                              me2, hip_stream, hme::SelectArgs{});
+  if (rc != HME_OK) return rc;
+  const hipError_t e = hme::launch_alpha_scale(me2, alpha_s, nevt, h->info.gs_power / 2,
+                                               static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return hip_fail(e, "hme_compute_alphas: launch");
+  return HME_OK;
 }
 
 int hme_compute_select(hme_handle* h, double alpha_s, int64_t nevt, const double* momenta, const double* rnd_hel,
@@ -317,7 +354,7 @@ int hme_compute_select(hme_handle* h, double alpha_s, int64_t nevt, const double
       ((reinterpret_cast<uintptr_t>(sel_hel) | reinterpret_cast<uintptr_t>(sel_col)) & 3u))
     return fail(HME_E_ARG, "hme_compute_select: misaligned buffer");
   if (!(alpha_s > 0)) return fail(HME_E_ARG, "hme_compute_select: alpha_s must be positive");
-  return compute_impl("hme_compute_select", h, alpha_s, nevt, momenta, me2, hip_stream,
+  return compute_impl("hme_compute_select", h, hme::handle_norm(h, alpha_s), nevt, momenta, me2, hip_stream,
                       hme::SelectArgs{rnd_hel, rnd_col, sel_hel, sel_col});
 }
 

@@ -63,3 +63,11 @@ def test_phase_space_argument_errors_without_gpu():
     assert L.hme_weighted_sum(buf, buf, -1, buf, None) == hme.HME_E_ARG
     assert L.hme_weighted_sum(buf, buf, 10, None, None) == hme.HME_E_ARG
     assert L.hme_weighted_sum(None, buf, 10, buf, None) == hme.HME_E_ARG
+
+
+@pytest.mark.skipif(not os.path.exists(hme.LIB_PATH), reason="libhme.so not built")
+def test_alphas_and_select_argument_errors_without_gpu():
+    L = hme.lib()
+    buf = ctypes.c_void_p(8)
+    assert L.hme_compute_alphas(None, buf, 10, buf, buf, None) == hme.HME_E_ARG
+    assert L.hme_compute_select(None, 0.118, 10, buf, buf, buf, buf, buf, buf, None) == hme.HME_E_ARG
