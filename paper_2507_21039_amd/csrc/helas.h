@@ -41,6 +41,21 @@ template <class T> HME_FN cx<T> operator*(cx<T> a, cx<T> b) {
 }
 template <class T> HME_FN cx<T> operator*(T s, cx<T> a) { return {s * a.r, s * a.i}; }
 template <class T> HME_FN cx<T> mul_i(cx<T> a) { return {-a.i, a.r}; }  // i * a
+
+// Fused multiply-adds: sums of products are written as chains of these so that each term
+// after the first costs FMAs only (the vertex routines are bound by instruction issue).
+HME_FN double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+HME_FN float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+// acc + a b
+template <class T> HME_FN cx<T> cfma(cx<T> a, cx<T> b, cx<T> acc) {
+  return {fmadd(a.r, b.r, fmadd(-a.i, b.i, acc.r)), fmadd(a.r, b.i, fmadd(a.i, b.r, acc.i))};
+}
+// acc - a b
+template <class T> HME_FN cx<T> cfms(cx<T> a, cx<T> b, cx<T> acc) {
+  return {fmadd(-a.r, b.r, fmadd(a.i, b.i, acc.r)), fmadd(-a.r, b.i, fmadd(-a.i, b.r, acc.i))};
+}
+// acc + s a, s real
+template <class T> HME_FN cx<T> rfma(T s, cx<T> a, cx<T> acc) { return {fmadd(s, a.r, acc.r), fmadd(s, a.i, acc.i)}; }
 template <class T> HME_FN cx<T> conj(cx<T> a) { return {a.r, -a.i}; }
 template <class T, class U> HME_FN cx<T> cast(cx<U> a) { return {T(a.r), T(a.i)}; }
 
@@ -62,11 +77,11 @@ template <class T, class U> HME_FN vw4<T> cast(const vw4<U>& a) {
 
 // Minkowski product of two complex vectors (bilinear, no conjugation)
 template <class T> HME_FN cx<T> mdot(const vw4<T>& a, const vw4<T>& b) {
-  return a.c[0] * b.c[0] - a.c[1] * b.c[1] - a.c[2] * b.c[2] - a.c[3] * b.c[3];
+  return cfms(a.c[3], b.c[3], cfms(a.c[2], b.c[2], cfms(a.c[1], b.c[1], a.c[0] * b.c[0])));
 }
 // Minkowski product of a real vector with a complex vector
 template <class T> HME_FN cx<T> mdot(const T* q, const vw4<T>& a) {
-  return q[0] * a.c[0] - q[1] * a.c[1] - q[2] * a.c[2] - q[3] * a.c[3];
+  return rfma(-q[3], a.c[3], rfma(-q[2], a.c[2], rfma(-q[1], a.c[1], q[0] * a.c[0])));
 }
 
 // ------------------------------------------------------------------ external states
@@ -176,11 +191,16 @@ HME_FN vw4<double> vxxxxx(const double* k, int lam, int nsv) {
 // sigma.V = [[vm, -vtb], [-vt, vp]] and sigmabar.V = [[vp, vtb], [vt, vm]].
 
 // Amplitude fbar V-slash f (ALOHA-style "FFV1_0").
+// Grouped by the vector's components: vm (fb0 f2 + fb3 f1) + vp (fb1 f3 + fb2 f0)
+// + vtb (fb2 f1 - fb0 f3) + vt (fb3 f0 - fb1 f2).
 template <class T> HME_FN cx<T> ffv_amp(const sp4<T>& fb, const sp4<T>& f, const vw4<T>& V) {
   const cx<T> vp = V.c[0] + V.c[3], vm = V.c[0] - V.c[3];
   const cx<T> vt = V.c[1] + mul_i(V.c[2]), vtb = V.c[1] - mul_i(V.c[2]);
-  return fb.c[0] * (vm * f.c[2] - vtb * f.c[3]) + fb.c[1] * (vp * f.c[3] - vt * f.c[2]) +
-         fb.c[2] * (vp * f.c[0] + vtb * f.c[1]) + fb.c[3] * (vt * f.c[0] + vm * f.c[1]);
+  const cx<T> p1 = cfma(fb.c[3], f.c[1], fb.c[0] * f.c[2]);
+  const cx<T> p2 = cfma(fb.c[2], f.c[0], fb.c[1] * f.c[3]);
+  const cx<T> p3 = cfms(fb.c[0], f.c[3], fb.c[2] * f.c[1]);
+  const cx<T> p4 = cfms(fb.c[1], f.c[2], fb.c[3] * f.c[0]);
+  return cfma(vt, p4, cfma(vtb, p3, cfma(vp, p2, vm * p1)));
 }
 
 // Same with chiral couplings gamma^mu (gL P_L + gR P_R).
@@ -196,17 +216,18 @@ template <class T> HME_FN cx<T> ffvlr_amp(const sp4<T>& fb, const sp4<T>& f, con
 template <class T> HME_FN sp4<T> ffv_psi(const sp4<T>& f, const vw4<T>& V, const T* K, T m, T den) {
   const cx<T> vp = V.c[0] + V.c[3], vm = V.c[0] - V.c[3];
   const cx<T> vt = V.c[1] + mul_i(V.c[2]), vtb = V.c[1] - mul_i(V.c[2]);
-  const cx<T> g0 = vm * f.c[2] - vtb * f.c[3];
-  const cx<T> g1 = vp * f.c[3] - vt * f.c[2];
-  const cx<T> g2 = vp * f.c[0] + vtb * f.c[1];
-  const cx<T> g3 = vt * f.c[0] + vm * f.c[1];
-  const T kp = K[0] + K[3], km = K[0] - K[3];
-  const cx<T> kt = {K[1], K[2]}, ktb = {K[1], -K[2]};
+  const cx<T> g0 = cfms(vtb, f.c[3], vm * f.c[2]);
+  const cx<T> g1 = cfms(vt, f.c[2], vp * f.c[3]);
+  const cx<T> g2 = cfma(vtb, f.c[1], vp * f.c[0]);
+  const cx<T> g3 = cfma(vm, f.c[1], vt * f.c[0]);
+  // the propagator factor is folded into K and m
+  const T kp = den * (K[0] + K[3]), km = den * (K[0] - K[3]), md = den * m;
+  const cx<T> kt = {den * K[1], den * K[2]}, ktb = {kt.r, -kt.i};
   sp4<T> o;
-  o.c[0] = den * (km * g2 - ktb * g3 + m * g0);
-  o.c[1] = den * (kp * g3 - kt * g2 + m * g1);
-  o.c[2] = den * (kp * g0 + ktb * g1 + m * g2);
-  o.c[3] = den * (kt * g0 + km * g1 + m * g3);
+  o.c[0] = cfms(ktb, g3, rfma(md, g0, km * g2));
+  o.c[1] = cfms(kt, g2, rfma(md, g1, kp * g3));
+  o.c[2] = cfma(ktb, g1, rfma(md, g2, kp * g0));
+  o.c[3] = cfma(kt, g0, rfma(md, g3, km * g1));
   return o;
 }
 
@@ -215,27 +236,27 @@ template <class T> HME_FN sp4<T> ffv_psi(const sp4<T>& f, const vw4<T>& V, const
 template <class T> HME_FN sp4<T> ffv_psibar(const sp4<T>& fb, const vw4<T>& V, const T* K, T m, T den) {
   const cx<T> vp = V.c[0] + V.c[3], vm = V.c[0] - V.c[3];
   const cx<T> vt = V.c[1] + mul_i(V.c[2]), vtb = V.c[1] - mul_i(V.c[2]);
-  const cx<T> h0 = fb.c[2] * vp + fb.c[3] * vt;
-  const cx<T> h1 = fb.c[2] * vtb + fb.c[3] * vm;
-  const cx<T> h2 = fb.c[0] * vm - fb.c[1] * vt;
-  const cx<T> h3 = fb.c[1] * vp - fb.c[0] * vtb;
-  const T kp = K[0] + K[3], km = K[0] - K[3];
-  const cx<T> kt = {K[1], K[2]}, ktb = {K[1], -K[2]};
+  const cx<T> h0 = cfma(fb.c[3], vt, fb.c[2] * vp);
+  const cx<T> h1 = cfma(fb.c[3], vm, fb.c[2] * vtb);
+  const cx<T> h2 = cfms(fb.c[1], vt, fb.c[0] * vm);
+  const cx<T> h3 = cfms(fb.c[0], vtb, fb.c[1] * vp);
+  const T kp = den * (K[0] + K[3]), km = den * (K[0] - K[3]), md = den * m;
+  const cx<T> kt = {den * K[1], den * K[2]}, ktb = {kt.r, -kt.i};
   sp4<T> o;
-  o.c[0] = den * (kp * h2 + kt * h3 + m * h0);
-  o.c[1] = den * (ktb * h2 + km * h3 + m * h1);
-  o.c[2] = den * (km * h0 - kt * h1 + m * h2);
-  o.c[3] = den * (kp * h1 - ktb * h0 + m * h3);
+  o.c[0] = cfma(kt, h3, rfma(md, h0, kp * h2));
+  o.c[1] = cfma(ktb, h2, rfma(md, h1, km * h3));
+  o.c[2] = cfms(kt, h1, rfma(md, h2, km * h0));
+  o.c[3] = cfms(ktb, h0, rfma(md, h3, kp * h1));
   return o;
 }
 
 // Off-shell vector from a fermion pair through a massless propagator: J^mu = fb gamma^mu f * den.
 template <class T> HME_FN vw4<T> ffv_vec(const sp4<T>& fb, const sp4<T>& f, T den) {
   vw4<T> J;
-  J.c[0] = den * (fb.c[0] * f.c[2] + fb.c[1] * f.c[3] + fb.c[2] * f.c[0] + fb.c[3] * f.c[1]);
-  J.c[1] = den * (fb.c[0] * f.c[3] + fb.c[1] * f.c[2] - fb.c[2] * f.c[1] - fb.c[3] * f.c[0]);
-  J.c[2] = den * mul_i(fb.c[1] * f.c[2] - fb.c[0] * f.c[3] + fb.c[2] * f.c[1] - fb.c[3] * f.c[0]);
-  J.c[3] = den * (fb.c[0] * f.c[2] - fb.c[1] * f.c[3] - fb.c[2] * f.c[0] + fb.c[3] * f.c[1]);
+  J.c[0] = den * cfma(fb.c[3], f.c[1], cfma(fb.c[2], f.c[0], cfma(fb.c[1], f.c[3], fb.c[0] * f.c[2])));
+  J.c[1] = den * cfms(fb.c[3], f.c[0], cfms(fb.c[2], f.c[1], cfma(fb.c[1], f.c[2], fb.c[0] * f.c[3])));
+  J.c[2] = den * mul_i(cfms(fb.c[3], f.c[0], cfma(fb.c[2], f.c[1], cfms(fb.c[0], f.c[3], fb.c[1] * f.c[2]))));
+  J.c[3] = den * cfma(fb.c[3], f.c[1], cfms(fb.c[2], f.c[0], cfms(fb.c[1], f.c[3], fb.c[0] * f.c[2])));
   return J;
 }
 
@@ -268,7 +289,7 @@ HME_FN cx<T> vvv_amp(const vw4<T>& a, const T* Qa, const vw4<T>& b, const T* Qb,
     d2[mu] = Qb[mu] - Qc[mu];
     d3[mu] = Qc[mu] - Qa[mu];
   }
-  return mdot(a, b) * mdot(d1, c) + mdot(b, c) * mdot(d2, a) + mdot(c, a) * mdot(d3, b);
+  return cfma(mdot(c, a), mdot(d3, b), cfma(mdot(b, c), mdot(d2, a), mdot(a, b) * mdot(d1, c)));
 }
 
 // Off-shell vector through a massless propagator (ALOHA-style "VVV1P0_1"):
@@ -283,7 +304,7 @@ template <class T> HME_FN vw4<T> vvv_vec(const vw4<T>& a, const T* Qa, const vw4
   }
   const cx<T> ab = den * mdot(a, b), va = den * mdot(v, a), wb = den * mdot(w, b);
   vw4<T> J;
-  for (int mu = 0; mu < 4; ++mu) J.c[mu] = u[mu] * ab + va * b.c[mu] - wb * a.c[mu];
+  for (int mu = 0; mu < 4; ++mu) J.c[mu] = cfms(wb, a.c[mu], cfma(va, b.c[mu], u[mu] * ab));
   return J;
 }
 
@@ -292,9 +313,9 @@ template <class T> HME_FN vw4<T> vvv_vec(const vw4<T>& a, const T* Qa, const vw4
 //   S = 2: g^{mu nu} g^{rho sigma} - g^{mu sigma} g^{nu rho}
 //   S = 3: g^{mu nu} g^{rho sigma} - g^{mu rho} g^{nu sigma}
 template <int S, class T> HME_FN cx<T> vvvv_amp(const vw4<T>& a, const vw4<T>& b, const vw4<T>& c, const vw4<T>& d) {
-  if (S == 1) return mdot(a, c) * mdot(b, d) - mdot(a, d) * mdot(b, c);
-  if (S == 2) return mdot(a, b) * mdot(c, d) - mdot(a, d) * mdot(b, c);
-  return mdot(a, b) * mdot(c, d) - mdot(a, c) * mdot(b, d);
+  if (S == 1) return cfms(mdot(a, d), mdot(b, c), mdot(a, c) * mdot(b, d));
+  if (S == 2) return cfms(mdot(a, d), mdot(b, c), mdot(a, b) * mdot(c, d));
+  return cfms(mdot(a, c), mdot(b, d), mdot(a, b) * mdot(c, d));
 }
 
 // Off-shell leg d through a massless propagator.
@@ -302,13 +323,13 @@ template <int S, class T> HME_FN vw4<T> vvvv_vec(const vw4<T>& a, const vw4<T>& 
   vw4<T> J;
   if (S == 1) {
     const cx<T> x = den * mdot(a, c), y = den * mdot(b, c);
-    for (int mu = 0; mu < 4; ++mu) J.c[mu] = x * b.c[mu] - y * a.c[mu];
+    for (int mu = 0; mu < 4; ++mu) J.c[mu] = cfms(y, a.c[mu], x * b.c[mu]);
   } else if (S == 2) {
     const cx<T> x = den * mdot(a, b), y = den * mdot(b, c);
-    for (int mu = 0; mu < 4; ++mu) J.c[mu] = x * c.c[mu] - y * a.c[mu];
+    for (int mu = 0; mu < 4; ++mu) J.c[mu] = cfms(y, a.c[mu], x * c.c[mu]);
   } else {
     const cx<T> x = den * mdot(a, b), y = den * mdot(a, c);
-    for (int mu = 0; mu < 4; ++mu) J.c[mu] = x * c.c[mu] - y * b.c[mu];
+    for (int mu = 0; mu < 4; ++mu) J.c[mu] = cfms(y, b.c[mu], x * c.c[mu]);
   }
   return J;
 }
