@@ -361,36 +361,55 @@ template <class T> HME_FN T dv(tab_ptr tab, int i) { return T(tab[i]); }
 namespace hme {
 
 // ------------------------------------------------------------------ per-event kits
-// The helicity-independent parts of the external states, computed once per event
-// into the LDS table; each lane then builds the state of its own helicity with a
-// few multiplies and selects, at every use.
+// The external states of both helicities, computed once per event into the LDS table;
+// each lane reads the half of its own helicity at every use (no arithmetic per use).
 
-// Massless vector: kit = (e1x, e1y, e1z, e2x, e2y) / sqrt(2) (e1 and e2 as in vxxxxx; e2z = 0).
-HME_FN void vector_kit(const double* k, double* kit) {
+// Massless vector with nsv = -1 (incoming: eps) or +1 (outgoing: conj(eps)): for lam = +1
+// then lam = -1 the nonzero parts (Re eps1, Re eps2, Re eps3, Im eps1, Im eps2), with
+// eps(k, lam) = (-lam e1 - i e2) / sqrt(2) and e1, e2 as in vxxxxx (eps0 = Im eps3 = 0).
+HME_FN void vector_kit(const double* k, int nsv, double* kit) {
   const double pt2 = k[1] * k[1] + k[2] * k[2];
   const double pt = sqrt(pt2);
   const double P = sqrt(pt2 + k[3] * k[3]);
   const double ct = k[3] / P, st = pt / P;
   const double cp = pt > 0 ? k[1] / pt : 1.0, sp = pt > 0 ? k[2] / pt : 0.0;
   const double r = 0.70710678118654752440;
-  kit[0] = r * ct * cp;
-  kit[1] = r * ct * sp;
-  kit[2] = -r * st;
-  kit[3] = -r * sp;
-  kit[4] = r * cp;
+  const double e1[3] = {r * ct * cp, r * ct * sp, -r * st}, e2[2] = {-r * sp, r * cp};
+  const double b = nsv < 0 ? -1.0 : 1.0;  // imaginary part: -i e2 (incoming), +i e2 (outgoing)
+  for (int h = 0; h < 2; ++h) {
+    const double a = h == 0 ? -1.0 : 1.0;  // -lam
+    double* o = kit + 5 * h;
+    o[0] = a * e1[0];
+    o[1] = a * e1[1];
+    o[2] = a * e1[2];
+    o[3] = b * e2[0];
+    o[4] = b * e2[1];
+  }
 }
 
-// Fermion: kit = (chi_+[0], chi_+[1], chi_-[0], chi_-[1] as (re, im) pairs, sqrt(E+|p|), sqrt(E-|p|)).
-HME_FN void fermion_kit(const double* p, double m, double* kit) {
-  cx<double> cp[2], cm[2];
-  helicity_chi(p, +1, cp);
-  helicity_chi(p, -1, cm);
+// Fermion states for lam = +1 then lam = -1, each 4 complex components as (re, im) pairs:
+// kind 1, ubar(p, lam) of an outgoing fermion (oxxxxx with nsf = +1); kind 2, v(p, lam) of an
+// outgoing antifermion (ixxxxx with nsf = -1).
+HME_FN void fermion_kit(const double* p, double m, int kind, double* kit) {
   double wp, wm;
   spinor_weights(p, m, wp, wm);
-  kit[0] = cp[0].r; kit[1] = cp[0].i; kit[2] = cp[1].r; kit[3] = cp[1].i;
-  kit[4] = cm[0].r; kit[5] = cm[0].i; kit[6] = cm[1].r; kit[7] = cm[1].i;
-  kit[8] = wp;
-  kit[9] = wm;
+  for (int h = 0; h < 2; ++h) {
+    const int lam = h == 0 ? 1 : -1;
+    cx<double> chi[2];
+    sp4<double> w;
+    const double a = lam > 0 ? wp : wm, b = lam > 0 ? wm : wp;
+    if (kind == 1) {
+      helicity_chi(p, lam, chi);
+      w = {{a * conj(chi[0]), a * conj(chi[1]), b * conj(chi[0]), b * conj(chi[1])}};
+    } else {
+      helicity_chi(p, -lam, chi);
+      w = {{a * chi[0], a * chi[1], -b * chi[0], -b * chi[1]}};
+    }
+    for (int c = 0; c < 4; ++c) {
+      kit[8 * h + 2 * c] = w.c[c].r;
+      kit[8 * h + 2 * c + 1] = w.c[c].i;
+    }
+  }
 }
 
 // A kit read out of the table (N values, already in the arithmetic type).
@@ -404,40 +423,31 @@ template <class T, int N> HME_FN kitv<T, N> load_kit(tab_ptr kit) {
   return r;
 }
 
-// eps(k, lam) (nsv = -1, incoming) or conj(eps) (nsv = +1, outgoing) from a vector kit.
-template <class T> HME_FN vw4<T> vxxxxx_from(const kitv<T, 5>& k, int lam, int nsv) {
-  const T a = T(-lam), b = nsv < 0 ? T(-1) : T(1);
+// The state from the half of a kit that belongs to the lane's helicity (lam and nsv are
+// already folded into the kit; the arguments keep the call shape of the builders above).
+template <class T> HME_FN vw4<T> vxxxxx_from(const kitv<T, 5>& k, int, int) {
   vw4<T> w;
   w.c[0] = {T(0), T(0)};
-  w.c[1] = {a * k.v[0], b * k.v[3]};
-  w.c[2] = {a * k.v[1], b * k.v[4]};
-  w.c[3] = {a * k.v[2], T(0)};
+  w.c[1] = {k.v[0], k.v[3]};
+  w.c[2] = {k.v[1], k.v[4]};
+  w.c[3] = {k.v[2], T(0)};
   return w;
 }
-
-// ubar(p, lam) of an outgoing fermion from a fermion kit (same state as oxxxxx with nsf = +1).
-template <class T> HME_FN sp4<T> oxxxxx_from(const kitv<T, 10>& k, int lam) {
-  const bool plus = lam > 0;
-  const cx<T> c0 = {plus ? k.v[0] : k.v[4], plus ? -k.v[1] : -k.v[5]};  // conj(chi)
-  const cx<T> c1 = {plus ? k.v[2] : k.v[6], plus ? -k.v[3] : -k.v[7]};
-  const T a = plus ? k.v[8] : k.v[9], b = plus ? k.v[9] : k.v[8];
-  return {{a * c0, a * c1, b * c0, b * c1}};
+template <class T> HME_FN sp4<T> spinor_from(const kitv<T, 8>& k) {
+  return {{{k.v[0], k.v[1]}, {k.v[2], k.v[3]}, {k.v[4], k.v[5]}, {k.v[6], k.v[7]}}};
 }
-
-// v(p, lam) of an outgoing antifermion from a fermion kit (same state as ixxxxx with nsf = -1).
-template <class T> HME_FN sp4<T> ixxxxx_from(const kitv<T, 10>& k, int lam) {
-  const bool plus = lam > 0;
-  const cx<T> c0 = {plus ? k.v[4] : k.v[0], plus ? k.v[5] : k.v[1]};  // chi_{-lam}
-  const cx<T> c1 = {plus ? k.v[6] : k.v[2], plus ? k.v[7] : k.v[3]};
-  const T a = plus ? k.v[8] : k.v[9], b = plus ? k.v[9] : k.v[8];
-  return {{a * c0, a * c1, -b * c0, -b * c1}};
-}
+template <class T> HME_FN sp4<T> oxxxxx_from(const kitv<T, 8>& k, int) { return spinor_from<T>(k); }
+template <class T> HME_FN sp4<T> ixxxxx_from(const kitv<T, 8>& k, int) { return spinor_from<T>(k); }
 
 template <class T> HME_FN vw4<T> vxxxxx_kit(tab_ptr kit, int lam, int nsv) {
-  return vxxxxx_from<T>(load_kit<T, 5>(kit), lam, nsv);
+  return vxxxxx_from<T>(load_kit<T, 5>(kit + (lam > 0 ? 0 : 5)), lam, nsv);
 }
-template <class T> HME_FN sp4<T> oxxxxx_kit(tab_ptr kit, int lam) { return oxxxxx_from<T>(load_kit<T, 10>(kit), lam); }
-template <class T> HME_FN sp4<T> ixxxxx_kit(tab_ptr kit, int lam) { return ixxxxx_from<T>(load_kit<T, 10>(kit), lam); }
+template <class T> HME_FN sp4<T> oxxxxx_kit(tab_ptr kit, int lam) {
+  return spinor_from<T>(load_kit<T, 8>(kit + (lam > 0 ? 0 : 8)));
+}
+template <class T> HME_FN sp4<T> ixxxxx_kit(tab_ptr kit, int lam) {
+  return spinor_from<T>(load_kit<T, 8>(kit + (lam > 0 ? 0 : 8)));
+}
 
 // Scheduling fence for the generated code: table reads issued before it are not moved
 // past it, so their LDS latency overlaps the arithmetic that follows.

@@ -71,11 +71,11 @@ def _closure(g, keys):
 
 
 NODE_FLOPS = {"vvv": "vvv_vec", "vvvv": "vvvv_vec", "psi": "ffv_psi", "psibar": "ffv_psibar", "qq": "ffv_vec"}
-KIT_FLOPS = {"ext_v": 4, "ext_o": 12, "ext_i": 12}  # building a wavefunction from its per-event kit
+KIT_FLOPS = {"ext_v": 0, "ext_o": 0, "ext_i": 0}  # a wavefunction is read from its per-event kit
 
 
 UNIT = "@@UNIT@@"
-_READ = re.compile(r"(qv<T>\(tab, \d+\)|dv<T>\(tab, [^)]*\)|(vxxxxx|oxxxxx|ixxxxx)_kit<T>\(tab \+ (\w+), )")
+_READ = re.compile(r"(qv<T>\(tab, \d+\)|dv<T>\(tab, [^)]*\)|(vxxxxx|oxxxxx|ixxxxx)_kit<T>\(tab \+ (\w+), hel\((\d+)\))")
 
 
 def prefetch_units(lines, enable, kits: bool = True):
@@ -112,12 +112,12 @@ def prefetch_units(lines, enable, kits: bool = True):
                 d.append(f"  const T {nm} = {txt};")
                 seen[txt] = nm
                 return nm
-            kind, off = m.group(2), m.group(3)
+            kind, off, part = m.group(2), m.group(3), m.group(4)
             if not kits:
                 return txt
-            n = 5 if kind == "vxxxxx" else 10
-            d.append(f"  const kitv<T, {n}> {nm} = load_kit<T, {n}>(tab + {off});")
-            seen[txt] = f"{kind}_from<T>({nm}, "
+            n = 5 if kind == "vxxxxx" else 8  # the half of the kit for the lane's helicity
+            d.append(f"  const kitv<T, {n}> {nm} = load_kit<T, {n}>(tab + {off} + (hel({part}) > 0 ? 0 : {n}));")
+            seen[txt] = f"{kind}_from<T>({nm}, hel({part})"
             return seen[txt]
 
         body = [_READ.sub(repl, l) for l in u]
@@ -403,7 +403,7 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
     off = 4 * nq + nd
     for k in ext:
         koff[k] = off
-        off += 5 if g.nodes[("E", k)].kind == "ext_v" else 10
+        off += 10 if g.nodes[("E", k)].kind == "ext_v" else 16  # both helicities
     ntab = off
     def finish(lines, pf):
         lines = [l.replace("DOFF", str(4 * nq)) for l in lines]
@@ -543,8 +543,8 @@ struct {name} {{
 
   // Per-event table (LDS): {nq} momentum sums (incoming momenta of the particles in the mask,
   // negated for barred currents), {nd} propagator denominators 1/(Q^2 - m^2), and for every
-  // external particle a kit from which either helicity state is built (gluon: e1, e2 / sqrt 2;
-  // fermion: chi_+, chi_-, sqrt(E + |p|), sqrt(E - |p|)).
+  // external particle a kit holding its state for either helicity (gluon: the five nonzero real
+  // parts of eps or conj(eps); fermion: the four complex components of ubar or v).
   static constexpr int nq = {nq}, nd = {nd}, nitems = {nitems}, ntab = {ntab};
   static constexpr unsigned qmask[{max(nq, 1)}] = {{{", ".join(map(str, qmask))}}};
   static constexpr int qsign[{max(nq, 1)}] = {{{", ".join(map(str, qsign))}}};
@@ -560,8 +560,8 @@ struct {name} {{
 #pragma unroll
       for (int k = 0; k < {npar}; ++k) {{
         if (j - nq - nd != k) continue;
-        if (kit_kind[k] == 0) vector_kit(p[k], tab + kit_off[k]);
-        else fermion_kit(p[k], k < 2 ? 0.0 : prm.mT, tab + kit_off[k]);
+        if (kit_kind[k] == 0) vector_kit(p[k], k < 2 ? -1 : 1, tab + kit_off[k]);
+        else fermion_kit(p[k], k < 2 ? 0.0 : prm.mT, kit_kind[k], tab + kit_off[k]);
       }}
       return;
     }}
