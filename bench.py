@@ -28,19 +28,19 @@ PEAK_HBM = 8.0e12
 # counter reads for a plain 256 MiB device copy.  Valid only for the kernel sources it was taken
 # on (sha256 prefix of me2_kernels.h + colour_mfma.h + helas.h + procs/ggttgg.h); otherwise
 # traffic is null.
-TRAFFIC = {"source_sha": "8f75b3613f103543", "nevt": 1048576,
-           "fetch_kib": 198374.1875, "write_kib": 8192.0, "fetch_factor": 262144 / 131088.375, "write_factor": 1.0}
+TRAFFIC = {"source_sha": "b6be980fd3b5473f", "nevt": 1048576,
+           "fetch_kib": 198169.5625, "write_kib": 8192.0, "fetch_factor": 262144 / 131088.8125, "write_factor": 1.0}
 
 # VALU and MFMA instruction counters of the same launches (profiles/me2_ggttgg_1M_valu_counters.md),
 # wave instructions summed over the device: FLOPs = 64 lanes x (2 FMA + ADD + MUL + TRANS) plus
 # 512 per MFMA "MOPS" unit (the counter's own scale).
 COUNTERS = {
-    "source_sha": "8f75b3613f103543", "nevt": 1048576,
-    "fp64": {"FMA_F64": 17557356544, "ADD_F64": 2545942528, "MUL_F64": 6369050624, "TRANS_F64": 39845888,
-             "VALU": 28741468160},
-    "mixed_fast": {"FMA_F32": 13863223296, "ADD_F32": 2416967680, "MUL_F32": 4939841536, "TRANS_F32": 0,
-                   "FMA_F64": 322961408, "ADD_F64": 17825792, "MUL_F64": 104857600, "TRANS_F64": 39845888,
-                   "MFMA_MOPS_BF16": 2684354560, "VALU": 26792165376},
+    "source_sha": "b6be980fd3b5473f", "nevt": 1048576,
+    "fp64": {"FMA_F64": 16802381824, "ADD_F64": 3300917248, "MUL_F64": 4637851648, "TRANS_F64": 39845888,
+             "VALU": 25321013248},
+    "mixed_fast": {"FMA_F32": 13234077696, "ADD_F32": 3046113280, "MUL_F32": 3572498432, "TRANS_F32": 0,
+                   "FMA_F64": 322961408, "ADD_F64": 17825792, "MUL_F64": 132120576, "TRANS_F64": 39845888,
+                   "MFMA_MOPS_BF16": 2684354560, "VALU": 24559747072},
 }
 
 
