@@ -449,6 +449,59 @@ template <class T> HME_FN sp4<T> ixxxxx_kit(tab_ptr kit, int lam) {
   return spinor_from<T>(load_kit<T, 8>(kit + (lam > 0 ? 0 : 8)));
 }
 
+// ------------------------------------------------------------------ vertices with per-event kits
+// The helicity-independent parts of a vertex (momentum combinations, propagator factor) are
+// computed once per event into the table; these variants read them instead of forming them
+// at every use.
+
+// vvv_vec with k = (den (Qa - Qb), den (Qa + 2 Qb), den (2 Qa + Qb)).
+template <class T> HME_FN vw4<T> vvv_vec_k(const vw4<T>& a, const vw4<T>& b, const kitv<T, 12>& k) {
+  const cx<T> ab = mdot(a, b), va = mdot(k.v + 4, a), wb = mdot(k.v + 8, b);
+  vw4<T> J;
+  for (int mu = 0; mu < 4; ++mu) J.c[mu] = cfms(wb, a.c[mu], cfma(va, b.c[mu], k.v[mu] * ab));
+  return J;
+}
+
+// vvv_amp with k = (Qa - Qb, Qb - Qc, Qc - Qa).
+template <class T>
+HME_FN cx<T> vvv_amp_k(const vw4<T>& a, const vw4<T>& b, const vw4<T>& c, const kitv<T, 12>& k) {
+  return cfma(mdot(c, a), mdot(k.v + 8, b), cfma(mdot(b, c), mdot(k.v + 4, a), mdot(a, b) * mdot(k.v, c)));
+}
+
+// ffv_psi / ffv_psibar with k = den (K0 + K3, K0 - K3, K1, K2, m).
+template <class T> HME_FN sp4<T> ffv_psi_k(const sp4<T>& f, const vw4<T>& V, const kitv<T, 5>& k) {
+  const cx<T> vp = V.c[0] + V.c[3], vm = V.c[0] - V.c[3];
+  const cx<T> vt = V.c[1] + mul_i(V.c[2]), vtb = V.c[1] - mul_i(V.c[2]);
+  const cx<T> g0 = cfms(vtb, f.c[3], vm * f.c[2]);
+  const cx<T> g1 = cfms(vt, f.c[2], vp * f.c[3]);
+  const cx<T> g2 = cfma(vtb, f.c[1], vp * f.c[0]);
+  const cx<T> g3 = cfma(vm, f.c[1], vt * f.c[0]);
+  const T kp = k.v[0], km = k.v[1], md = k.v[4];
+  const cx<T> kt = {k.v[2], k.v[3]}, ktb = {k.v[2], -k.v[3]};
+  sp4<T> o;
+  o.c[0] = cfms(ktb, g3, rfma(md, g0, km * g2));
+  o.c[1] = cfms(kt, g2, rfma(md, g1, kp * g3));
+  o.c[2] = cfma(ktb, g1, rfma(md, g2, kp * g0));
+  o.c[3] = cfma(kt, g0, rfma(md, g3, km * g1));
+  return o;
+}
+template <class T> HME_FN sp4<T> ffv_psibar_k(const sp4<T>& fb, const vw4<T>& V, const kitv<T, 5>& k) {
+  const cx<T> vp = V.c[0] + V.c[3], vm = V.c[0] - V.c[3];
+  const cx<T> vt = V.c[1] + mul_i(V.c[2]), vtb = V.c[1] - mul_i(V.c[2]);
+  const cx<T> h0 = cfma(fb.c[3], vt, fb.c[2] * vp);
+  const cx<T> h1 = cfma(fb.c[3], vm, fb.c[2] * vtb);
+  const cx<T> h2 = cfms(fb.c[1], vt, fb.c[0] * vm);
+  const cx<T> h3 = cfms(fb.c[0], vtb, fb.c[1] * vp);
+  const T kp = k.v[0], km = k.v[1], md = k.v[4];
+  const cx<T> kt = {k.v[2], k.v[3]}, ktb = {k.v[2], -k.v[3]};
+  sp4<T> o;
+  o.c[0] = cfma(kt, h3, rfma(md, h0, kp * h2));
+  o.c[1] = cfma(ktb, h2, rfma(md, h1, km * h3));
+  o.c[2] = cfms(kt, h1, rfma(md, h2, km * h0));
+  o.c[3] = cfms(ktb, h0, rfma(md, h3, kp * h1));
+  return o;
+}
+
 // Scheduling fence for the generated code: table reads issued before it are not moved
 // past it, so their LDS latency overlaps the arithmetic that follows.
 #if defined(__HIP_DEVICE_COMPILE__)

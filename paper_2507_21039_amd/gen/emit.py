@@ -32,6 +32,13 @@ FLOPS = {
     "vvvv_amp": 4 * (4 * 6 + 3 * 2) + 2 * 6 + 2,
     "vvvv_vec": 2 * (4 * 6 + 3 * 2) + 2 * 2 + 4 * (6 + 6 + 2),
 }
+# the momentum combinations and propagator factors of a vertex, read from the per-event table
+FLOPS["vvv_vec_k"] = FLOPS["vvv_vec"] - 18
+FLOPS["ffv_psi_k"] = FLOPS["ffv_psi"] - 10
+FLOPS["ffv_psibar_k"] = FLOPS["ffv_psibar"] - 10
+FLOPS["vvv_amp_k"] = FLOPS["vvv_amp"] - 12
+VK_SIZE = {"vvv": 12, "psi": 5, "amp3": 12}  # doubles per vertex kit
+VK_FLOPS = {"vvv": 24, "psi": 7, "amp3": 12}  # per event, in the table
 EXT_FLOPS = {"vxxxxx": 20, "ixxxxx": 30, "oxxxxx": 30}  # includes sqrt/div as one each
 DEN_FLOPS = 9  # momentum square (7) and the reciprocal of (Q^2 - m^2) (2)
 
@@ -70,12 +77,13 @@ def _closure(g, keys):
     return out
 
 
-NODE_FLOPS = {"vvv": "vvv_vec", "vvvv": "vvvv_vec", "psi": "ffv_psi", "psibar": "ffv_psibar", "qq": "ffv_vec"}
+NODE_FLOPS = {"vvv": "vvv_vec_k", "vvvv": "vvvv_vec", "psi": "ffv_psi_k", "psibar": "ffv_psibar_k", "qq": "ffv_vec"}
 KIT_FLOPS = {"ext_v": 0, "ext_o": 0, "ext_i": 0}  # a wavefunction is read from its per-event kit
 
 
 UNIT = "@@UNIT@@"
-_READ = re.compile(r"(qv<T>\(tab, \d+\)|dv<T>\(tab, [^)]*\)|(vxxxxx|oxxxxx|ixxxxx)_kit<T>\(tab \+ (\w+), hel\((\d+)\))")
+_READ = re.compile(r"(qv<T>\(tab, \d+\)|dv<T>\(tab, [^)]*\)|load_kit<T, \d+>\(tab \+ [^)]*\)|"
+                   r"(vxxxxx|oxxxxx|ixxxxx)_kit<T>\(tab \+ (\w+), hel\((\d+)\))")
 
 
 def prefetch_units(lines, enable, kits: bool = True):
@@ -110,6 +118,11 @@ def prefetch_units(lines, enable, kits: bool = True):
                 return nm
             if txt.startswith("dv"):
                 d.append(f"  const T {nm} = {txt};")
+                seen[txt] = nm
+                return nm
+            if txt.startswith("load_kit"):
+                n = txt.split("<T, ", 1)[1].split(">", 1)[0]
+                d.append(f"  const kitv<T, {n}> {nm} = {txt};")
                 seen[txt] = nm
                 return nm
             kind, off, part = m.group(2), m.group(3), m.group(4)
@@ -179,6 +192,19 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
         if mask not in didx:
             didx[mask] = (len(didx), massive)
         return f"dv<T>(tab, DOFF + {didx[mask][0]})"
+
+    vkidx = {}  # vertex-kit key -> offset in the vertex-kit region of the table
+    vk_list = []  # (kind, mask0, mask1, mask2, sign, offset)
+    vk_off = [0]
+
+    def vkit(kind, m0, m1=0, m2=0, sign=1):
+        key = (kind, m0, m1, m2, sign)
+        if key not in vkidx:
+            vkidx[key] = vk_off[0]
+            vk_list.append((kind, m0, m1, m2, sign, vk_off[0]))
+            vk_off[0] += VK_SIZE[kind]
+        n = VK_SIZE[kind]
+        return f"load_kit<T, {n}>(tab + VOFF + {vkidx[key]})"
 
     from .diagrams import schedule, schedule_cached
     node_cost = {kind: FLOPS[NODE_FLOPS[kind]] for kind in NODE_FLOPS}
@@ -263,13 +289,13 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
             v = f"w{node_ids[key]}" + (f"_{version[key]}" if version[key] else "")
             if n.kind == "vvv":
                 ma, mb = g.nodes[n.args[0]].mask, g.nodes[n.args[1]].mask
-                call = f"vw4<T> {v} = vvv_vec<T>({args[0]}, {mom(ma)}, {args[1]}, {mom(mb)}, {den(n.mask, False)});"
+                call = f"vw4<T> {v} = vvv_vec_k<T>({args[0]}, {args[1]}, {vkit('vvv', ma, mb, n.mask)});"
             elif n.kind == "vvvv":
                 call = f"vw4<T> {v} = vvvv_vec<{n.extra[0]}, T>({args[0]}, {args[1]}, {args[2]}, {den(n.mask, False)});"
             elif n.kind == "psi":
-                call = f"sp4<T> {v} = ffv_psi<T>({args[0]}, {args[1]}, {mom(n.mask)}, mT, {den(n.mask, True)});"
+                call = f"sp4<T> {v} = ffv_psi_k<T>({args[0]}, {args[1]}, {vkit('psi', n.mask)});"
             elif n.kind == "psibar":
-                call = f"sp4<T> {v} = ffv_psibar<T>({args[0]}, {args[1]}, {mom(n.mask, -1)}, mT, {den(n.mask, True)});"
+                call = f"sp4<T> {v} = ffv_psibar_k<T>({args[0]}, {args[1]}, {vkit('psi', n.mask, sign=-1)});"
             elif n.kind == "qq":
                 call = f"vw4<T> {v} = ffv_vec<T>({args[0]}, {args[1]}, {den(n.mask, False)});"
             else:
@@ -329,9 +355,9 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
                 f = FLOPS["ffv_amp"]
             elif amp.kind == "vvv":
                 a, b, q = amp.args
-                call = (f"vvv_amp<T>({args[0]}, {mom(g.nodes[a].mask)}, {args[1]}, {mom(g.nodes[b].mask)}, "
-                        f"{args[2]}, {mom(g.nodes[q].mask)})")
-                f = FLOPS["vvv_amp"]
+                call = (f"vvv_amp_k<T>({args[0]}, {args[1]}, {args[2]}, "
+                        f"{vkit('amp3', g.nodes[a].mask, g.nodes[b].mask, g.nodes[q].mask)})")
+                f = FLOPS["vvv_amp_k"]
             else:
                 call = f"vvvv_amp<{amp.extra[0]}, T>({args[0]}, {args[1]}, {args[2]}, {args[3]})"
                 f = FLOPS["vvvv_amp"]
@@ -404,9 +430,10 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
     for k in ext:
         koff[k] = off
         off += 10 if g.nodes[("E", k)].kind == "ext_v" else 16  # both helicities
-    ntab = off
+    voff = off
+    ntab = off + vk_off[0]
     def finish(lines, pf):
-        lines = [l.replace("DOFF", str(4 * nq)) for l in lines]
+        lines = [l.replace("DOFF", str(4 * nq)).replace("VOFF", str(voff)) for l in lines]
         for k in ext:
             lines = [l.replace(f"KOFF{k}", str(koff[k])) for l in lines]
         return "\n".join(prefetch_units(lines, bool(pf), kits=(pf != "table")))
@@ -468,7 +495,10 @@ struct {name}_c{c} {{
         cs.append(f"    s += jamp[{i}].r * ({zr}) + jamp[{i}].i * ({zi});")
         cs_flops += 4 * len(terms) + 4
 
-    nitems = nq + nd + npar
+    nvk = len(vk_list)
+    nitems = nq + nd + npar + nvk
+    flops_table += sum(VK_FLOPS[x[0]] for x in vk_list)
+    vk_kind_code = {"vvv": 0, "psi": 1, "amp3": 2}
     numer_list = ", ".join(str(N[i][j]) for i in range(ncol) for j in range(ncol))
     assert all(abs(N[i][j]) < 32768 for i in range(ncol) for j in range(ncol))
     gather_code = ""
@@ -553,8 +583,69 @@ struct {name} {{
   static constexpr int kit_off[{npar}] = {{{", ".join(str(k[0]) for k in kits)}}};
   static constexpr int kit_kind[{npar}] = {{{", ".join(str(k[1]) for k in kits)}}};  // 0 vector, 1 ubar, 2 v
 
+  // vertex kits after the external-state kits: kind 0 three-gluon current (den (Qa - Qb),
+  // den (Qa + 2 Qb), den (2 Qa + Qb) with den = 1 / Q^2 of mask 2), kind 1 quark propagator
+  // (den sign (K0 + K3, K0 - K3, K1, K2), den mT with K of mask 0 and den = 1 / (K^2 - mT^2)),
+  // kind 2 three-gluon amplitude (Qa - Qb, Qb - Qc, Qc - Qa)
+  static constexpr int nvk = {nvk}, voff = {voff};
+  static constexpr int vk_kind[{max(nvk, 1)}] = {{{", ".join(str(vk_kind_code[x[0]]) for x in vk_list) or "0"}}};
+  static constexpr unsigned vk_m0[{max(nvk, 1)}] = {{{", ".join(str(x[1]) for x in vk_list) or "0"}}};
+  static constexpr unsigned vk_m1[{max(nvk, 1)}] = {{{", ".join(str(x[2]) for x in vk_list) or "0"}}};
+  static constexpr unsigned vk_m2[{max(nvk, 1)}] = {{{", ".join(str(x[3]) for x in vk_list) or "0"}}};
+  static constexpr int vk_sign[{max(nvk, 1)}] = {{{", ".join(str(x[4]) for x in vk_list) or "1"}}};
+  static constexpr int vk_off[{max(nvk, 1)}] = {{{", ".join(str(x[5]) for x in vk_list) or "0"}}};
+
+  // sum of the incoming momenta of the particles in mask m (outgoing ones negated)
+  HME_FN static void mask_sum(const double (&p)[{npar}][4], unsigned m, double* Q) {{
+    Q[0] = Q[1] = Q[2] = Q[3] = 0.0;
+#pragma unroll
+    for (int k = 0; k < {npar}; ++k) {{
+      const double s = (m >> k & 1u) ? (k < 2 ? 1.0 : -1.0) : 0.0;
+#pragma unroll
+      for (int mu = 0; mu < 4; ++mu) Q[mu] += s * p[k][mu];
+    }}
+  }}
+
+  HME_FN static void vertex_kit(const double (&p)[{npar}][4], const ProcParams& prm, int v, double* o) {{
+    double A[4], B[4], C[4];
+    mask_sum(p, vk_m0[v], A);
+    if (vk_kind[v] == 1) {{
+      const double den = 1.0 / (A[0] * A[0] - A[1] * A[1] - A[2] * A[2] - A[3] * A[3] - prm.mT * prm.mT);
+      const double ds = den * vk_sign[v];
+      o[0] = ds * (A[0] + A[3]);
+      o[1] = ds * (A[0] - A[3]);
+      o[2] = ds * A[1];
+      o[3] = ds * A[2];
+      o[4] = den * prm.mT;
+      return;
+    }}
+    mask_sum(p, vk_m1[v], B);
+    mask_sum(p, vk_m2[v], C);
+    if (vk_kind[v] == 0) {{
+      const double den = 1.0 / (C[0] * C[0] - C[1] * C[1] - C[2] * C[2] - C[3] * C[3]);
+#pragma unroll
+      for (int mu = 0; mu < 4; ++mu) {{
+        o[mu] = den * (A[mu] - B[mu]);
+        o[4 + mu] = den * (A[mu] + 2 * B[mu]);
+        o[8 + mu] = den * (2 * A[mu] + B[mu]);
+      }}
+    }} else {{
+#pragma unroll
+      for (int mu = 0; mu < 4; ++mu) {{
+        o[mu] = A[mu] - B[mu];
+        o[4 + mu] = B[mu] - C[mu];
+        o[8 + mu] = C[mu] - A[mu];
+      }}
+    }}
+  }}
+
   // item j of the table (j < nitems); the lanes of an event compute disjoint items
   HME_FN static void table_entry(const double (&p)[{npar}][4], const ProcParams& prm, int j, double* tab) {{
+    if (j >= nq + nd + {npar}) {{
+      const int v = j - nq - nd - {npar};
+      vertex_kit(p, prm, v, tab + voff + vk_off[v]);
+      return;
+    }}
     if (j >= nq + nd) {{
       // static indexing of p (a dynamic index would put the event record in scratch)
 #pragma unroll
