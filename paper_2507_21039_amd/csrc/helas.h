@@ -342,7 +342,10 @@ namespace hme {
 // that the kernel keeps in LDS.  The reads are volatile so that every use loads
 // the value again instead of the compiler keeping it in a register across the
 // whole diagram sequence (register pressure, not LDS traffic, is the limit).
-typedef const volatile HME_LDS double* tab_ptr;
+// The table holds the arithmetic type of the kernel that reads it (values are computed in
+// double and rounded once when stored).
+template <class S> using tab_of = const volatile HME_LDS S*;
+typedef tab_of<double> tab_ptr;
 
 template <class T> struct m4 {
   T v[4];
@@ -350,11 +353,11 @@ template <class T> struct m4 {
   HME_FN operator const T*() const { return v; }
 };
 
-template <class T> HME_FN m4<T> qv(tab_ptr tab, int i) {
+template <class T, class S> HME_FN m4<T> qv(const volatile HME_LDS S* tab, int i) {
   return m4<T>{{T(tab[4 * i]), T(tab[4 * i + 1]), T(tab[4 * i + 2]), T(tab[4 * i + 3])}};
 }
 
-template <class T> HME_FN T dv(tab_ptr tab, int i) { return T(tab[i]); }
+template <class T, class S> HME_FN T dv(const volatile HME_LDS S* tab, int i) { return T(tab[i]); }
 
 }  // namespace hme
 
@@ -367,7 +370,7 @@ namespace hme {
 // Massless vector with nsv = -1 (incoming: eps) or +1 (outgoing: conj(eps)): for lam = +1
 // then lam = -1 the nonzero parts (Re eps1, Re eps2, Re eps3, Im eps1, Im eps2), with
 // eps(k, lam) = (-lam e1 - i e2) / sqrt(2) and e1, e2 as in vxxxxx (eps0 = Im eps3 = 0).
-HME_FN void vector_kit(const double* k, int nsv, double* kit) {
+template <class S> HME_FN void vector_kit(const double* k, int nsv, S* kit) {
   const double pt2 = k[1] * k[1] + k[2] * k[2];
   const double pt = sqrt(pt2);
   const double P = sqrt(pt2 + k[3] * k[3]);
@@ -378,19 +381,19 @@ HME_FN void vector_kit(const double* k, int nsv, double* kit) {
   const double b = nsv < 0 ? -1.0 : 1.0;  // imaginary part: -i e2 (incoming), +i e2 (outgoing)
   for (int h = 0; h < 2; ++h) {
     const double a = h == 0 ? -1.0 : 1.0;  // -lam
-    double* o = kit + 5 * h;
-    o[0] = a * e1[0];
-    o[1] = a * e1[1];
-    o[2] = a * e1[2];
-    o[3] = b * e2[0];
-    o[4] = b * e2[1];
+    S* o = kit + 5 * h;
+    o[0] = S(a * e1[0]);
+    o[1] = S(a * e1[1]);
+    o[2] = S(a * e1[2]);
+    o[3] = S(b * e2[0]);
+    o[4] = S(b * e2[1]);
   }
 }
 
 // Fermion states for lam = +1 then lam = -1, each 4 complex components as (re, im) pairs:
 // kind 1, ubar(p, lam) of an outgoing fermion (oxxxxx with nsf = +1); kind 2, v(p, lam) of an
 // outgoing antifermion (ixxxxx with nsf = -1).
-HME_FN void fermion_kit(const double* p, double m, int kind, double* kit) {
+template <class S> HME_FN void fermion_kit(const double* p, double m, int kind, S* kit) {
   double wp, wm;
   spinor_weights(p, m, wp, wm);
   for (int h = 0; h < 2; ++h) {
@@ -406,8 +409,8 @@ HME_FN void fermion_kit(const double* p, double m, int kind, double* kit) {
       w = {{a * chi[0], a * chi[1], -b * chi[0], -b * chi[1]}};
     }
     for (int c = 0; c < 4; ++c) {
-      kit[8 * h + 2 * c] = w.c[c].r;
-      kit[8 * h + 2 * c + 1] = w.c[c].i;
+      kit[8 * h + 2 * c] = S(w.c[c].r);
+      kit[8 * h + 2 * c + 1] = S(w.c[c].i);
     }
   }
 }
@@ -416,7 +419,7 @@ HME_FN void fermion_kit(const double* p, double m, int kind, double* kit) {
 template <class T, int N> struct kitv {
   T v[N];
 };
-template <class T, int N> HME_FN kitv<T, N> load_kit(tab_ptr kit) {
+template <class T, int N, class S> HME_FN kitv<T, N> load_kit(const volatile HME_LDS S* kit) {
   kitv<T, N> r;
 #pragma unroll
   for (int i = 0; i < N; ++i) r.v[i] = T(kit[i]);
@@ -439,13 +442,13 @@ template <class T> HME_FN sp4<T> spinor_from(const kitv<T, 8>& k) {
 template <class T> HME_FN sp4<T> oxxxxx_from(const kitv<T, 8>& k, int) { return spinor_from<T>(k); }
 template <class T> HME_FN sp4<T> ixxxxx_from(const kitv<T, 8>& k, int) { return spinor_from<T>(k); }
 
-template <class T> HME_FN vw4<T> vxxxxx_kit(tab_ptr kit, int lam, int nsv) {
+template <class T, class S> HME_FN vw4<T> vxxxxx_kit(const volatile HME_LDS S* kit, int lam, int nsv) {
   return vxxxxx_from<T>(load_kit<T, 5>(kit + (lam > 0 ? 0 : 5)), lam, nsv);
 }
-template <class T> HME_FN sp4<T> oxxxxx_kit(tab_ptr kit, int lam) {
+template <class T, class S> HME_FN sp4<T> oxxxxx_kit(const volatile HME_LDS S* kit, int lam) {
   return spinor_from<T>(load_kit<T, 8>(kit + (lam > 0 ? 0 : 8)));
 }
-template <class T> HME_FN sp4<T> ixxxxx_kit(tab_ptr kit, int lam) {
+template <class T, class S> HME_FN sp4<T> ixxxxx_kit(const volatile HME_LDS S* kit, int lam) {
   return spinor_from<T>(load_kit<T, 8>(kit + (lam > 0 ? 0 : 8)));
 }
 

@@ -193,7 +193,7 @@ __global__ void __launch_bounds__(256, me2_min_waves<T>())
   constexpr int EPW = 64 / LPE;   // events per wavefront
   constexpr int EPB = 256 / LPE;  // events per block
   // per-event table of momentum sums and propagator denominators, shared by the event's lanes
-  __shared__ double table[EPB * (Proc::ntab > 0 ? Proc::ntab : 1)];
+  __shared__ T table[EPB * (Proc::ntab > 0 ? Proc::ntab : 1)];
   // with single-precision amplitudes, the colour sums of processes with 24 or more flows run
   // on the matrix cores (one event per wavefront, the 64 lanes are 64 helicity columns)
   constexpr bool kMfmaColour = LPE == 64 && Proc::ncol >= 24 && sizeof(T) == 4;
@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(256, me2_min_waves<T>())
   const int64_t evc = ev < nevt ? ev : nevt - 1;  // ragged tail: recompute the last event, store nothing
   double p[Proc::npar][4];
   load_event<Proc>(mom, evc, p);
-  double* tab = table + (threadIdx.x / LPE) * Proc::ntab;
+  T* tab = table + (threadIdx.x / LPE) * Proc::ntab;
   for (int j = sub; j < Proc::nitems; j += LPE) Proc::table_entry(p, prm, j, tab);
   if constexpr (kMfmaColour) colour_tiles_fill<Proc>(cnh, cnl, threadIdx.x, 256);
   __syncthreads();
@@ -226,7 +226,7 @@ __global__ void __launch_bounds__(256, me2_min_waves<T>())
     cx<T> jamp[Proc::ncol];
 #pragma unroll
     for (int c = 0; c < Proc::ncol; ++c) jamp[c] = {T(0), T(0)};
-    Proc::template amplitudes<T>(p, prm, (unsigned)goodhel[valid ? sub : ngood - 1], (tab_ptr)tab, jamp);
+    Proc::template amplitudes<T>(p, prm, (unsigned)goodhel[valid ? sub : ngood - 1], (tab_of<T>)tab, jamp);
     double mh;
     if constexpr (kMfmaColour) {
       mh = (double)colour_sum_wave<Proc>(jamp, NumerLds<Proc>{(const HME_LDS __bf16*)cnh, (const HME_LDS __bf16*)cnl});
@@ -251,7 +251,7 @@ __global__ void __launch_bounds__(256, me2_min_waves<T>())
       cx<T> jamp[Proc::ncol];
 #pragma unroll
       for (int c = 0; c < Proc::ncol; ++c) jamp[c] = {T(0), T(0)};
-      Proc::template amplitudes<T>(p, prm, (unsigned)goodhel[valid ? k : ngood - 1], (tab_ptr)tab, jamp);
+      Proc::template amplitudes<T>(p, prm, (unsigned)goodhel[valid ? k : ngood - 1], (tab_of<T>)tab, jamp);
       const float s = colour_sum_wave<Proc>(jamp, NumerLds<Proc>{(const HME_LDS __bf16*)cnh, (const HME_LDS __bf16*)cnl});
       acc += valid ? (double)s : 0.0;
     }
@@ -260,7 +260,7 @@ __global__ void __launch_bounds__(256, me2_min_waves<T>())
       cx<T> jamp[Proc::ncol];
 #pragma unroll
       for (int c = 0; c < Proc::ncol; ++c) jamp[c] = {T(0), T(0)};
-      Proc::template amplitudes<T>(p, prm, (unsigned)goodhel[k], (tab_ptr)tab, jamp);
+      Proc::template amplitudes<T>(p, prm, (unsigned)goodhel[k], (tab_of<T>)tab, jamp);
       if (colour_f32) {  // wave-uniform: the colour algebra in single precision
         cx<float> jf[Proc::ncol];
 #pragma unroll

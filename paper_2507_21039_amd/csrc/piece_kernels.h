@@ -47,8 +47,8 @@ struct WorkspaceSink {
 };
 
 // the per-event table in LDS, built by the event's lanes (as in me2_kernel)
-template <class Proc, int LPE>
-HME_FN void build_table(const double (&p)[Proc::npar][4], const ProcParams& prm, int sub, double* tab) {
+template <class Proc, int LPE, class S>
+HME_FN void build_table(const double (&p)[Proc::npar][4], const ProcParams& prm, int sub, S* tab) {
   for (int j = sub; j < Proc::nitems; j += LPE) Proc::table_entry(p, prm, j, tab);
 }
 
@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(256, HME_PIECE_WAVES)
                  const int* __restrict__ goodhel, int ngood, ProcParams prm, const int64_t* __restrict__ nevt_dev,
                  int64_t e0) {
   constexpr int EPW = 64 / LPE, EPB = 256 / LPE;
-  __shared__ double table[EPB * Proc::ntab];
+  __shared__ float table[EPB * Proc::ntab];
   const int lane = threadIdx.x & 63;
   nevt = sub_batch_events(nevt, nevt_dev, e0);
   if ((int64_t)blockIdx.x * EPB >= nevt) return;  // uniform per block
@@ -74,14 +74,14 @@ __global__ void __launch_bounds__(256, HME_PIECE_WAVES)
   const int64_t evc = ev < nevt ? ev : nevt - 1;  // ragged tail: recompute the last event, store nothing
   double p[Proc::npar][4];
   load_event<Proc>(mom, evc, p);
-  double* tab = table + (threadIdx.x / LPE) * Proc::ntab;
+  float* tab = table + (threadIdx.x / LPE) * Proc::ntab;
   build_table<Proc, LPE>(p, prm, sub, tab);
   __syncthreads();
   if (ev >= nevt) return;  // no barrier follows
   cx<float>* w = ws + (size_t)ev * Proc::nslot * ngood;
   for (int k = sub; k < ngood; k += LPE) {
     WorkspaceSink sink{w + k, ngood};
-    Chunk::template amplitudes<float>(prm, (unsigned)goodhel[k], (tab_ptr)tab, sink);
+    Chunk::template amplitudes<float>(prm, (unsigned)goodhel[k], (tab_of<float>)tab, sink);
   }
 }
 

@@ -461,7 +461,7 @@ struct {name}_c{c} {{
   // through sink.put(slot, value), to a workspace slot no other code writes; the colour
   // kernel adds up the slots of every flow (Base::gather).
   template <class T, class Sink>
-  HME_FN static void amplitudes(const ProcParams& prm, unsigned h, tab_ptr tab, Sink& sink) {{
+  HME_FN static void amplitudes(const ProcParams& prm, unsigned h, tab_of<T> tab, Sink& sink) {{
     auto hel = [h](int k) {{ return (h >> ({npar - 1} - k) & 1u) ? 1 : -1; }};
     const T mT = T(prm.mT);
     cx<T> jr[{jbudget}];
@@ -526,7 +526,7 @@ struct {name}_c{c} {{
   // arithmetic type (budget {budget[0]} / prefetch "{prefetch[0]}" for double, {budget[1]} / "{prefetch[1]}" for float)
   template <class T>
   HME_FN static void amplitudes(const double (&p)[{npar}][4], const ProcParams& prm, unsigned h,
-                                tab_ptr tab, cx<T> (&jamp)[{ncol}]) {{
+                                tab_of<T> tab, cx<T> (&jamp)[{ncol}]) {{
     if constexpr (sizeof(T) == 8)
       amplitudes_d<T>(prm, h, tab, jamp);
     else
@@ -534,14 +534,14 @@ struct {name}_c{c} {{
   }}
 
   template <class T>
-  HME_FN static void amplitudes_d(const ProcParams& prm, unsigned h, tab_ptr tab, cx<T> (&jamp)[{ncol}]) {{
+  HME_FN static void amplitudes_d(const ProcParams& prm, unsigned h, tab_of<T> tab, cx<T> (&jamp)[{ncol}]) {{
     auto hel = [h](int k) {{ return (h >> ({npar - 1} - k) & 1u) ? 1 : -1; }};
     const T mT = T(prm.mT);
 {body_d}
   }}
 
   template <class T>
-  HME_FN static void amplitudes_f(const ProcParams& prm, unsigned h, tab_ptr tab, cx<T> (&jamp)[{ncol}]) {{
+  HME_FN static void amplitudes_f(const ProcParams& prm, unsigned h, tab_of<T> tab, cx<T> (&jamp)[{ncol}]) {{
     auto hel = [h](int k) {{ return (h >> ({npar - 1} - k) & 1u) ? 1 : -1; }};
     const T mT = T(prm.mT);
 {body_f}
@@ -606,17 +606,17 @@ struct {name} {{
     }}
   }}
 
-  HME_FN static void vertex_kit(const double (&p)[{npar}][4], const ProcParams& prm, int v, double* o) {{
+  template <class S> HME_FN static void vertex_kit(const double (&p)[{npar}][4], const ProcParams& prm, int v, S* o) {{
     double A[4], B[4], C[4];
     mask_sum(p, vk_m0[v], A);
     if (vk_kind[v] == 1) {{
       const double den = 1.0 / (A[0] * A[0] - A[1] * A[1] - A[2] * A[2] - A[3] * A[3] - prm.mT * prm.mT);
       const double ds = den * vk_sign[v];
-      o[0] = ds * (A[0] + A[3]);
-      o[1] = ds * (A[0] - A[3]);
-      o[2] = ds * A[1];
-      o[3] = ds * A[2];
-      o[4] = den * prm.mT;
+      o[0] = S(ds * (A[0] + A[3]));
+      o[1] = S(ds * (A[0] - A[3]));
+      o[2] = S(ds * A[1]);
+      o[3] = S(ds * A[2]);
+      o[4] = S(den * prm.mT);
       return;
     }}
     mask_sum(p, vk_m1[v], B);
@@ -625,22 +625,23 @@ struct {name} {{
       const double den = 1.0 / (C[0] * C[0] - C[1] * C[1] - C[2] * C[2] - C[3] * C[3]);
 #pragma unroll
       for (int mu = 0; mu < 4; ++mu) {{
-        o[mu] = den * (A[mu] - B[mu]);
-        o[4 + mu] = den * (A[mu] + 2 * B[mu]);
-        o[8 + mu] = den * (2 * A[mu] + B[mu]);
+        o[mu] = S(den * (A[mu] - B[mu]));
+        o[4 + mu] = S(den * (A[mu] + 2 * B[mu]));
+        o[8 + mu] = S(den * (2 * A[mu] + B[mu]));
       }}
     }} else {{
 #pragma unroll
       for (int mu = 0; mu < 4; ++mu) {{
-        o[mu] = A[mu] - B[mu];
-        o[4 + mu] = B[mu] - C[mu];
-        o[8 + mu] = C[mu] - A[mu];
+        o[mu] = S(A[mu] - B[mu]);
+        o[4 + mu] = S(B[mu] - C[mu]);
+        o[8 + mu] = S(C[mu] - A[mu]);
       }}
     }}
   }}
 
   // item j of the table (j < nitems); the lanes of an event compute disjoint items
-  HME_FN static void table_entry(const double (&p)[{npar}][4], const ProcParams& prm, int j, double* tab) {{
+  template <class S>
+  HME_FN static void table_entry(const double (&p)[{npar}][4], const ProcParams& prm, int j, S* tab) {{
     if (j >= nq + nd + {npar}) {{
       const int v = j - nq - nd - {npar};
       vertex_kit(p, prm, v, tab + voff + vk_off[v]);
@@ -668,10 +669,10 @@ struct {name} {{
     if (isq) {{
       const double sg = qsign[j];
 #pragma unroll
-      for (int mu = 0; mu < 4; ++mu) tab[4 * j + mu] = sg * Q[mu];
+      for (int mu = 0; mu < 4; ++mu) tab[4 * j + mu] = S(sg * Q[mu]);
     }} else {{
       const double m2 = dmassive[j - nq] ? prm.mT * prm.mT : 0.0;
-      tab[4 * nq + (j - nq)] = 1.0 / (Q[0] * Q[0] - Q[1] * Q[1] - Q[2] * Q[2] - Q[3] * Q[3] - m2);
+      tab[4 * nq + (j - nq)] = S(1.0 / (Q[0] * Q[0] - Q[1] * Q[1] - Q[2] * Q[2] - Q[3] * Q[3] - m2));
     }}
   }}
 
@@ -734,11 +735,11 @@ struct {name} {{
   static constexpr double flops_per_event = 20.0;  // s, 1/s, Z propagator denominator
 
   static constexpr int nq = 0, nd = 0, nitems = 0, ntab = 0;  // no per-event table
-  HME_FN static void table_entry(const double (&)[4][4], const ProcParams&, int, double*) {{}}
+  template <class S> HME_FN static void table_entry(const double (&)[4][4], const ProcParams&, int, S*) {{}}
 
   template <class T>
   HME_FN static void amplitudes(const double (&p)[4][4], const ProcParams& prm, unsigned h,
-                                tab_ptr, cx<T> (&jamp)[1]) {{
+                                tab_of<T>, cx<T> (&jamp)[1]) {{
     auto hel = [h](int k) {{ return (h >> (3 - k) & 1u) ? 1 : -1; }};
     const sp4<T> w0 = cast<T>(oxxxxx(p[0], 0.0, hel(0), -1));  // vbar(e+)
     const sp4<T> w1 = cast<T>(ixxxxx(p[1], 0.0, hel(1), +1));  // u(e-)

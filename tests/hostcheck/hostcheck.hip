@@ -20,13 +20,13 @@ void run(const hme::ProcParams& prm, double alpha_s, int64_t nevt, const double*
     double p[Proc::npar][4];
     for (int k = 0; k < Proc::npar; ++k)
       for (int mu = 0; mu < 4; ++mu) p[k][mu] = mom[(e * Proc::npar + k) * 4 + mu];
-    double tab[Proc::ntab > 0 ? Proc::ntab : 1];
+    T tab[Proc::ntab > 0 ? Proc::ntab : 1];
     for (int j = 0; j < Proc::nitems; ++j) Proc::table_entry(p, prm, j, tab);
     double acc = 0;
     for (int h = 0; h < Proc::nhel; ++h) {
       hme::cx<T> jamp[Proc::ncol];
       for (auto& j : jamp) j = {T(0), T(0)};
-      Proc::template amplitudes<T>(p, prm, (unsigned)h, (hme::tab_ptr)tab, jamp);
+      Proc::template amplitudes<T>(p, prm, (unsigned)h, (hme::tab_of<T>)tab, jamp);
       const double v = (double)Proc::template colour_sum<T>(jamp) * norm;
       if (per_hel) per_hel[e * Proc::nhel + h] = v;
       acc += v;

@@ -36,7 +36,7 @@ template <class T> struct SlotSink {
 };
 
 template <class C, class T>
-void add_piece(const hme::ProcParams& prm, unsigned h, hme::tab_ptr tab, SlotSink<T>& sink) {
+void add_piece(const hme::ProcParams& prm, unsigned h, hme::tab_of<T> tab, SlotSink<T>& sink) {
   C::template amplitudes<T>(prm, h, tab, sink);
 }
 
@@ -49,7 +49,7 @@ void run(const hme::ProcParams& prm, double alpha_s, int64_t nevt, const double*
     double p[P::npar][4];
     for (int k = 0; k < P::npar; ++k)
       for (int mu = 0; mu < 4; ++mu) p[k][mu] = mom[(e * P::npar + k) * 4 + mu];
-    double tab[P::ntab];
+    T tab[P::ntab];
     for (int j = 0; j < P::nitems; ++j) P::table_entry(p, prm, j, tab);
     double acc = 0;
     for (int h = 0; h < P::nhel; ++h) {
@@ -57,7 +57,7 @@ void run(const hme::ProcParams& prm, double alpha_s, int64_t nevt, const double*
       static bool written[P::nslot];
       for (bool& x : written) x = false;
       SlotSink<T> sink{slots, written};
-      const auto t = (hme::tab_ptr)tab;
+      const auto t = (hme::tab_of<T>)tab;
       add_piece<hme::P_ggttggg_c0, T>(prm, h, t, sink);
       add_piece<hme::P_ggttggg_c1, T>(prm, h, t, sink);
       add_piece<hme::P_ggttggg_c2, T>(prm, h, t, sink);
