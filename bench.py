@@ -28,19 +28,19 @@ PEAK_HBM = 8.0e12
 # counter reads for a plain 256 MiB device copy.  Valid only for the kernel sources it was taken
 # on (sha256 prefix of me2_kernels.h + colour_mfma.h + helas.h + procs/ggttgg.h); otherwise
 # traffic is null.
-TRAFFIC = {"source_sha": "b6be980fd3b5473f", "nevt": 1048576,
-           "fetch_kib": 198169.5625, "write_kib": 8192.0, "fetch_factor": 262144 / 131088.8125, "write_factor": 1.0}
+TRAFFIC = {"source_sha": "f64fa9a3ee127763", "nevt": 1048576,
+           "fetch_kib": 198114.5, "write_kib": 8192.0, "fetch_factor": 262144 / 131088.875, "write_factor": 1.0}
 
 # VALU and MFMA instruction counters of the same launches (profiles/me2_ggttgg_1M_valu_counters.md),
 # wave instructions summed over the device: FLOPs = 64 lanes x (2 FMA + ADD + MUL + TRANS) plus
 # 512 per MFMA "MOPS" unit (the counter's own scale).
 COUNTERS = {
-    "source_sha": "b6be980fd3b5473f", "nevt": 1048576,
-    "fp64": {"FMA_F64": 16802381824, "ADD_F64": 3300917248, "MUL_F64": 4637851648, "TRANS_F64": 39845888,
-             "VALU": 25321013248},
-    "mixed_fast": {"FMA_F32": 13234077696, "ADD_F32": 3046113280, "MUL_F32": 3572498432, "TRANS_F32": 0,
-                   "FMA_F64": 322961408, "ADD_F64": 17825792, "MUL_F64": 132120576, "TRANS_F64": 39845888,
-                   "MFMA_MOPS_BF16": 2684354560, "VALU": 24559747072},
+    "source_sha": "f64fa9a3ee127763", "nevt": 1048576,
+    "fp64": {"FMA_F64": 16571695104, "ADD_F64": 2621440000, "MUL_F64": 3951034368, "TRANS_F64": 45088768,
+             "VALU": 23765975040},
+    "mixed_fast": {"FMA_F32": 13015973888, "ADD_F32": 2454716416, "MUL_F32": 3052404736, "TRANS_F32": 0,
+                   "FMA_F64": 392167424, "ADD_F64": 30408704, "MUL_F64": 147849216, "TRANS_F64": 40894464,
+                   "MFMA_MOPS_BF16": 2684354560, "VALU": 20260585472},
 }
 
 
