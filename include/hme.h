@@ -90,7 +90,8 @@ int hme_create(int process, const hme_sm_card* card, int precision, int device, 
  * strong coupling for this call.  nevt = 0 is a successful no-op; any nevt >= 1
  * is valid (partial wavefronts are masked).  Not thread-safe per handle.
  * HME_GGTTGGG also takes a device workspace of min(nevt, 8192) events times
- * hme_info.workspace_bytes_per_event (about 2 MB per event), allocated and released on
+ * hme_info.workspace_bytes_per_event (partial-jamp slots x good helicities x the size of a
+ * complex jamp: 789 x 128 x 8 bytes = 0.81 MB per event in single precision), allocated and released on
  * `hip_stream` in stream order (HME_E_OOM if that fails); larger batches run as
  * consecutive sub-batches of 8192 events. */
 int hme_compute(hme_handle* h, double alpha_s, int64_t nevt, const double* momenta, double* me2, void* hip_stream);
@@ -173,6 +174,14 @@ int hme_rambo(int process, const hme_sm_card* card, double sqrt_s, uint64_t seed
  * Returns HME_E_ARG for nevt < 0 or a NULL / misaligned buffer. */
 int hme_weighted_sum(const double* me2, const double* weights, int64_t nevt, double* out, void* hip_stream);
 
+/* The flat Monte Carlo cross section and its statistical error, in pb, from the two sums of
+ * hme_weighted_sum over npoints points (sums: a HOST pointer to those two doubles, copied back by
+ * the caller): sigma = sums[0] / (2 s npoints) times (hbar c)^2 = 0.3893793721e9 GeV^2 pb (flux
+ * of massless colliding partons, s = sqrt_s^2), error = sqrt(sums[1] / npoints -
+ * (sums[0] / npoints)^2) / sqrt(npoints) / (2 s) in the same units.  Host arithmetic only.
+ * Returns HME_E_ARG for NULL pointers, npoints <= 0 or sqrt_s <= 0. */
+int hme_flat_cross_section(const double* sums, int64_t npoints, double sqrt_s, double* sigma_pb, double* error_pb);
+
 /* ------------------------------------------------------------------ serving
  * A persistent request loop over every process of the library on one device
  * (the paper's multi-event interface and gridpack workers, section "Event
@@ -208,13 +217,24 @@ int hme_server_create(const hme_sm_card* card, int precision, int device, size_t
 /* Queue |M|^2 of nevt events of `process`.  momenta_dev / me2_dev are caller-owned
  * device pointers that must stay valid until hme_wait returns for *req_id.
  * Returns HME_E_BUDGET if the request cannot fit in one slot; nothing is copied
- * at submit time. */
+ * at submit time.  The server's streams do not wait for any stream of the caller: the
+ * momenta must already be complete in device memory (for instance the stream that wrote them
+ * synchronized) when hme_submit is called; use hme_submit_after otherwise. */
 int hme_submit(hme_server* s, int process, double alpha_s, int64_t nevt, const double* momenta_dev, double* me2_dev,
                uint64_t* req_id);
 
+/* As hme_submit, for momenta still being produced on the caller's stream `producer_stream`
+ * (a hipStream_t on the server's device, NULL for the default stream): the server records an
+ * event on that stream at submit time, and the request's batch reads the momenta only after
+ * the work queued there before the call has finished.  HME_E_HIP if the event cannot be
+ * recorded. */
+int hme_submit_after(hme_server* s, int process, double alpha_s, int64_t nevt, const double* momenta_dev,
+                     double* me2_dev, void* producer_stream, uint64_t* req_id);
+
 /* Wait for a request: HME_OK once its |M|^2 are in me2_dev (the request is then
  * forgotten), HME_E_TIMEOUT if timeout_s (< 0: forever) passes first, HME_E_ARG
- * for an unknown id, HME_E_HIP if its batch failed. */
+ * for an unknown id, HME_E_HIP if its batch failed (hme_last_error on the waiting thread
+ * then names the failing HIP call). */
 int hme_wait(hme_server* s, uint64_t req_id, double timeout_s);
 
 /* As hme_wait; on HME_OK also stores the request's latency from hme_submit to the end of

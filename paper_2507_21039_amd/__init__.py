@@ -27,7 +27,8 @@ HME_OK, HME_E_ARG, HME_E_HIP, HME_E_OOM, HME_E_BUDGET, HME_E_TIMEOUT, HME_E_UNSU
 
 EXPORTED = ("hme_create", "hme_compute", "hme_query", "hme_good_helicities", "hme_destroy", "hme_last_error",
             "hme_server_create", "hme_submit", "hme_wait", "hme_wait_timed", "hme_server_stats_get",
-            "hme_server_destroy", "hme_rambo", "hme_weighted_sum", "hme_compute_select", "hme_compute_alphas")
+            "hme_server_destroy", "hme_rambo", "hme_weighted_sum", "hme_compute_select", "hme_compute_alphas",
+            "hme_submit_after", "hme_flat_cross_section")
 
 
 class SmCard(ctypes.Structure):
@@ -80,6 +81,10 @@ def lib():
                                         ctypes.c_int, ctypes.POINTER(vp)]
         L.hme_submit.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_int64, vp, vp,
                                  ctypes.POINTER(ctypes.c_uint64)]
+        L.hme_submit_after.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_int64, vp, vp, vp,
+                                       ctypes.POINTER(ctypes.c_uint64)]
+        L.hme_flat_cross_section.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_int64, ctypes.c_double,
+                                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.hme_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_double]
         L.hme_wait_timed.argtypes = [vp, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
         L.hme_server_stats_get.argtypes = [vp, ctypes.POINTER(ServerStats)]
@@ -92,7 +97,7 @@ def lib():
         for name in ("hme_create", "hme_compute", "hme_query", "hme_good_helicities", "hme_destroy",
                      "hme_server_create", "hme_submit", "hme_wait", "hme_wait_timed", "hme_server_stats_get",
                      "hme_server_destroy", "hme_rambo", "hme_weighted_sum", "hme_compute_select",
-                     "hme_compute_alphas"):
+                     "hme_compute_alphas", "hme_submit_after", "hme_flat_cross_section"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -168,12 +173,12 @@ def weighted_sum(me2, weights, stream=None):
 
 
 def cross_section_pb(sums, nevt: int, sqrt_s: float):
-    """Flat Monte Carlo cross section and its error in pb from weighted_sum's two sums."""
-    s1, s2 = float(sums[0]), float(sums[1])
-    flux = 2.0 * sqrt_s * sqrt_s
-    mean = s1 / nevt
-    var = max(s2 / nevt - mean * mean, 0.0)
-    return mean / flux * GEV2_TO_PB, (var / nevt) ** 0.5 / flux * GEV2_TO_PB
+    """Flat Monte Carlo cross section and its error in pb from weighted_sum's two sums
+    (hme_flat_cross_section)."""
+    arr = (ctypes.c_double * 2)(float(sums[0]), float(sums[1]))
+    sigma, err = ctypes.c_double(), ctypes.c_double()
+    _check(lib().hme_flat_cross_section(arr, int(nevt), float(sqrt_s), ctypes.byref(sigma), ctypes.byref(err)))
+    return sigma.value, err.value
 
 
 class Handle:
@@ -292,13 +297,25 @@ class Server:
                                 ctypes.c_void_p(me2_ptr), ctypes.byref(rid)))
         return rid.value
 
-    def submit(self, process: int, momenta, out, alpha_s: float = 0.118) -> int:
-        """momenta [nevt, npar, 4] float64 GPU tensor, out [nevt] float64 GPU tensor (kept alive by the caller)."""
+    def submit_after_ptr(self, process: int, alpha_s: float, nevt: int, momenta_ptr: int, me2_ptr: int,
+                         stream_ptr: int) -> int:
+        rid = ctypes.c_uint64()
+        _check(lib().hme_submit_after(self._s, process, float(alpha_s), int(nevt), ctypes.c_void_p(momenta_ptr),
+                                      ctypes.c_void_p(me2_ptr), ctypes.c_void_p(stream_ptr), ctypes.byref(rid)))
+        return rid.value
+
+    def submit(self, process: int, momenta, out, alpha_s: float = 0.118, stream=None) -> int:
+        """momenta [nevt, npar, 4] float64 GPU tensor, out [nevt] float64 GPU tensor (kept alive by the caller).
+        The request reads the momenta after the work queued so far on `stream` (default: torch's current
+        stream), so they may still be in flight there (hme_submit_after)."""
+        import torch
         if momenta.dim() != 3 or momenta.shape[1] != NPAR[process] or not momenta.is_contiguous():
             raise ValueError(f"momenta must be contiguous [nevt, {NPAR[process]}, 4]")
         if out.numel() < momenta.shape[0] or not out.is_contiguous():
             raise ValueError("out too small or not contiguous")
-        return self.submit_ptr(process, alpha_s, momenta.shape[0], momenta.data_ptr(), out.data_ptr())
+        s = stream if stream is not None else torch.cuda.current_stream(momenta.device)
+        return self.submit_after_ptr(process, alpha_s, momenta.shape[0], momenta.data_ptr(), out.data_ptr(),
+                                     s.cuda_stream)
 
     def wait(self, req_id: int, timeout_s: float = -1.0):
         """Returns the request's submit-to-completion latency in seconds, or None on timeout."""

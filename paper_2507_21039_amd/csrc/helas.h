@@ -505,6 +505,52 @@ template <class T> HME_FN sp4<T> ffv_psibar_k(const sp4<T>& fb, const vw4<T>& V,
   return o;
 }
 
+// ------------------------------------------------------------------ compensated per-event arithmetic
+// A propagator denominator Q^2 - m^2 of an almost on-shell line is a small difference of large
+// numbers (soft or collinear emissions), so the rounding of the momentum sum Q and of Q^2 is
+// amplified by Q0^2 / |Q^2 - m^2|.  The per-event table therefore forms momentum sums, their
+// differences and Q^2 - m^2 as unevaluated sums hi + lo of two doubles (error-free
+// transformations: Knuth's two-sum, and the exact product a b = p + fma(a, b, -p)), and rounds
+// once at the end.  This runs once per event, not per helicity.
+struct dd {
+  double hi, lo;
+};
+HME_FN dd two_sum(double a, double b) {
+  const double s = a + b;
+  const double bb = s - a;
+  return {s, (a - (s - bb)) + (b - bb)};
+}
+HME_FN dd quick_two_sum(double a, double b) {  // |a| >= |b|
+  const double s = a + b;
+  return {s, b - (s - a)};
+}
+HME_FN dd dd_add(dd a, dd b) {
+  const dd s = two_sum(a.hi, b.hi);
+  return quick_two_sum(s.hi, s.lo + (a.lo + b.lo));
+}
+HME_FN dd dd_scale(double k, dd a) {  // k a for a small integer k (exact)
+  return {k * a.hi, k * a.lo};
+}
+HME_FN dd dd_neg(dd a) { return {-a.hi, -a.lo}; }
+HME_FN dd two_prod(double a, double b) {
+  const double p = a * b;
+  return {p, __builtin_fma(a, b, -p)};
+}
+HME_FN dd dd_sq(dd a) {
+  const dd p = two_prod(a.hi, a.hi);
+  return quick_two_sum(p.hi, __builtin_fma(2.0 * a.hi, a.lo, p.lo));
+}
+HME_FN double dd_val(dd a) { return a.hi + a.lo; }
+// Minkowski square minus m^2 of a compensated four-vector, rounded once
+HME_FN double dd_minkowski_sq(const dd* Q, double m) {
+  dd s = dd_sq(Q[0]);
+  s = dd_add(s, dd_neg(dd_sq(Q[1])));
+  s = dd_add(s, dd_neg(dd_sq(Q[2])));
+  s = dd_add(s, dd_neg(dd_sq(Q[3])));
+  if (m != 0.0) s = dd_add(s, dd_neg(two_prod(m, m)));
+  return dd_val(s);
+}
+
 // Scheduling fence for the generated code: table reads issued before it are not moved
 // past it, so their LDS latency overlaps the arithmetic that follows.
 #if defined(__HIP_DEVICE_COMPILE__)

@@ -42,7 +42,7 @@ static const ProcEntry kProcs[] = {
     {info_ggttggg, launch_me2_ggttggg, launch_hel_ggttggg, true, 2000.0},
 };
 
-// events per sub-batch of a process evaluated in pieces (workspace ncol * ngood * 8 bytes each)
+// events per sub-batch of a process evaluated in pieces (workspace nslot * ngood * sizeof(cx) bytes each)
 constexpr int64_t kChunkSubBatch = 8192;
 constexpr int kNumProcs = sizeof(kProcs) / sizeof(kProcs[0]);
 

@@ -302,3 +302,24 @@ extern "C" int hme_weighted_sum(const double* me2, const double* weights, int64_
   if (e != hipSuccess) return rambo_fail(HME_E_HIP, std::string("hme_weighted_sum: ") + hipGetErrorString(e));
   return HME_OK;
 }
+
+// Flat Monte Carlo cross section from the two sums of hme_weighted_sum (host arithmetic):
+// sigma = (1 / (2 s)) (1 / N) sum_i w_i |M_i|^2, the flux factor of massless colliding
+// partons times the mean of weight x |M|^2 (the integral over flat phase space of the paper's
+// standalone application), converted from GeV^-2 to pb with (hbar c)^2 = 0.3893793721e9 GeV^2 pb;
+// its error from the variance of w |M|^2 over the N points.
+extern "C" int hme_flat_cross_section(const double* sums, int64_t npoints, double sqrt_s, double* sigma_pb,
+                                      double* error_pb) {
+  if (!sums || !sigma_pb || !error_pb) return rambo_fail(HME_E_ARG, "hme_flat_cross_section: NULL argument");
+  if (npoints <= 0) return rambo_fail(HME_E_ARG, "hme_flat_cross_section: npoints must be positive");
+  if (!(sqrt_s > 0)) return rambo_fail(HME_E_ARG, "hme_flat_cross_section: sqrt_s must be positive");
+  constexpr double kGeV2ToPb = 0.3893793721e9;
+  const double flux = 2.0 * sqrt_s * sqrt_s;
+  const double n = (double)npoints;
+  const double mean = sums[0] / n;
+  double var = sums[1] / n - mean * mean;
+  if (var < 0) var = 0;
+  *sigma_pb = mean / flux * kGeV2ToPb;
+  *error_pb = std::sqrt(var / n) / flux * kGeV2ToPb;
+  return HME_OK;
+}

@@ -79,6 +79,8 @@ struct Request {
   double* out;
   bool done = false;
   int status = HME_OK;
+  std::string error;               // message of a failed batch, handed to the waiting thread
+  hipEvent_t ready = nullptr;      // recorded on the producer stream at submit (hme_submit_after)
   std::chrono::steady_clock::time_point t_submit, t_done;
 };
 
@@ -216,11 +218,12 @@ struct Server : hme_server {
   }
 
   void fail_batch(Batch* b, hipError_t e) {
-    hme::set_last_error(std::string("server batch: ") + hipGetErrorString(e));
+    const std::string msg = std::string("server batch: ") + hipGetErrorString(e);
     std::lock_guard<std::mutex> lk(mu);
     for (auto& r : b->reqs) {
       r->done = true;
       r->status = HME_E_HIP;
+      r->error = msg;
       r->t_done = std::chrono::steady_clock::now();
     }
     slots[b->slot].busy = false;
@@ -280,6 +283,14 @@ struct Server : hme_server {
       }
       hipGraphExec_t ex = nullptr;
       hipError_t e = graph_for(sl, head->process, bucket_for(total, cap), &ex);
+      // requests submitted with a producer stream: the gather reads their momenta only after
+      // the work queued on that stream before the submit
+      for (auto& r : b->reqs) {
+        if (!r->ready) continue;
+        if (e == hipSuccess) e = hipStreamWaitEvent(sl.stream, r->ready, 0);
+        (void)hipEventDestroy(r->ready);  // released once the event has completed
+        r->ready = nullptr;
+      }
       if (e == hipSuccess) e = hipGraphLaunch(ex, sl.stream);
       if (e == hipSuccess) e = hipLaunchHostFunc(sl.stream, &Server::on_batch_done, b);
       if (e != hipSuccess) {
@@ -355,8 +366,8 @@ int hme_server_create(const hme_sm_card* card, int precision, int device, size_t
   return HME_OK;
 }
 
-int hme_submit(hme_server* srv, int process, double alpha_s, int64_t nevt, const double* momenta_dev, double* me2_dev,
-               uint64_t* req_id) {
+static int submit_impl(hme_server* srv, int process, double alpha_s, int64_t nevt, const double* momenta_dev,
+                       double* me2_dev, bool after, void* producer_stream, uint64_t* req_id) {
   auto* s = static_cast<Server*>(srv);
   if (!s || !req_id) return srv_fail(HME_E_ARG, "hme_submit: NULL server or req_id");
   if (process < 0 || process >= kNumProcesses) return srv_fail(HME_E_ARG, "hme_submit: unknown process");
@@ -374,9 +385,24 @@ int hme_submit(hme_server* srv, int process, double alpha_s, int64_t nevt, const
   r->nevt = nevt;
   r->mom = momenta_dev;
   r->out = me2_dev;
+  if (after && nevt > 0) {
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    hipError_t e = hipSetDevice(s->device);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&r->ready, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(r->ready, static_cast<hipStream_t>(producer_stream));
+    (void)hipSetDevice(prev);
+    if (e != hipSuccess) {
+      if (r->ready) (void)hipEventDestroy(r->ready);
+      return srv_fail(HME_E_HIP, std::string("hme_submit_after: ") + hipGetErrorString(e));
+    }
+  }
   {
     std::lock_guard<std::mutex> lk(s->mu);
-    if (s->stop) return srv_fail(HME_E_ARG, "hme_submit: server is shutting down");
+    if (s->stop) {
+      if (r->ready) (void)hipEventDestroy(r->ready);
+      return srv_fail(HME_E_ARG, "hme_submit: server is shutting down");
+    }
     r->id = s->next_id++;
     s->requests[r->id] = r;
     s->stats.submitted++;
@@ -391,6 +417,16 @@ int hme_submit(hme_server* srv, int process, double alpha_s, int64_t nevt, const
   s->cv_sched.notify_one();
   *req_id = r->id;
   return HME_OK;
+}
+
+int hme_submit(hme_server* srv, int process, double alpha_s, int64_t nevt, const double* momenta_dev, double* me2_dev,
+               uint64_t* req_id) {
+  return submit_impl(srv, process, alpha_s, nevt, momenta_dev, me2_dev, false, nullptr, req_id);
+}
+
+int hme_submit_after(hme_server* srv, int process, double alpha_s, int64_t nevt, const double* momenta_dev,
+                     double* me2_dev, void* producer_stream, uint64_t* req_id) {
+  return submit_impl(srv, process, alpha_s, nevt, momenta_dev, me2_dev, true, producer_stream, req_id);
 }
 
 int hme_wait(hme_server* srv, uint64_t req_id, double timeout_s) {
@@ -411,6 +447,7 @@ int hme_wait_timed(hme_server* srv, uint64_t req_id, double timeout_s, double* l
   }
   s->requests.erase(req_id);
   if (latency_s) *latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
+  if (r->status != HME_OK) return srv_fail(r->status, "hme_wait: " + r->error);
   return r->status;
 }
 

@@ -595,46 +595,49 @@ struct {name} {{
   static constexpr int vk_sign[{max(nvk, 1)}] = {{{", ".join(str(x[4]) for x in vk_list) or "1"}}};
   static constexpr int vk_off[{max(nvk, 1)}] = {{{", ".join(str(x[5]) for x in vk_list) or "0"}}};
 
-  // sum of the incoming momenta of the particles in mask m (outgoing ones negated)
-  HME_FN static void mask_sum(const double (&p)[{npar}][4], unsigned m, double* Q) {{
-    Q[0] = Q[1] = Q[2] = Q[3] = 0.0;
+  // sum of the incoming momenta of the particles in mask m (outgoing ones negated), each
+  // component as a compensated sum (exact for up to {npar} terms); k: a factor applied to every term
+  HME_FN static void mask_sum(const double (&p)[{npar}][4], unsigned m, dd* Q, double k = 1.0) {{
+    Q[0] = Q[1] = Q[2] = Q[3] = dd{{0.0, 0.0}};
 #pragma unroll
-    for (int k = 0; k < {npar}; ++k) {{
-      const double s = (m >> k & 1u) ? (k < 2 ? 1.0 : -1.0) : 0.0;
+    for (int j = 0; j < {npar}; ++j) {{
+      const double s = (m >> j & 1u) ? (j < 2 ? k : -k) : 0.0;
 #pragma unroll
-      for (int mu = 0; mu < 4; ++mu) Q[mu] += s * p[k][mu];
+      for (int mu = 0; mu < 4; ++mu) Q[mu] = dd_add(Q[mu], two_prod(s, p[j][mu]));
     }}
   }}
 
+  // the quantities below are formed in compensated arithmetic and rounded once
+  // (differences of momentum sums, and Q^2 - m^2 of almost on-shell propagators)
   template <class S> HME_FN static void vertex_kit(const double (&p)[{npar}][4], const ProcParams& prm, int v, S* o) {{
-    double A[4], B[4], C[4];
+    dd A[4], B[4], C[4];
     mask_sum(p, vk_m0[v], A);
     if (vk_kind[v] == 1) {{
-      const double den = 1.0 / (A[0] * A[0] - A[1] * A[1] - A[2] * A[2] - A[3] * A[3] - prm.mT * prm.mT);
+      const double den = 1.0 / dd_minkowski_sq(A, prm.mT);
       const double ds = den * vk_sign[v];
-      o[0] = S(ds * (A[0] + A[3]));
-      o[1] = S(ds * (A[0] - A[3]));
-      o[2] = S(ds * A[1]);
-      o[3] = S(ds * A[2]);
+      o[0] = S(ds * dd_val(dd_add(A[0], A[3])));
+      o[1] = S(ds * dd_val(dd_add(A[0], dd_neg(A[3]))));
+      o[2] = S(ds * dd_val(A[1]));
+      o[3] = S(ds * dd_val(A[2]));
       o[4] = S(den * prm.mT);
       return;
     }}
     mask_sum(p, vk_m1[v], B);
     mask_sum(p, vk_m2[v], C);
     if (vk_kind[v] == 0) {{
-      const double den = 1.0 / (C[0] * C[0] - C[1] * C[1] - C[2] * C[2] - C[3] * C[3]);
+      const double den = 1.0 / dd_minkowski_sq(C, 0.0);
 #pragma unroll
       for (int mu = 0; mu < 4; ++mu) {{
-        o[mu] = S(den * (A[mu] - B[mu]));
-        o[4 + mu] = S(den * (A[mu] + 2 * B[mu]));
-        o[8 + mu] = S(den * (2 * A[mu] + B[mu]));
+        o[mu] = S(den * dd_val(dd_add(A[mu], dd_neg(B[mu]))));
+        o[4 + mu] = S(den * dd_val(dd_add(A[mu], dd_scale(2.0, B[mu]))));
+        o[8 + mu] = S(den * dd_val(dd_add(dd_scale(2.0, A[mu]), B[mu])));
       }}
     }} else {{
 #pragma unroll
       for (int mu = 0; mu < 4; ++mu) {{
-        o[mu] = S(A[mu] - B[mu]);
-        o[4 + mu] = S(B[mu] - C[mu]);
-        o[8 + mu] = S(C[mu] - A[mu]);
+        o[mu] = S(dd_val(dd_add(A[mu], dd_neg(B[mu]))));
+        o[4 + mu] = S(dd_val(dd_add(B[mu], dd_neg(C[mu]))));
+        o[8 + mu] = S(dd_val(dd_add(C[mu], dd_neg(A[mu]))));
       }}
     }}
   }}
@@ -658,21 +661,14 @@ struct {name} {{
       return;
     }}
     const bool isq = j < nq;
-    const unsigned m = isq ? qmask[j] : dmask[j - nq];
-    double Q[4] = {{0, 0, 0, 0}};
-#pragma unroll
-    for (int k = 0; k < {npar}; ++k) {{
-      const double s = (m >> k & 1u) ? (k < 2 ? 1.0 : -1.0) : 0.0;
-#pragma unroll
-      for (int mu = 0; mu < 4; ++mu) Q[mu] += s * p[k][mu];
-    }}
+    dd Q[4];
+    mask_sum(p, isq ? qmask[j] : dmask[j - nq], Q);
     if (isq) {{
       const double sg = qsign[j];
 #pragma unroll
-      for (int mu = 0; mu < 4; ++mu) tab[4 * j + mu] = S(sg * Q[mu]);
+      for (int mu = 0; mu < 4; ++mu) tab[4 * j + mu] = S(sg * dd_val(Q[mu]));
     }} else {{
-      const double m2 = dmassive[j - nq] ? prm.mT * prm.mT : 0.0;
-      tab[4 * nq + (j - nq)] = S(1.0 / (Q[0] * Q[0] - Q[1] * Q[1] - Q[2] * Q[2] - Q[3] * Q[3] - m2));
+      tab[4 * nq + (j - nq)] = S(1.0 / dd_minkowski_sq(Q, dmassive[j - nq] ? prm.mT : 0.0));
     }}
   }}
 

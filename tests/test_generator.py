@@ -87,9 +87,32 @@ def test_generated_code_on_host_matches_oracle(hostlib, card, key, proc, n):
     p = configs.WORKLOADS[key].momenta(n)
     ref = oracle.me2(proc, p, card)
     got = host_me2(hostlib, proc, 0, p, card)
-    assert np.abs(got / ref - 1).max() <= 1e-13
+    rel = np.abs(got / ref - 1)
+    far = rel > 1e-13  # decided by the long double oracle (the FP64 oracle's own rounding)
+    if far.any():
+        ld = oracle.me2(proc, p[far], card, extended=True)
+        assert np.abs(got[far] / ld - 1).max() <= 1e-13
     mixed = host_me2(hostlib, proc, 1, p, card)
     assert np.abs(mixed / ref - 1).max() <= 1e-5
+
+
+@pytest.mark.parametrize("key,proc,n,first", [("ggttg", 2, 3000, 0), ("ggttgg", 3, 1500, 500000)])
+def test_generated_fp64_against_extended_precision(hostlib, card, key, proc, n, first):
+    """The generated FP64 code against the long double oracle (the exact value of the same
+    double inputs).  The per-event table forms momentum sums and Q^2 - m^2 in compensated
+    arithmetic, so the generated code stays within 5e-14 even on events where the FP64 oracle,
+    which forms Q^2 - m^2 directly, is off by 1e-13 or more (the first gg -> ttbar gg sample
+    below holds such events)."""
+    p = configs.WORKLOADS[key].momenta(n, first_event=first)
+    ld = oracle.me2(proc, p, card, extended=True)
+    got = host_me2(hostlib, proc, 0, p, card)
+    ora = oracle.me2(proc, p, card)
+    err_gen = np.abs(got / ld - 1)
+    err_ora = np.abs(ora / ld - 1)
+    print(f"generated max {err_gen.max():.3g}, FP64 oracle max {err_ora.max():.3g}")
+    assert err_gen.max() <= 5e-14
+    if key == "ggttgg":
+        assert err_ora.max() > 1e-13  # the sample does exercise the ill-conditioned case
 
 
 HOSTLIB7 = os.path.join(HERE, "_build", "libhostcheck7.so")

@@ -80,13 +80,47 @@ def test_gggg_closed_form(card):
     assert np.abs(me / cf - 1).max() <= 1e-13
 
 
-@pytest.mark.parametrize("proc,key,nevt", [(oracle.GGTT, "ggtt", 200), (oracle.GGTTG, "ggttg", 6),
-                                           (oracle.GGTTGG, "ggttgg", 1)])
+@pytest.mark.parametrize("proc,key,nevt", [(oracle.GGTT, "ggtt", 200), (oracle.GGTTG, "ggttg", 40),
+                                           (oracle.GGTTGG, "ggttgg", 16)])
 def test_dressed_equals_ordered(card, proc, key, nevt):
-    p = configs.WORKLOADS[key].momenta(nevt)
+    """|M|^2 summed over every external colour assignment with explicit generators (the plain
+    definition) equals the colour-ordered amplitudes contracted with the colour matrix."""
+    p = configs.WORKLOADS[key].momenta(nevt, first_event=100)
     a = oracle.me2(proc, p, card, AS, mode=oracle.DRESSED)
     b = oracle.me2(proc, p, card, AS, mode=oracle.ORDERED)
     assert np.abs(a / b - 1).max() <= 1e-12
+
+
+@pytest.mark.parametrize("key,n", [("ggttg", 3), ("ggttgg", 4), ("ggttggg", 5)])
+def test_dressed_amplitude_is_sum_over_orderings(card, key, n):
+    """Colour decomposition amplitude by amplitude: for explicit gluon colours a_k and quark colours
+    (i, j), the colour-dressed amplitude (every Feynman diagram with explicit generators and
+    structure constants) equals sum over orderings s of (T^a_s1 ... T^a_sn)_ij A(s), for random
+    spin and colour assignments.  This pins the n = 5 ordered amplitudes (four-gluon terms
+    included) to the plain definition, where the summed |M|^2 would take hours."""
+    T, _ = oracle.su3()
+    perms = list(itertools.permutations(range(n)))
+    rng = np.random.default_rng(20 + n)
+    p = configs.WORKLOADS[key].momenta(3, first_event=200)
+    checked = 0
+    for ev in p:
+        for _ in range(3):
+            sp = rng.integers(0, 2, n + 2)
+            A = oracle.partial_amps(ev, card, sp)
+            scale = np.abs(A).max()
+            for _ in range(12):
+                col = rng.integers(0, 8, n)
+                i3, j4 = (int(x) for x in rng.integers(0, 3, 2))
+                dressed = oracle.dressed_amp(ev, card, sp, col, i3, j4)
+                ordered = 0j
+                for s, perm in enumerate(perms):
+                    M = np.eye(3, dtype=complex)
+                    for g in perm:
+                        M = M @ T[col[g]]
+                    ordered += M[i3, j4] * A[s]
+                assert abs(dressed - ordered) <= 1e-13 * scale
+                checked += abs(dressed) > 1e-3 * scale
+    assert checked >= 20  # most assignments give a nonzero amplitude
 
 
 def _random_spins(rng, npar):

@@ -1,15 +1,15 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same seeded inputs.
 
 Gates (relative difference in |M|^2):
-  FP64: 1e-12 against the FP64 oracle in every event, with arbitration.  The two
-    evaluations share no code (Feynman diagrams in the chiral basis against
-    Berends-Giele recursion in the Dirac basis), so on ill-conditioned events
-    (large cancellations between diagrams, e.g. soft or collinear gluons) both
-    lose digits, each in its own way.  An event whose two FP64 values differ by
-    more than 1e-12 is decided by the extended-precision (long double) oracle:
-    the GPU value must lie within max(1e-12, 100 x the FP64 oracle's own error)
-    of it, and never more than 1e-8 away.  The bulk is gated separately: the
-    99th percentile against the FP64 oracle must stay at or below 1e-13.
+  FP64: 1e-12 against the exact value of the same double-precision inputs, in every event.
+    The FP64 oracle is compared first; an event whose two FP64 values differ by more than
+    1e-12 is decided by the extended-precision (long double) oracle, which the GPU value
+    itself must match to 1e-12 (no allowance beyond the gate).  Both the GPU's and the
+    FP64 oracle's errors against long double are printed for every such event.  The
+    two FP64 evaluations share no code; the oracle's own error on ill-conditioned events
+    (almost on-shell propagators of soft or collinear gluons: Q^2 - m^2 formed from
+    large momenta) reaches a few 1e-12, while the library forms Q^2 - m^2 in compensated
+    arithmetic and stays near 1e-14.
   MIXED_PAPER (double amplitudes, single-precision colour algebra): 1e-5.
   MIXED_FAST (single-precision vertices, propagators, jamps): 1e-5 for the
     99th percentile and 1e-3 for the maximum (single-precision cancellation
@@ -61,18 +61,17 @@ def run(h, p, alpha_s=AS):
     return out.cpu().numpy()
 
 
-def fp64_gate(proc, p, got, ref, card):
-    """Apply the FP64 gate with extended-precision arbitration; returns (max_rel, n_arbitrated)."""
+def fp64_gate(proc, p, got, ref, card, alpha_s=AS):
+    """The FP64 gate with extended-precision arbitration; returns (max_rel, n_arbitrated)."""
     rel = np.abs(got / ref - 1)
     bad = np.nonzero(~(rel <= FP64_TOL))[0]
     if bad.size:
-        ld = oracle.me2(proc, p[bad], card, AS, extended=True)
+        ld = oracle.me2(proc, p[bad], card, alpha_s, extended=True)
         gpu_err = np.abs(got[bad] / ld - 1)
         ora_err = np.abs(ref[bad] / ld - 1)
-        allowed = np.minimum(np.maximum(100 * ora_err, FP64_TOL), 1e-8)
-        for i, e, a, o in zip(bad, gpu_err, allowed, ora_err):
-            print(f"  arbitrated event {i}: gpu-vs-ld {e:.3g}, oracle-vs-ld {o:.3g}, allowed {a:.3g}")
-        assert np.all(gpu_err <= allowed), "FP64 result outside the arbitrated tolerance"
+        for i, e, o in zip(bad, gpu_err, ora_err):
+            print(f"  arbitrated event {i}: gpu-vs-ld {e:.3g}, oracle-vs-ld {o:.3g}")
+        assert np.all(gpu_err <= FP64_TOL), "FP64 result more than 1e-12 from the extended-precision value"
     return float(rel.max()), int(bad.size)
 
 
@@ -127,7 +126,7 @@ def test_fp64_ggttgg_large_sample(handles, card):
     fast = np.abs(run(handles[(hme.GGTTGG, hme.MIXED_FAST)], p) / ref - 1)
     print(f"  mixed_paper max {paper.max():.3g} p99 {np.quantile(paper, 0.99):.3g}; "
           f"mixed_fast max {fast.max():.3g} p99 {np.quantile(fast, 0.99):.3g}")
-    assert np.quantile(paper, 0.99) <= 1e-6 and paper.max() <= 1e-4
+    assert np.quantile(paper, 0.99) <= 1e-6 and paper.max() <= MIXED_TOL
     assert np.quantile(fast, 0.99) <= MIXED_TOL and fast.max() <= 1e-3
 
 
@@ -219,17 +218,50 @@ def test_nan_in_nan_out(handles):
     assert np.isnan(got[5]) and np.all(np.isfinite(np.delete(got, 5)))
 
 
-@pytest.mark.parametrize("key,proc", [("ggtt", hme.GGTT), ("ggttg", hme.GGTTG), ("ggttgg", hme.GGTTGG)])
-def test_full_size_sampled(handles, card, key, proc):
-    """Full configuration size in the benchmark's launch, checked on 256 sampled events."""
+def dist(rel):
+    return f"max {rel.max():.3g} p99 {np.quantile(rel, 0.99):.3g} median {np.median(rel):.3g}"
+
+
+@pytest.mark.parametrize("key,proc", [("ggtt", hme.GGTT), ("ggttg", hme.GGTTG)])
+def test_full_configuration_every_event(handles, card, key, proc):
+    """The whole configuration (524,288 gg -> ttbar events at 1 TeV; 1,048,576 gg -> ttbar g
+    events at 1.5 TeV with the gluon pT cut) in the benchmark's launch, every event against the
+    oracle: the FP64 gate in every event, MIXED_PAPER within 1e-5 in every event, MIXED_FAST
+    within 1e-5 at the 99th percentile and 1e-3 at most."""
     w = configs.WORKLOADS[key]
-    print(f"[gpu] full size {key} n={w.nevt}", flush=True)
+    print(f"[gpu] full configuration {key} n={w.nevt}", flush=True)
     p = w.momenta()
+    ref = oracle.me2(proc, p, card, AS)
     got = run(handles[(proc, hme.FP64)], p)
     assert np.all(np.isfinite(got)) and np.all(got > 0)
-    idx = np.unique(np.concatenate([np.random.default_rng(9).integers(0, w.nevt, 250), [0, w.nevt - 1]]))
-    ref = oracle.me2(proc, p[idx], card, AS)
-    fp64_gate(proc, p[idx], got[idx], ref, card)
+    rel = np.abs(got / ref - 1)
+    mx, narb = fp64_gate(proc, p, got, ref, card)
+    print(f"  fp64 vs oracle: {dist(rel)}; {narb} events arbitrated")
+    paper = np.abs(run(handles[(proc, hme.MIXED_PAPER)], p) / ref - 1)
+    fast = np.abs(run(handles[(proc, hme.MIXED_FAST)], p) / ref - 1)
+    print(f"  mixed_paper: {dist(paper)}; mixed_fast: {dist(fast)}")
+    assert paper.max() <= MIXED_TOL
+    assert np.quantile(fast, 0.99) <= MIXED_TOL and fast.max() <= 1e-3
+
+
+def test_full_configuration_ggttgg_sampled(handles, card):
+    """All 1,048,576 gg -> ttbar gg events in one launch (the benchmark's), 4,096 evenly spaced
+    events plus both ends against the oracle in all three precisions."""
+    w = configs.WORKLOADS["ggttgg"]
+    print(f"[gpu] full configuration ggttgg n={w.nevt}", flush=True)
+    p = w.momenta()
+    idx = np.unique(np.concatenate([np.linspace(0, w.nevt - 1, 4096).astype(np.int64), [1, w.nevt - 2]]))
+    ref = oracle.me2(hme.GGTTGG, p[idx], card, AS)
+    got = run(handles[(hme.GGTTGG, hme.FP64)], p)
+    assert np.all(np.isfinite(got)) and np.all(got > 0)
+    rel = np.abs(got[idx] / ref - 1)
+    _, narb = fp64_gate(hme.GGTTGG, p[idx], got[idx], ref, card)
+    print(f"  fp64 vs oracle: {dist(rel)}; {narb} events arbitrated")
+    paper = np.abs(run(handles[(hme.GGTTGG, hme.MIXED_PAPER)], p)[idx] / ref - 1)
+    fast = np.abs(run(handles[(hme.GGTTGG, hme.MIXED_FAST)], p)[idx] / ref - 1)
+    print(f"  mixed_paper: {dist(paper)}; mixed_fast: {dist(fast)}")
+    assert paper.max() <= MIXED_TOL
+    assert np.quantile(fast, 0.99) <= MIXED_TOL and fast.max() <= 1e-3
 
 
 # ---------------------------------------------------------------- g g -> t tbar g g g
@@ -258,12 +290,13 @@ def test_ggttggg_constants(h7):
 
 
 def test_ggttggg_mixed_fast_accuracy(h7, card):
-    p = configs.WORKLOADS["ggttggg"].momenta(67)
-    print("[gpu] ggttggg mixed (fast) accuracy n=67", flush=True)
+    """2,048 events against the oracle (the single-precision bars)."""
+    p = configs.WORKLOADS["ggttggg"].momenta(2048)
+    print("[gpu] ggttggg mixed (fast) accuracy n=2048", flush=True)
     ref = oracle.me2(configs.GGTTGGG, p, card, AS)
     got = run(h7, p)
     rel = np.abs(got / ref - 1)
-    print(f"  max {rel.max():.3g} p99 {np.quantile(rel, 0.99):.3g} median {np.median(rel):.3g}")
+    print(f"  {dist(rel)}")
     assert np.quantile(rel, 0.99) <= MIXED_TOL
     assert rel.max() <= 1e-3
 
