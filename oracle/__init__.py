@@ -21,8 +21,11 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
 
-EEMUMU, GGTT, GGTTG, GGTTGG, GGTTGGG, GGGG = 0, 1, 2, 3, 4, 5
-NPAR = {EEMUMU: 4, GGTT: 4, GGTTG: 5, GGTTGG: 6, GGTTGGG: 7, GGGG: 4}
+EEMUMU, GGTT, GGTTG, GGTTGG, GGTTGGG = 0, 1, 2, 3, 4
+UUEE, UUEEG, UUEEGG, UUEEGGG = 5, 6, 7, 8  # u ubar -> e+ e- + n g (Drell-Yan family)
+GGGG = 9  # g g -> g g, test only
+NPAR = {EEMUMU: 4, GGTT: 4, GGTTG: 5, GGTTGG: 6, GGTTGGG: 7, UUEE: 4, UUEEG: 5, UUEEGG: 6, UUEEGGG: 7, GGGG: 4}
+DY = (UUEE, UUEEG, UUEEGG, UUEEGGG)
 ORDERED, DRESSED = 0, 1
 
 
@@ -55,6 +58,9 @@ def lib():
             L.oracle_me2_hel.argtypes = [ctypes.c_int, dp, ctypes.c_double, dp, dp]
             L.oracle_dressed_amp.argtypes = [ctypes.c_int, dp, dp, ip, ip, ctypes.c_int, ctypes.c_int,
                                              ctypes.c_int, ctypes.c_int, dp]
+            L.oracle_partial_amps_dy.argtypes = [ctypes.c_int, dp, dp, ip, ctypes.c_int, ctypes.c_int, dp]
+            L.oracle_dressed_amp_dy.argtypes = [ctypes.c_int, dp, dp, ip, ip, ctypes.c_int, ctypes.c_int,
+                                                ctypes.c_int, dp]
             L.oracle_external.argtypes = [ctypes.c_int, dp, ctypes.c_double, ctypes.c_int, dp]
             L.oracle_gamma.argtypes = [ctypes.c_int, dp]
             L.oracle_su3.argtypes = [dp, dp]
@@ -146,6 +152,36 @@ def dressed_amp(momentum, card, spins, colours, i3: int = 0, j4: int = 0, gauge_
     out = np.empty(2, dtype=np.float64)
     if lib().oracle_dressed_amp(mom.shape[0], _dp(card), _dp(mom), _ip(sp), _ip(col), i3, j4, gauge_leg,
                                 int(pure_gluon), _dp(out)) != 0:
+        raise ValueError("bad arguments")
+    return complex(out[0], out[1])
+
+
+def partial_amps_dy(momentum, card, spins, gauge_leg: int = -1, helicity_basis: bool = False) -> np.ndarray:
+    """Colour-ordered partial amplitudes (g_s = 1) of u ubar -> e+ e- + n g for one event and one spin
+    configuration (spins[k] in {0, 1}; gluons linear e1 / e2, or helicity -1 / +1 with
+    helicity_basis), the n! gluon orderings in lexicographic order."""
+    import math
+    mom = np.ascontiguousarray(momentum, dtype=np.float64)
+    npar = mom.shape[0]
+    card = np.ascontiguousarray(card, dtype=np.float64)
+    sp = np.ascontiguousarray(spins, dtype=np.int32)
+    out = np.empty(2 * math.factorial(npar - 4), dtype=np.float64)
+    if lib().oracle_partial_amps_dy(npar, _dp(card), _dp(mom), _ip(sp), gauge_leg, int(helicity_basis),
+                                    _dp(out)) != 0:
+        raise ValueError("bad arguments")
+    return out[0::2] + 1j * out[1::2]
+
+
+def dressed_amp_dy(momentum, card, spins, colours, i1: int = 0, j2: int = 0, gauge_leg: int = -1) -> complex:
+    """Colour-dressed amplitude (g_s = 1) of u ubar -> e+ e- + n g: gluon colours (0..7), u colour i1,
+    ubar colour j2 (0..2), linear gluon polarisations."""
+    mom = np.ascontiguousarray(momentum, dtype=np.float64)
+    card = np.ascontiguousarray(card, dtype=np.float64)
+    sp = np.ascontiguousarray(spins, dtype=np.int32)
+    col = np.ascontiguousarray(list(colours) if len(colours) else [0], dtype=np.int32)
+    out = np.empty(2, dtype=np.float64)
+    if lib().oracle_dressed_amp_dy(mom.shape[0], _dp(card), _dp(mom), _ip(sp), _ip(col), i1, j2, gauge_leg,
+                                   _dp(out)) != 0:
         raise ValueError("bad arguments")
     return complex(out[0], out[1])
 

@@ -2,7 +2,8 @@
 //
 // A plain, slow CPU evaluation of the helicity- and colour-summed tree-level
 // squared matrix element |M|^2 for
-//   e+ e- -> mu+ mu-  (photon + Z),  g g -> t tbar + n g  (n = 0..3),  g g -> g g.
+//   e+ e- -> mu+ mu-  (photon + Z),  g g -> t tbar + n g  (n = 0..3),
+//   u ubar -> e+ e- + n g  (photon + Z, n = 0..3: the Drell-Yan family),  g g -> g g.
 //
 // It follows the paper's section "Parallel scattering amplitudes": external
 // wavefunctions, propagators and vertices are evaluated explicitly, every
@@ -687,9 +688,354 @@ template <class R> cx<R> dressed_amp_gluons(const QcdLegs<R>& L, const int* col,
   return mdot<R>(acc[col[last]], L.eps[last]);
 }
 
+// ------------------------------------------- u ubar -> e+ e- + n g (Drell-Yan family)
+
+// Particles: 0 u (incoming), 1 ubar (incoming), 2 e+ (outgoing), 3 e- (outgoing), 4.. gluons
+// (outgoing).  The quark line runs from vbar(p_ubar) to u(p_u); the gluons and one electroweak
+// boson (photon or Z, s-channel, decaying to the lepton pair) attach to it.  Feynman rules with
+// the strong coupling set to 1 (every amplitude carries g_s^n):
+//   photon: vertex -i e Q gamma^mu (Q_u = 2/3, Q_e = -1), propagator -i g_{mu nu} / q^2;
+//   Z: vertex -i (e / (sw cw)) gamma^mu (gL P_L + gR P_R), gL = T3 - Q sw^2, gR = -Q sw^2
+//      (u: T3 = 1/2; e: T3 = -1/2), propagator -i (g_{mu nu} - q_mu q_nu / mZ^2) / (q^2 - mZ^2 + i mZ wZ);
+//   quark-gluon vertex and gluon interactions as in the colour-ordered and colour-dressed
+//   evaluations above; massless quark propagator i K-slash / K^2.
+template <class R> struct DyLegs {
+  int n;
+  R q[8][4];     // incoming momenta of the gluons (outgoing ones negated)
+  V4<R> eps[8];  // gluon polarisations (real linear ones, or conjugated circular ones)
+  R p1[4];       // u momentum (incoming)
+  R qv[4];       // momentum of the electroweak boson, p_e+ + p_e- (outgoing)
+  Spinor<R> u1, vbar2;
+  Mat<R> ew;  // the boson insertion as a matrix on the quark line: quark vertex x propagator x lepton current
+};
+
+// The electroweak insertion for given lepton spinors: sum over photon and Z of
+// Gamma_q^nu P_{nu mu} L^mu with the lepton current L^mu = ubar(e-) Gamma_e^mu v(e+).
+template <class R> Mat<R> dy_insertion(const Couplings<R>& cp, const Spinor<R>& v_ep, const Spinor<R>& ubar_em,
+                                       const R* qv) {
+  const Dirac<R>& d = dirac<R>();
+  const cx<R> I(0, 1);
+  const R metric[4] = {1, -1, -1, -1};
+  const R Qu = R(2) / R(3), Qe = -1;
+  const R gLu = R(0.5) - Qu * cp.sw2, gRu = -Qu * cp.sw2;
+  const R gLe = R(-0.5) - Qe * cp.sw2, gRe = -Qe * cp.sw2;
+  const R gz = cp.e / std::sqrt(cp.sw2 * cp.cw2);
+  Mat<R> PL, PR;
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      const cx<R> id = (i == j) ? cx<R>(1) : cx<R>(0);
+      PL[i][j] = (id - d.g5[i][j]) / R(2);
+      PR[i][j] = (id + d.g5[i][j]) / R(2);
+    }
+  // vertex matrices Gamma^mu of the photon and the Z for a fermion of the given couplings
+  auto vertex = [&](int mu, bool z, R Q, R gL, R gR) {
+    Mat<R> m;
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) {
+        if (!z) {
+          m[i][j] = -I * cp.e * Q * d.g[mu][i][j];
+        } else {
+          cx<R> t = 0;
+          for (int k = 0; k < 4; ++k) t += d.g[mu][i][k] * (gL * PL[k][j] + gR * PR[k][j]);
+          m[i][j] = -I * gz * t;
+        }
+      }
+    return m;
+  };
+  const R s = qv[0] * qv[0] - qv[1] * qv[1] - qv[2] * qv[2] - qv[3] * qv[3];
+  const cx<R> dz(s - cp.mZ * cp.mZ, cp.mZ * cp.wZ);
+  Mat<R> out;
+  for (auto& r : out)
+    for (auto& e : r) e = 0;
+  for (int z = 0; z < 2; ++z) {
+    // lepton current with an upper index
+    cx<R> L[4];
+    for (int mu = 0; mu < 4; ++mu)
+      L[mu] = row_col(ubar_em, mat_vec(vertex(mu, z, Qe, gLe, gRe), v_ep));
+    // propagator times current, lower index: P_{nu mu} L^mu
+    cx<R> PLow[4];
+    cx<R> qL = 0;
+    for (int mu = 0; mu < 4; ++mu) qL += metric[mu] * qv[mu] * L[mu];
+    for (int nu = 0; nu < 4; ++nu) {
+      if (!z) {
+        PLow[nu] = -I * metric[nu] * L[nu] / s;
+      } else {
+        PLow[nu] = -I * (metric[nu] * L[nu] - metric[nu] * qv[nu] * qL / (cp.mZ * cp.mZ)) / dz;
+      }
+    }
+    for (int nu = 0; nu < 4; ++nu) {
+      const Mat<R> G = vertex(nu, z, Qu, gLu, gRu);
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) out[i][j] += G[i][j] * PLow[nu];
+    }
+  }
+  return out;
+}
+
+// External states of one spin configuration: spins[k] in {0, 1} is the helicity -1 / +1 of the
+// quarks and leptons, and of the gluons the linear polarisation e1 / e2 (helicity_basis false)
+// or the helicity -1 / +1 (true).  gauge_leg >= 0 replaces that gluon's polarisation by its momentum.
+template <class R> DyLegs<R> dy_legs(const R* mom, int npar, const Couplings<R>& cp, const int* spins, int gauge_leg,
+                                     bool helicity_basis = false) {
+  DyLegs<R> L;
+  L.n = npar - 4;
+  for (int g = 0; g < L.n; ++g) {
+    const R* p = mom + 4 * (4 + g);
+    for (int i = 0; i < 4; ++i) L.q[g][i] = -p[i];
+    if (g == gauge_leg) L.eps[g] = real4<R>(p);
+    else if (helicity_basis) L.eps[g] = hel_pol(p, 2 * spins[4 + g] - 1, true);
+    else L.eps[g] = lin_pol(p, spins[4 + g]);
+  }
+  for (int i = 0; i < 4; ++i) {
+    L.p1[i] = mom[i];
+    L.qv[i] = mom[8 + i] + mom[12 + i];
+  }
+  L.u1 = spinor_u(mom, R(0), 2 * spins[0] - 1);
+  L.vbar2 = dirac_bar(spinor_v(mom + 4, R(0), 2 * spins[1] - 1));
+  const Spinor<R> v_ep = spinor_v(mom + 8, R(0), 2 * spins[2] - 1);
+  const Spinor<R> ubar_em = dirac_bar(spinor_u(mom + 12, R(0), 2 * spins[3] - 1));
+  L.ew = dy_insertion(cp, v_ep, ubar_em, L.qv);
+  return L;
+}
+
+// i K-slash / K^2 applied to a spinor (massless quark propagator)
+template <class R> Spinor<R> massless_prop(const R* K, const Spinor<R>& x) {
+  const cx<R> I(0, 1);
+  const Spinor<R> t = mat_vec(slash(real4<R>(K)), x);
+  const R den = K[0] * K[0] - K[1] * K[1] - K[2] * K[2] - K[3] * K[3];
+  Spinor<R> r;
+  for (int i = 0; i < 4; ++i) r[i] = I * t[i] / den;
+  return r;
+}
+
+// Colour-ordered amplitude A(perm) of u ubar -> e+ e- + n g for the gluon ordering `perm`,
+// read from the vbar(p_ubar) end: the ordered product (T^{s1} .. T^{sn})_{j i} (j the ubar
+// colour, i the u colour) multiplies it.  The boson attaches anywhere between the gluon
+// currents of consecutive ranges of the ordering.
+template <class R> cx<R> ordered_amp_dy(const DyLegs<R>& L, const int* perm) {
+  const int n = L.n;
+  const cx<R> I(0, 1);
+  std::vector<V4<R>> J(n * n > 0 ? n * n : 1);
+  std::vector<std::array<R, 4>> Q(n * n > 0 ? n * n : 1);
+  auto idx = [n](int a, int b) { return a * n + b; };
+  for (int a = 0; a < n; ++a) {
+    J[idx(a, a)] = L.eps[perm[a]];
+    for (int i = 0; i < 4; ++i) Q[idx(a, a)][i] = L.q[perm[a]][i];
+  }
+  for (int len = 2; len <= n; ++len)
+    for (int a = 0; a + len - 1 < n; ++a) {
+      const int b = a + len - 1;
+      auto& Qab = Q[idx(a, b)];
+      for (int i = 0; i < 4; ++i) Qab[i] = Q[idx(a, a)][i] + Q[idx(a + 1, b)][i];
+      V4<R> acc{};
+      for (int k = a; k < b; ++k) {
+        V4<R> v = vertex3(J[idx(a, k)], Q[idx(a, k)].data(), J[idx(k + 1, b)], Q[idx(k + 1, b)].data());
+        for (int i = 0; i < 4; ++i) acc[i] += -I * v[i];
+      }
+      for (int k = a; k < b; ++k)
+        for (int l = k + 1; l < b; ++l) {
+          V4<R> Ls[3];
+          vertex4(J[idx(a, k)], J[idx(k + 1, l)], J[idx(l + 1, b)], Ls);
+          for (int i = 0; i < 4; ++i) acc[i] += I * (Ls[0][i] - Ls[2][i]);
+        }
+      const R Q2 = Qab[0] * Qab[0] - Qab[1] * Qab[1] - Qab[2] * Qab[2] - Qab[3] * Qab[3];
+      for (int i = 0; i < 4; ++i) J[idx(a, b)][i] = -I * acc[i] / Q2;
+    }
+  // psi[k][e]: u(p_u) with the gluons perm[k..n-1] attached (and the boson if e = 1), the
+  // propagator of the last attachment included (psi[n][0] is the external spinor)
+  std::vector<std::array<Spinor<R>, 2>> psi(n + 1);
+  for (int k = n; k >= 0; --k) {
+    R K[4];
+    for (int i = 0; i < 4; ++i) {
+      K[i] = L.p1[i];
+      for (int m = k; m < n; ++m) K[i] += L.q[perm[m]][i];
+    }
+    for (int e = 0; e < 2; ++e) {
+      if (k == n && e == 0) {
+        psi[n][0] = L.u1;
+        continue;
+      }
+      Spinor<R> acc{};
+      for (int j = k; j < n; ++j) {
+        const Spinor<R> t = mat_vec(slash(J[idx(k, j)]), psi[j + 1][e]);
+        for (int i = 0; i < 4; ++i) acc[i] += I * t[i];
+      }
+      if (e == 1) {
+        const Spinor<R> t = mat_vec(L.ew, psi[k][0]);
+        for (int i = 0; i < 4; ++i) acc[i] += t[i];
+      }
+      R Ke[4];
+      for (int i = 0; i < 4; ++i) Ke[i] = K[i] - (e ? L.qv[i] : R(0));
+      psi[k][e] = massless_prop(Ke, acc);
+    }
+  }
+  // close at the vbar(p_ubar) end
+  Spinor<R> acc{};
+  for (int j = 0; j < n; ++j) {
+    const Spinor<R> t = mat_vec(slash(J[idx(0, j)]), psi[j + 1][1]);
+    for (int i = 0; i < 4; ++i) acc[i] += I * t[i];
+  }
+  const Spinor<R> t = mat_vec(L.ew, psi[0][0]);
+  for (int i = 0; i < 4; ++i) acc[i] += t[i];
+  return row_col(L.vbar2, acc);
+}
+
+// Colour-dressed amplitude of u ubar -> e+ e- + n g for gluon colours col[], u colour i1;
+// out[j] for the three ubar colours j.  Every Feynman diagram with explicit generators and
+// structure constants (the plain definition).
+template <class R> void dressed_amp_dy(const DyLegs<R>& L, const int* col, int i1, cx<R> out[3], Dressed<R>& D) {
+  const SU3<R>& S = su3<R>();
+  const cx<R> I(0, 1);
+  const int n = L.n, all = (1 << n) - 1;
+  QcdLegs<R> G;
+  G.n = n;
+  for (int g = 0; g < n; ++g) {
+    G.eps[g] = L.eps[g];
+    for (int i = 0; i < 4; ++i) G.q[g][i] = L.q[g][i];
+  }
+  if (n > 0) D.gluon_currents(G, col, all);
+  // psi[mask][e][colour], as in ordered_amp_dy but for subsets of the gluons
+  std::vector<std::array<std::array<Spinor<R>, 3>, 2>> psi(1 << n);
+  std::vector<std::array<std::array<bool, 3>, 2>> pnz(1 << n);
+  std::vector<int> masks;
+  for (int m = 0; m <= all; ++m) masks.push_back(m);
+  std::stable_sort(masks.begin(), masks.end(),
+                   [](int a, int b) { return __builtin_popcount(a) < __builtin_popcount(b); });
+  // vertex i gamma^mu T^a_{jk} J^a_mu psi_k(rest) summed over the gluon subset S1 at the vertex,
+  // then (e = 1) the boson insertion on psi(mask, e = 0)
+  auto attach = [&](int mask, int e, std::array<Spinor<R>, 3>& acc, std::array<bool, 3>& nz) {
+    for (auto& x : acc) x = Spinor<R>{};
+    nz = {false, false, false};
+    for (int s1 = mask; s1 > 0; s1 = (s1 - 1) & mask) {
+      const int s2 = mask ^ s1;
+      for (int a = 0; a < 8; ++a) {
+        if (!D.Jnz[s1][a]) continue;
+        const Mat<R> js = slash(D.J[s1][a]);
+        for (int k = 0; k < 3; ++k) {
+          if (!pnz[s2][e][k]) continue;
+          const Spinor<R> t = mat_vec(js, psi[s2][e][k]);
+          for (int j = 0; j < 3; ++j) {
+            const cx<R> tjk = S.T[a][j][k];
+            if (tjk == cx<R>(0)) continue;
+            for (int c = 0; c < 4; ++c) acc[j][c] += I * tjk * t[c];
+            nz[j] = true;
+          }
+        }
+      }
+    }
+    if (e == 1)
+      for (int j = 0; j < 3; ++j) {
+        if (!pnz[mask][0][j]) continue;
+        const Spinor<R> t = mat_vec(L.ew, psi[mask][0][j]);
+        for (int c = 0; c < 4; ++c) acc[j][c] += t[c];
+        nz[j] = true;
+      }
+  };
+  for (int m : masks) {
+    if (m == all) break;  // the full set is closed below, not propagated
+    R K[4] = {L.p1[0], L.p1[1], L.p1[2], L.p1[3]};
+    for (int g = 0; g < n; ++g)
+      if (m >> g & 1)
+        for (int i = 0; i < 4; ++i) K[i] += L.q[g][i];
+    for (int e = 0; e < 2; ++e) {
+      if (m == 0 && e == 0) {
+        for (int j = 0; j < 3; ++j) {
+          psi[0][0][j] = (j == i1) ? L.u1 : Spinor<R>{};
+          pnz[0][0][j] = (j == i1);
+        }
+        continue;
+      }
+      std::array<Spinor<R>, 3> acc;
+      std::array<bool, 3> nz;
+      attach(m, e, acc, nz);
+      R Ke[4];
+      for (int i = 0; i < 4; ++i) Ke[i] = K[i] - (e ? L.qv[i] : R(0));
+      for (int j = 0; j < 3; ++j) {
+        pnz[m][e][j] = nz[j];
+        psi[m][e][j] = nz[j] ? massless_prop(Ke, acc[j]) : Spinor<R>{};
+      }
+    }
+  }
+  if (all == 0) {
+    // no gluons: the boson insertion alone between the two spinors
+    for (int j = 0; j < 3; ++j) out[j] = (j == i1) ? row_col(L.vbar2, mat_vec(L.ew, L.u1)) : cx<R>(0);
+    return;
+  }
+  // psi(all, e = 0) is needed by the closing insertion: propagate it too
+  {
+    R K[4] = {L.p1[0], L.p1[1], L.p1[2], L.p1[3]};
+    for (int g = 0; g < n; ++g)
+      for (int i = 0; i < 4; ++i) K[i] += L.q[g][i];
+    std::array<Spinor<R>, 3> acc;
+    std::array<bool, 3> nz;
+    attach(all, 0, acc, nz);
+    for (int j = 0; j < 3; ++j) {
+      pnz[all][0][j] = nz[j];
+      psi[all][0][j] = nz[j] ? massless_prop(K, acc[j]) : Spinor<R>{};
+    }
+  }
+  std::array<Spinor<R>, 3> acc;
+  std::array<bool, 3> nz;
+  attach(all, 1, acc, nz);
+  for (int j = 0; j < 3; ++j) out[j] = nz[j] ? row_col(L.vbar2, acc[j]) : cx<R>(0);
+}
+
+// sum over spins of sum over colours of |A|^2 for u ubar -> e+ e- + n g (g_s = 1):
+// colour-ordered amplitudes with the colour matrix (dressed = false) or every colour
+// assignment of the dressed amplitude (dressed = true)
+template <class R> R spin_colour_sum_dy(const R* mom, int npar, const Couplings<R>& cp, bool dressed) {
+  const int n = npar - 4;
+  int spins[8];
+  R total = 0;
+  if (!dressed) {
+    std::vector<std::vector<int>> perms;
+    std::vector<int> p(n);
+    std::iota(p.begin(), p.end(), 0);
+    do perms.push_back(p); while (std::next_permutation(p.begin(), p.end()));
+    const int np = (int)perms.size();
+    // colour matrix of the quark line with n gluons (the same traces as for a top pair);
+    // with no gluon the colour sum is delta_ij delta_ij = 3
+    std::vector<R> C(1, R(3));
+    if (n > 0) C = colour_matrix_cached<R>(n);
+    std::vector<cx<R>> A(np);
+    for (int cfg = 0; cfg < (1 << npar); ++cfg) {
+      for (int k = 0; k < npar; ++k) spins[k] = (cfg >> k) & 1;
+      const DyLegs<R> L = dy_legs(mom, npar, cp, spins, -1);
+      for (int s = 0; s < np; ++s) A[s] = ordered_amp_dy(L, perms[s].data());
+      for (int s = 0; s < np; ++s) {
+        cx<R> row = 0;
+        for (int t = 0; t < np; ++t) row += C[(size_t)s * np + t] * std::conj(A[t]);
+        total += (A[s] * row).real();
+      }
+    }
+    return total;
+  }
+  long ncol = 1;
+  for (int i = 0; i < n; ++i) ncol *= 8;
+  Dressed<R> D;
+  int col[8];
+  for (int cfg = 0; cfg < (1 << npar); ++cfg) {
+    for (int k = 0; k < npar; ++k) spins[k] = (cfg >> k) & 1;
+    const DyLegs<R> L = dy_legs(mom, npar, cp, spins, -1);
+    for (long c = 0; c < ncol; ++c) {
+      long r = c;
+      for (int k = 0; k < n; ++k) { col[k] = r % 8; r /= 8; }
+      for (int i1 = 0; i1 < 3; ++i1) {
+        cx<R> a[3];
+        dressed_amp_dy(L, col, i1, a, D);
+        for (int j = 0; j < 3; ++j) total += std::norm(a[j]);
+      }
+    }
+  }
+  return total;
+}
+
 // ------------------------------------------- process set-up and spin sums
 
-enum { P_EEMUMU = 0, P_GGTT = 1, P_GGTTG = 2, P_GGTTGG = 3, P_GGTTGGG = 4, P_GGGG = 5 };
+enum { P_EEMUMU = 0, P_GGTT = 1, P_GGTTG = 2, P_GGTTGG = 3, P_GGTTGGG = 4,
+       P_UUEE = 5, P_UUEEG = 6, P_UUEEGG = 7, P_UUEEGGG = 8, P_GGGG = 9 };
+
+bool is_dy(int proc) { return proc >= P_UUEE && proc <= P_UUEEGGG; }
 
 int npar_of(int proc) {
   switch (proc) {
@@ -698,6 +1044,10 @@ int npar_of(int proc) {
     case P_GGTTG: return 5;
     case P_GGTTGG: return 6;
     case P_GGTTGGG: return 7;
+    case P_UUEE: return 4;
+    case P_UUEEG: return 5;
+    case P_UUEEGG: return 6;
+    case P_UUEEGGG: return 7;
     case P_GGGG: return 4;
   }
   return -1;
@@ -711,6 +1061,11 @@ double iden_of(int proc) {
     case P_GGTTG: return 256;
     case P_GGTTGG: return 512;
     case P_GGTTGGG: return 1536;
+    // quark-antiquark initial state: 4 spins x 9 colours x (identical final-state gluons)!
+    case P_UUEE: return 36;
+    case P_UUEEG: return 36;
+    case P_UUEEGG: return 72;
+    case P_UUEEGGG: return 216;
     case P_GGGG: return 512;
   }
   return 0;
@@ -849,6 +1204,19 @@ template <class R> int me2_batch(int proc, const double* card, double alpha_s, i
     }
     return 0;
   }
+  if (is_dy(proc)) {
+    // n gluons: g_s^(2n); colour-ordered (mode 0) or every colour assignment (mode 1)
+    R cdy = 1;
+    for (int i = 0; i < npar - 4; ++i) cdy *= gs2;
+    if (mode == 0 && npar > 4) colour_matrix_cached<R>(npar - 4);
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1)
+    for (int64_t e = 0; e < nevt; ++e) {
+      R m[32];
+      for (int i = 0; i < 4 * npar; ++i) m[i] = mom[e * 4 * npar + i];
+      out[e] = (double)(cdy * spin_colour_sum_dy(m, npar, cp, mode == 1) / iden);
+    }
+    return 0;
+  }
   if (mode == 0) {
     colour_matrix_cached<R>(ngl);
 #pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1)
@@ -894,6 +1262,34 @@ int oracle_me2_hel(int proc, const double* card, double alpha_s, const double* m
   Couplings<double> cp = make_couplings<double>(card);
   if (proc == P_EEMUMU) {
     me2_eemumu(mom, cp, out);
+    return 0;
+  }
+  if (is_dy(proc)) {
+    const double pi = std::acos(-1.0);
+    const int n = npar - 4;
+    double coup = 1;
+    for (int i = 0; i < n; ++i) coup *= 4 * pi * alpha_s;
+    std::vector<double> C(1, 3.0);
+    if (n > 0) C = colour_matrix_cached<double>(n);
+    std::vector<std::vector<int>> perms;
+    std::vector<int> p(n);
+    std::iota(p.begin(), p.end(), 0);
+    do perms.push_back(p); while (std::next_permutation(p.begin(), p.end()));
+    const int np = (int)perms.size();
+    std::vector<cx<double>> A(np);
+    int spins[8];
+    for (int h = 0; h < (1 << npar); ++h) {
+      for (int k = 0; k < npar; ++k) spins[k] = (h >> (npar - 1 - k)) & 1;
+      const DyLegs<double> L = dy_legs(mom, npar, cp, spins, -1, true);
+      for (int s = 0; s < np; ++s) A[s] = ordered_amp_dy(L, perms[s].data());
+      double m2 = 0;
+      for (int s = 0; s < np; ++s) {
+        cx<double> row = 0;
+        for (int t = 0; t < np; ++t) row += C[(size_t)s * np + t] * std::conj(A[t]);
+        m2 += (A[s] * row).real();
+      }
+      out[h] = coup * m2 / iden_of(proc);
+    }
     return 0;
   }
   const double pi = std::acos(-1.0);
@@ -993,6 +1389,46 @@ int oracle_dressed_amp(int npar, const double* card, const double* mom, const in
   }
   out[0] = a.real();
   out[1] = a.imag();
+  return 0;
+}
+
+// Colour-ordered partial amplitudes (g_s = 1) of u ubar -> e+ e- + n g (npar = 4 + n) for one
+// event and one spin configuration (spins[k] in {0, 1}; gluons linear e1 / e2, or helicity -1 / +1
+// with helicity_basis = 1), orderings in lexicographic order; out = [n!][2].  gauge_leg >= 0
+// replaces that gluon's polarisation by its momentum.
+int oracle_partial_amps_dy(int npar, const double* card, const double* mom, const int* spins, int gauge_leg,
+                           int helicity_basis, double* out) {
+  if (npar < 4 || npar > 7 || !card || !mom || !spins || !out) return -1;
+  Couplings<double> cp = make_couplings<double>(card);
+  const DyLegs<double> L = dy_legs(mom, npar, cp, spins, gauge_leg, helicity_basis != 0);
+  const int n = npar - 4;
+  std::vector<int> p(n);
+  std::iota(p.begin(), p.end(), 0);
+  int s = 0;
+  do {
+    const cx<double> a = ordered_amp_dy(L, p.data());
+    out[2 * s] = a.real();
+    out[2 * s + 1] = a.imag();
+    ++s;
+  } while (std::next_permutation(p.begin(), p.end()));
+  return 0;
+}
+
+// Colour-dressed amplitude (g_s = 1) of u ubar -> e+ e- + n g for gluon colours col[] (0..7),
+// u colour i1 and ubar colour j2 (0..2), linear gluon polarisations; gauge_leg as above.
+int oracle_dressed_amp_dy(int npar, const double* card, const double* mom, const int* spins, const int* col, int i1,
+                          int j2, int gauge_leg, double* out) {
+  if (npar < 4 || npar > 7 || !card || !mom || !spins || (!col && npar > 4) || !out || i1 < 0 || i1 > 2 || j2 < 0 ||
+      j2 > 2)
+    return -1;
+  Couplings<double> cp = make_couplings<double>(card);
+  const DyLegs<double> L = dy_legs(mom, npar, cp, spins, gauge_leg);
+  Dressed<double> D;
+  cx<double> a[3];
+  const int none[1] = {0};
+  dressed_amp_dy(L, col ? col : none, i1, a, D);
+  out[0] = a[j2].real();
+  out[1] = a[j2].imag();
   return 0;
 }
 

@@ -17,14 +17,20 @@ import numpy as np
 from . import rambo
 
 EEMUMU, GGTT, GGTTG, GGTTGG, GGTTGGG = 0, 1, 2, 3, 4
+UUEE, UUEEG, UUEEGG, UUEEGGG = 5, 6, 7, 8  # u ubar -> e+ e- + n g (Drell-Yan family)
 PROCESS_NAMES = {
     EEMUMU: "e+e- -> mu+mu-",
     GGTT: "gg -> ttbar",
     GGTTG: "gg -> ttbar g",
     GGTTGG: "gg -> ttbar gg",
     GGTTGGG: "gg -> ttbar ggg",
+    UUEE: "uu~ -> e+e-",
+    UUEEG: "uu~ -> e+e- g",
+    UUEEGG: "uu~ -> e+e- gg",
+    UUEEGGG: "uu~ -> e+e- ggg",
 }
-NPAR = {EEMUMU: 4, GGTT: 4, GGTTG: 5, GGTTGG: 6, GGTTGGG: 7}
+NPAR = {EEMUMU: 4, GGTT: 4, GGTTG: 5, GGTTGG: 6, GGTTGGG: 7, UUEE: 4, UUEEG: 5, UUEEGG: 6, UUEEGGG: 7}
+DY = (UUEE, UUEEG, UUEEGG, UUEEGGG)
 
 # Standard Model inputs shared by every evaluation (input data, not derived
 # quantities): mZ, width Z, 1/alpha, G_F, m_top, width top (GeV units).
@@ -40,8 +46,8 @@ def card_array(card=None) -> np.ndarray:
 
 
 def final_masses(process: int, mT: float = SM_CARD["mT"]):
-    if process == EEMUMU:
-        return [0.0, 0.0]
+    if process == EEMUMU or process in DY:
+        return [0.0] * (NPAR[process] - 2)  # massless leptons and gluons
     ng = NPAR[process] - 4
     return [mT, mT] + [0.0] * ng
 
@@ -86,6 +92,13 @@ WORKLOADS = {
     "ggttgg": Workload("ggttgg", GGTTGG, 1048576, 2000.0, 4, _cut_gluon_dr, "dR(g,g) > 0.4"),
     # the served mix's largest process on its own, at the largest request size (no cuts)
     "ggttggg": Workload("ggttggg", GGTTGGG, 65536, 2000.0, 5),
+    # the Drell-Yan family u ubar -> e+ e- + n g (the paper's second standalone workload): flat
+    # RAMBO points at sqrt(s) = 1 TeV, seed 6, pT > 20 GeV on the first gluon (n = 1) and
+    # Delta R > 0.4 between the first two gluons (n >= 2), as for the top-pair processes
+    "uuee": Workload("uuee", UUEE, 1048576, 1000.0, 6),
+    "uueeg": Workload("uueeg", UUEEG, 1048576, 1000.0, 6, _cut_gluon_pt, "pT(g) > 20 GeV"),
+    "uueegg": Workload("uueegg", UUEEGG, 1048576, 1000.0, 6, _cut_gluon_dr, "dR(g,g) > 0.4"),
+    "uueeggg": Workload("uueeggg", UUEEGGG, 1048576, 1000.0, 6, _cut_gluon_dr, "dR(g,g) > 0.4"),
     # served mix: request sizes log-uniform in [256, 65536], processes uniform over
     # the four gg -> ttbar + n g, Poisson arrivals with mean 200 requests/s
     "served": Workload("served", GGTTGGG, 0, 2000.0, 5,
