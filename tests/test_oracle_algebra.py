@@ -118,4 +118,5 @@ def test_electroweak_inputs():
 
 
 def test_iden():
-    assert [oracle.iden(p) for p in range(6)] == [4, 256, 256, 512, 1536, 512]
+    # initial spins x initial colours x (identical final-state gluons)!
+    assert [oracle.iden(p) for p in range(10)] == [4, 256, 256, 512, 1536, 36, 36, 72, 216, 512]
