@@ -131,8 +131,11 @@ def ggttggg_leg(card, steps=3, warmup=1):
         info = h.query()
         gpu_s, wall_s = time_steps(h, mom, out, steps, warmup)
     got = out.cpu().numpy()
-    idx = np.linspace(0, w.nevt - 1, 16).astype(int)
-    ref = oracle.me2(configs.GGTTGGG, p[idx], card)
+    idx = np.linspace(0, w.nevt - 1, 64).astype(int)
+    threads = oracle.default_threads()
+    t0 = time.perf_counter()
+    ref = oracle.me2(configs.GGTTGGG, p[idx], card, nthreads=threads)
+    dt = time.perf_counter() - t0
     per = gpu_s / steps
     tflops = info["flops_per_event"] * w.nevt / per / 1e12
     return {"value": w.nevt * steps / gpu_s, "unit": "events/s", "ms_per_step": per * 1e3, "steps": steps,
@@ -141,8 +144,10 @@ def ggttggg_leg(card, steps=3, warmup=1):
                      "f64 externals and sums",
             "diagrams": 1240, "helicities": 128, "good_helicities": info["ngoodhel"], "colour_flows": 120,
             "achieved_tflops": tflops, "frac_of_valu_peak": tflops * 1e12 / PEAK_FP32_VALU,
-            "max_rel_diff_vs_oracle_16_events": float(np.max(np.abs(got[idx] / ref - 1))),
-            "workspace_bytes_per_event": info["workspace_bytes_per_event"]}
+            "max_rel_diff_vs_oracle_64_events": float(np.max(np.abs(got[idx] / ref - 1))),
+            "workspace_bytes_per_event": info["workspace_bytes_per_event"],
+            "cpu_baseline": {"value": len(idx) / dt, "unit": "events/s", "cores": threads, "kind": "oracle",
+                             "sample": f"{len(idx)} evenly spaced events of the same batch, FP64 oracle, {dt:.1f} s"}}
 
 
 def e2e_leg(card, steps=5, warmup=2):
@@ -229,6 +234,74 @@ def select_leg(card, steps=3, warmup=1):
     return res
 
 
+# The other configurations, each timed like the main workload on momenta made on the device
+# (hme_rambo: the workload's energy, seed and cuts), in every precision the library builds,
+# with the mixed-precision error distributions against the FP64 output and the oracle timed
+# on the host cores: all events of e+e- -> mu+mu-, gg -> ttbar and gg -> ttbar g, a bounded
+# leading sample of the Drell-Yan processes.
+CONFIG_LEGS = (  # key, label, cpu-baseline sample (None: every event)
+    ("eemumu", "C1 e+e- -> mu+mu- (photon + Z), 16384 events at 500 GeV, seed 1", None),
+    ("ggtt", "C2 gg -> ttbar, 524288 events at 1 TeV, seed 2", None),
+    ("ggttg", "C3 gg -> ttbar g, 1048576 events at 1.5 TeV, pT(g) > 20 GeV, seed 3", None),
+    ("uuee", "Drell-Yan u u~ -> e+ e-, 1048576 events at 1 TeV, seed 6", 262144),
+    ("uueeg", "Drell-Yan u u~ -> e+ e- g, 1048576 events at 1 TeV, pT(g) > 20 GeV, seed 6", 131072),
+    ("uueegg", "Drell-Yan u u~ -> e+ e- g g, 1048576 events at 1 TeV, dR(g,g) > 0.4, seed 6", 32768),
+    ("uueeggg", "Drell-Yan u u~ -> e+ e- g g g, 1048576 events at 1 TeV, dR(g,g) > 0.4, seed 6", 8192),
+)
+
+
+def configs_leg(card, steps=10, warmup=3, cpu=True):
+    import torch
+
+    import oracle
+    import paper_2507_21039_amd as hme
+    from workloads import configs
+    res = {}
+    for key, label, sample in CONFIG_LEGS:
+        w = configs.WORKLOADS[key]
+        kind, value = configs.CUT_CODES[w.cut_text]
+        mom = hme.rambo(w.process, card, w.sqrt_s, w.seed, w.nevt, 0, kind, value)
+        out = torch.empty(w.nevt, dtype=torch.float64, device="cuda")
+        precs = (hme.FP64,) if w.process == hme.EEMUMU else (hme.FP64, hme.MIXED_FAST, hme.MIXED_PAPER)
+        entry, outs = {"workload": label, "nevt": w.nevt}, {}
+        for prec in precs:
+            name = hme.PRECISION_NAMES[prec]
+            with hme.Handle(w.process, card, prec) as h:
+                info = h.query()
+                gpu_s, _ = time_steps(h, mom, out, steps, warmup)
+            per = gpu_s / steps
+            peak = PEAK_FP32_VALU if prec == hme.MIXED_FAST else PEAK_FP64_VALU
+            tflops = info["flops_per_event"] * w.nevt / per / 1e12
+            outs[name] = out.cpu().numpy().copy()
+            entry[name] = {"value": w.nevt / per, "unit": "events/s", "ms_per_step": per * 1e3,
+                           "achieved_tflops": tflops, "frac_of_valu_peak": tflops * 1e12 / peak}
+            entry.update(diagrams=info["ndiag"], helicities=info["nhel"], good_helicities=info["ngoodhel"],
+                         colour_flows=info["ncol"], flops_per_event=info["flops_per_event"])
+            log(f"[bench] {key} {name}: {w.nevt / per:.4g} events/s, {per * 1e3:.3f} ms/step")
+        for name in outs:
+            if name != "fp64":
+                rel = np.abs(outs[name] / outs["fp64"] - 1)
+                entry[name].update(max_rel_diff_vs_fp64=float(rel.max()),
+                                   p99_rel_diff_vs_fp64=float(np.quantile(rel, 0.99)),
+                                   median_rel_diff_vs_fp64=float(np.median(rel)))
+        if cpu:
+            n = w.nevt if sample is None else sample
+            p = mom[:n].cpu().numpy()
+            threads = oracle.default_threads()
+            t0 = time.perf_counter()
+            ref = oracle.me2(w.process, p, card, nthreads=threads)
+            dt = time.perf_counter() - t0
+            entry["cpu_baseline"] = {
+                "value": n / dt, "unit": "events/s", "cores": threads, "kind": "oracle",
+                "sample": f"{'all' if sample is None else 'first'} {n} events of the same batch, FP64 oracle, "
+                          f"{dt:.1f} s",
+                "max_rel_diff_vs_gpu_fp64": float(np.max(np.abs(outs["fp64"][:n] / ref - 1)))}
+            log(f"[bench] {key} oracle: {n / dt:.4g} events/s on {threads} threads")
+        res[key] = entry
+        del mom, out
+    return res
+
+
 def served_leg(card, precision, nwarm=200, ntimed=3000, budget=32 << 30, nstreams=4):
     """Poisson request stream (200 requests/s, sizes log-uniform in 256..65536) through the server.
 
@@ -299,6 +372,7 @@ def main():
     ap.add_argument("--no-ggttggg", action="store_true")
     ap.add_argument("--no-e2e", action="store_true")
     ap.add_argument("--no-select", action="store_true")
+    ap.add_argument("--no-configs", action="store_true", help="skip the C1-C3 and Drell-Yan legs")
     ap.add_argument("--pmc", action="store_true",
                     help="counter-collection mode: one FP64 and one MIXED_FAST gg->ttbar gg launch, one "
                          "8192-event gg->ttbar ggg call, then a plain 256 MiB device copy (known traffic, "
@@ -399,11 +473,15 @@ def main():
                 ("mixed_fast", "f32 vertices/propagators/jamps, bf16x3-split MFMA colour sum with f32 accumulation, "
                            "f64 externals and sums", PEAK_FP32_VALU),
                 ("mixed_paper", "f64 amplitudes and jamps, f32 colour algebra, f64 sums", PEAK_FP64_VALU))},
+        "configs": None,
         "ggttggg": None,
         "e2e": None,
         "select": None,
         "served": None,
     }
+    if not args.no_configs:
+        log("[bench] other configurations (C1-C3, Drell-Yan)")
+        line["configs"] = configs_leg(card, cpu=not args.no_cpu_baseline)
     if not args.no_ggttggg:
         log("[bench] gg->ttbar ggg (mixed fast)")
         line["ggttggg"] = ggttggg_leg(card)

@@ -48,7 +48,15 @@ typedef struct {
 /* HME_GGTTGGG (1240 diagrams, 120 colour flows) is evaluated in pieces over a jamp
  * workspace (see hme_compute) and only at HME_MIXED_FAST; other precisions return
  * HME_E_UNSUPPORTED from hme_create. */
-enum hme_process { HME_EEMUMU = 0, HME_GGTT = 1, HME_GGTTG = 2, HME_GGTTGG = 3, HME_GGTTGGG = 4 };
+/* HME_UUEE .. HME_UUEEGGG: the Drell-Yan family u ubar -> e+ e- + n g (n = 0..3), the paper's
+ * second standalone workload (section "SIMT GPU results"): massless quarks and leptons, the
+ * lepton pair through a photon and a Z in the s channel, particles 0 u, 1 ubar (incoming),
+ * 2 e+, 3 e-, 4.. gluons (outgoing).  |M|^2 is averaged over the 4 initial spin and 9 colour
+ * states and divided by n! for the identical gluons. */
+enum hme_process {
+  HME_EEMUMU = 0, HME_GGTT = 1, HME_GGTTG = 2, HME_GGTTGG = 3, HME_GGTTGGG = 4,
+  HME_UUEE = 5, HME_UUEEG = 6, HME_UUEEGG = 7, HME_UUEEGGG = 8
+};
 
 /* HME_FP64: every step in double precision.
  * HME_MIXED_FAST: vertices, propagators, jamps and the colour sum in single

@@ -13,12 +13,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhme.so")
 
 EEMUMU, GGTT, GGTTG, GGTTGG, GGTTGGG = 0, 1, 2, 3, 4
+UUEE, UUEEG, UUEEGG, UUEEGGG = 5, 6, 7, 8  # u ubar -> e+ e- + n g (Drell-Yan family)
 FP64, MIXED_FAST, MIXED_PAPER = 0, 1, 2
 MIXED = MIXED_FAST
 PRECISION_NAMES = {FP64: "fp64", MIXED_FAST: "mixed_fast", MIXED_PAPER: "mixed_paper"}
-NPAR = {EEMUMU: 4, GGTT: 4, GGTTG: 5, GGTTGG: 6, GGTTGGG: 7}
+NPAR = {EEMUMU: 4, GGTT: 4, GGTTG: 5, GGTTGG: 6, GGTTGGG: 7, UUEE: 4, UUEEG: 5, UUEEGG: 6, UUEEGGG: 7}
 PROCESS_NAMES = {EEMUMU: "e+e- -> mu+mu-", GGTT: "gg -> ttbar", GGTTG: "gg -> ttbar g", GGTTGG: "gg -> ttbar gg",
-                 GGTTGGG: "gg -> ttbar ggg"}
+                 GGTTGGG: "gg -> ttbar ggg", UUEE: "uu~ -> e+e-", UUEEG: "uu~ -> e+e- g", UUEEGG: "uu~ -> e+e- gg",
+                 UUEEGGG: "uu~ -> e+e- ggg"}
 
 CUT_NONE, CUT_GLUON_PT, CUT_GLUON_DR, CUT_NO_RETRY = 0, 1, 2, 0x100
 GEV2_TO_PB = 0.3893793721e9  # (hbar c)^2 in GeV^2 pb

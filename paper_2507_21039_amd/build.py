@@ -20,7 +20,7 @@ ARCH = "gfx950"
 HIPFLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wall", "-Wno-unused-variable",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 _KERNEL_DEPS = ["me2_kernels.h", "colour_mfma.h", "helas.h", "process.h"]
-_PROCS = ("eemumu", "ggtt", "ggttg", "ggttgg", "ggttggg")
+_PROCS = ("eemumu", "ggtt", "ggttg", "ggttgg", "ggttggg", "uuee", "uueeg", "uueegg", "uueeggg")
 # g g -> t tbar g g g runs as pieces, one generated translation unit each
 PIECES = {"ggttggg": 12}
 SOURCES = ["hme.cpp", "server.hip", "rambo.hip"] + [f"proc_{p}.hip" for p in _PROCS] + [

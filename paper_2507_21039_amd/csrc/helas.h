@@ -392,8 +392,20 @@ template <class S> HME_FN void vector_kit(const double* k, int nsv, S* kit) {
 
 // Fermion states for lam = +1 then lam = -1, each 4 complex components as (re, im) pairs:
 // kind 1, ubar(p, lam) of an outgoing fermion (oxxxxx with nsf = +1); kind 2, v(p, lam) of an
-// outgoing antifermion (ixxxxx with nsf = -1).
+// outgoing antifermion (ixxxxx with nsf = -1); kind 3, vbar(p, lam) of an incoming antifermion
+// (oxxxxx with nsf = -1); kind 4, u(p, lam) of an incoming fermion (ixxxxx with nsf = +1).
 template <class S> HME_FN void fermion_kit(const double* p, double m, int kind, S* kit) {
+  if (kind >= 3) {
+    for (int h = 0; h < 2; ++h) {
+      const int lam = h == 0 ? 1 : -1;
+      const sp4<double> w = kind == 3 ? oxxxxx(p, m, lam, -1) : ixxxxx(p, m, lam, +1);
+      for (int c = 0; c < 4; ++c) {
+        kit[8 * h + 2 * c] = S(w.c[c].r);
+        kit[8 * h + 2 * c + 1] = S(w.c[c].i);
+      }
+    }
+    return;
+  }
   double wp, wm;
   spinor_weights(p, m, wp, wm);
   for (int h = 0; h < 2; ++h) {
@@ -511,44 +523,109 @@ template <class T> HME_FN sp4<T> ffv_psibar_k(const sp4<T>& fb, const vw4<T>& V,
 // amplified by Q0^2 / |Q^2 - m^2|.  The per-event table therefore forms momentum sums, their
 // differences and Q^2 - m^2 as unevaluated sums hi + lo of two doubles (error-free
 // transformations: Knuth's two-sum, and the exact product a b = p + fma(a, b, -p)), and rounds
-// once at the end.  This runs once per event, not per helicity.
+// once at the end.  This runs once per event, not per helicity.  Contraction is switched off in
+// these functions: the device compiler would otherwise fuse a product into a later sum (for
+// example round(a^2) + b into fma(a, a, b)), which breaks the error-free transformations.
 struct dd {
   double hi, lo;
 };
 HME_FN dd two_sum(double a, double b) {
+  _Pragma("clang fp contract(off)")
   const double s = a + b;
   const double bb = s - a;
   return {s, (a - (s - bb)) + (b - bb)};
 }
 HME_FN dd quick_two_sum(double a, double b) {  // |a| >= |b|
+  _Pragma("clang fp contract(off)")
   const double s = a + b;
   return {s, b - (s - a)};
 }
 HME_FN dd dd_add(dd a, dd b) {
+  _Pragma("clang fp contract(off)")
   const dd s = two_sum(a.hi, b.hi);
   return quick_two_sum(s.hi, s.lo + (a.lo + b.lo));
 }
 HME_FN dd dd_scale(double k, dd a) {  // k a for a small integer k (exact)
+  _Pragma("clang fp contract(off)")
   return {k * a.hi, k * a.lo};
 }
-HME_FN dd dd_neg(dd a) { return {-a.hi, -a.lo}; }
+HME_FN dd dd_neg(dd a) {
+  _Pragma("clang fp contract(off)")
+  return {-a.hi, -a.lo};
+}
 HME_FN dd two_prod(double a, double b) {
+  _Pragma("clang fp contract(off)")
   const double p = a * b;
   return {p, __builtin_fma(a, b, -p)};
 }
 HME_FN dd dd_sq(dd a) {
+  _Pragma("clang fp contract(off)")
   const dd p = two_prod(a.hi, a.hi);
   return quick_two_sum(p.hi, __builtin_fma(2.0 * a.hi, a.lo, p.lo));
 }
-HME_FN double dd_val(dd a) { return a.hi + a.lo; }
+HME_FN double dd_val(dd a) {
+  _Pragma("clang fp contract(off)")
+  return a.hi + a.lo;
+}
 // Minkowski square minus m^2 of a compensated four-vector, rounded once
 HME_FN double dd_minkowski_sq(const dd* Q, double m) {
+  _Pragma("clang fp contract(off)")
   dd s = dd_sq(Q[0]);
   s = dd_add(s, dd_neg(dd_sq(Q[1])));
   s = dd_add(s, dd_neg(dd_sq(Q[2])));
   s = dd_add(s, dd_neg(dd_sq(Q[3])));
   if (m != 0.0) s = dd_add(s, dd_neg(two_prod(m, m)));
   return dd_val(s);
+}
+
+// ------------------------------------------------------------------ electroweak current (Drell-Yan)
+// The lepton pair of q qbar -> e+ e- (+ gluons) as one vector wavefunction attached to the quark
+// line with a plain gamma^mu: W^mu = A_gamma L^mu + A_Z (L^mu - q^mu (q.L) / mZ^2), with the lepton
+// current L^mu = ubar(e-) gamma^mu v(e+), q = p(e+) + p(e-), s = q^2,
+//   A_gamma = e^2 Qq Qe / s,  A_Z = e^2 / (sw^2 cw^2) gq ge / (s - mZ^2 + i mZ wZ).
+// For massless fermions the chirality of each line is its helicity (u(p, +) and ubar(p, +) are
+// right-handed), so the Z couplings gL P_L + gR P_R reduce to the number gq = gR or gL of the
+// quark's helicity and ge = gR or gL of the electron's.  The vertex factors -i, the photon and Z
+// propagators' -i, common to every diagram, are left out.  q^2 and q^2 - mZ^2 are formed in
+// compensated arithmetic.  Item c of the kit (8 doubles: the 4 complex components) holds the
+// current for helicities (quark, e+, e-) = bits (4, 2, 1) of c set for +1.
+struct EwCouplings {
+  double cA, cZ;    // e^2 Qq Qe and e^2 / (sw^2 cw^2)
+  double gLq, gRq;  // quark Z couplings T3 - Qq sw^2, -Qq sw^2
+  double gLe, gRe;  // electron Z couplings -1/2 + sw^2, sw^2
+  double mZ, wZ;
+};
+
+template <class S>
+HME_FN void ew_kit(const double* pep, const double* pem, const EwCouplings& c, int item, S* kit) {
+  const int hq = (item >> 2 & 1) ? 1 : -1, hep = (item >> 1 & 1) ? 1 : -1, hem = (item & 1) ? 1 : -1;
+  const vw4<double> L = ffv_vec<double>(oxxxxx(pem, 0.0, hem, +1), ixxxxx(pep, 0.0, hep, -1), 1.0);
+  dd Q[4];
+  double q[4];
+  for (int mu = 0; mu < 4; ++mu) {
+    Q[mu] = two_sum(pep[mu], pem[mu]);
+    q[mu] = dd_val(Q[mu]);
+  }
+  const double s = dd_minkowski_sq(Q, 0.0);
+  const double dr = dd_minkowski_sq(Q, c.mZ), di = c.mZ * c.wZ, dn = 1.0 / (dr * dr + di * di);
+  const double gz = c.cZ * (hq > 0 ? c.gRq : c.gLq) * (hem > 0 ? c.gRe : c.gLe);
+  const cx<double> az = {gz * dr * dn, -gz * di * dn};  // gz / (s - mZ^2 + i mZ wZ)
+  const double aa = c.cA / s;
+  const cx<double> ql = (1.0 / (c.mZ * c.mZ)) * mdot(q, L);
+  for (int mu = 0; mu < 4; ++mu) {
+    const cx<double> w = aa * L.c[mu] + az * (L.c[mu] - q[mu] * ql);
+    kit[2 * mu] = S(w.r);
+    kit[2 * mu + 1] = S(w.i);
+  }
+}
+
+template <class T, class S> HME_FN vw4<T> ew_from_kit(const volatile HME_LDS S* kit, int hq, int hep, int hem) {
+  const int item = (hq > 0 ? 4 : 0) + (hep > 0 ? 2 : 0) + (hem > 0 ? 1 : 0);
+  const kitv<T, 8> k = load_kit<T, 8>(kit + 8 * item);
+  vw4<T> w;
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) w.c[mu] = {k.v[2 * mu], k.v[2 * mu + 1]};
+  return w;
 }
 
 // Scheduling fence for the generated code: table reads issued before it are not moved

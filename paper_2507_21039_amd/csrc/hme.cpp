@@ -24,13 +24,17 @@ HME_DECLARE(ggtt)
 HME_DECLARE(ggttg)
 HME_DECLARE(ggttgg)
 HME_DECLARE(ggttggg)
+HME_DECLARE(uuee)
+HME_DECLARE(uueeg)
+HME_DECLARE(uueegg)
+HME_DECLARE(uueeggg)
 #undef HME_DECLARE
 
 struct ProcEntry {
   ProcInfo (*info)();
   hipError_t (*me2)(const LaunchArgs&, int);
   hipError_t (*hel)(const double*, int, const ProcParams&, double*, hipStream_t);
-  bool qcd;            // g g -> t tbar + n g (otherwise e+ e- -> mu+ mu-)
+  bool qcd;            // g g -> t tbar + n g: massive final quarks (otherwise every particle is massless)
   double sample_sqrt_s;  // energy of the internal helicity-filter sample
 };
 
@@ -40,6 +44,10 @@ static const ProcEntry kProcs[] = {
     {info_ggttg, launch_me2_ggttg, launch_hel_ggttg, true, 1500.0},
     {info_ggttgg, launch_me2_ggttgg, launch_hel_ggttgg, true, 2000.0},
     {info_ggttggg, launch_me2_ggttggg, launch_hel_ggttggg, true, 2000.0},
+    {info_uuee, launch_me2_uuee, launch_hel_uuee, false, 1000.0},
+    {info_uueeg, launch_me2_uueeg, launch_hel_uueeg, false, 1000.0},
+    {info_uueegg, launch_me2_uueegg, launch_hel_uueegg, false, 1000.0},
+    {info_uueeggg, launch_me2_uueeggg, launch_hel_uueeggg, false, 1000.0},
 };
 
 // events per sub-batch of a process evaluated in pieces (workspace nslot * ngood * sizeof(cx) bytes each)

@@ -328,9 +328,10 @@ template <class Proc> ProcInfo make_info() {
                   Proc::nslot};
 }
 
-// lanes per event: the smallest of 4, 16, 32, 64 that holds all good helicities (64 loops over more)
+// lanes per event: the smallest of 4, 8, 16, 32, 64 that holds all good helicities (64 loops over more)
 inline int lanes_per_event(int ngood) {
   if (ngood <= 4) return 4;
+  if (ngood <= 8) return 8;
   if (ngood <= 16) return 16;
   if (ngood <= 32) return 32;
   return 64;
@@ -353,12 +354,14 @@ template <class Proc, class T, int LPE> hipError_t launch_lpe(const LaunchArgs& 
 }
 
 template <class Proc, class T> hipError_t launch_me2(const LaunchArgs& a) {
-  // processes with 64 or more helicities always fill whole wavefronts (idle lanes are masked)
-  if constexpr (Proc::nhel >= 64) {
+  // processes with 24 or more colour flows and 64 or more helicities always fill whole
+  // wavefronts (idle lanes are masked; the matrix-core colour sum takes one event per wavefront)
+  if constexpr (Proc::nhel >= 64 && Proc::ncol >= 24) {
     return launch_lpe<Proc, T, 64>(a);
   } else {
     switch (lanes_per_event(a.ngood)) {
       case 4: return launch_lpe<Proc, T, 4>(a);
+      case 8: return launch_lpe<Proc, T, 8>(a);
       case 16: return launch_lpe<Proc, T, 16>(a);
       case 32: return launch_lpe<Proc, T, 32>(a);
       default: return launch_lpe<Proc, T, 64>(a);

@@ -1,0 +1,19 @@
+// Kernels of one process (its own translation unit so processes compile in parallel).
+#include "me2_kernels.h"
+#include "procs/uueeggg.h"
+
+namespace hme {
+
+ProcInfo info_uueeggg() { return make_info<P_uueeggg>(); }
+
+// precision 1 (single-precision amplitudes) has its own kernel; 0 and 2 share the
+// double-precision one and differ in the colour-sum type only.
+hipError_t launch_me2_uueeggg(const LaunchArgs& a, int precision) {
+  return precision != 1 ? launch_me2<P_uueeggg, double>(a) : launch_me2<P_uueeggg, float>(a);
+}
+
+hipError_t launch_hel_uueeggg(const double* mom, int nev, const ProcParams& prm, double* out, hipStream_t s) {
+  return launch_hel<P_uueeggg>(mom, nev, prm, out, s);
+}
+
+}  // namespace hme

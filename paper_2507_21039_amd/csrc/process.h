@@ -12,6 +12,7 @@ struct ProcParams {
   double mZ, wZ;  // Z mass and width (s-channel Z only)
   double gL, gR;  // Z couplings to charged leptons: -1/2 + sin^2(thetaW), sin^2(thetaW)
   double cA, cZ;  // e^2 and e^2 / (sin^2 cos^2) for the photon and Z exchange
+  double gLu, gRu;  // Z couplings to up quarks: 1/2 - 2/3 sin^2(thetaW), -2/3 sin^2(thetaW)
 };
 
 }  // namespace hme

@@ -253,15 +253,17 @@ int rambo_fail(int code, const std::string& msg) {
 
 extern "C" int hme_rambo(int process, const hme_sm_card* card, double sqrt_s, uint64_t seed, int64_t first_event,
                          int64_t nevt, int cut, double cut_value, double* momenta, double* weights, void* hip_stream) {
-  static const int kNout[] = {2, 2, 3, 4, 5};  // final-state particles per process
-  if (process < 0 || process > HME_GGTTGGG) return rambo_fail(HME_E_ARG, "hme_rambo: unknown process");
+  static const int kNout[] = {2, 2, 3, 4, 5, 2, 3, 4, 5};  // final-state particles per process
+  if (process < 0 || process > HME_UUEEGGG) return rambo_fail(HME_E_ARG, "hme_rambo: unknown process");
   if (!card) return rambo_fail(HME_E_ARG, "hme_rambo: card is NULL");
   if (nevt < 0 || first_event < 0) return rambo_fail(HME_E_ARG, "hme_rambo: negative nevt or first_event");
   const int cut_kind = cut & ~HME_CUT_NO_RETRY;
   if ((cut & ~(HME_CUT_NO_RETRY | 0xff)) != 0 || cut_kind < HME_CUT_NONE || cut_kind > HME_CUT_GLUON_DR)
     return rambo_fail(HME_E_ARG, "hme_rambo: unknown cut");
   const int nout = kNout[process];
-  const double mt = process == HME_EEMUMU ? 0.0 : card->mT;
+  // massive final-state top pair for g g -> t tbar + n g; every other final state is massless
+  const bool tops = process >= HME_GGTT && process <= HME_GGTTGGG;
+  const double mt = tops ? card->mT : 0.0;
   if (!(mt >= 0)) return rambo_fail(HME_E_ARG, "hme_rambo: negative top mass");
   if (!(sqrt_s > 2 * mt) || !(sqrt_s > 0) || !std::isfinite(sqrt_s))
     return rambo_fail(HME_E_ARG, "hme_rambo: sqrt_s not above the final-state masses");

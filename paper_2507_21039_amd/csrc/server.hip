@@ -29,7 +29,7 @@ void set_last_error(const std::string& msg);
 
 namespace {
 
-constexpr int kNumProcesses = 5;
+constexpr int kNumProcesses = 9;  // every process of hme_process
 constexpr int64_t kMaxSubBatch = 4096;  // events per sub-batch of a process evaluated in pieces
 constexpr int kMaxBatchReq = 64;      // requests per batch
 constexpr int64_t kMinBucket = 256;   // smallest graph size bucket (events)

@@ -16,6 +16,13 @@ with one amplitude call.  This is the sequence the paper describes in section
 merged pairwise, a final vertex giving a complex amplitude, repeated for each
 diagram, then the colour inner product.
 
+The Drell-Yan family u ubar -> e+ e- + n g has the same structure with one more element on
+the quark line (from vbar(ubar), particle 1, to u(u), particle 0): the electroweak boson
+that carries the lepton pair.  Its photon and Z exchanges are one wavefunction here (the
+lepton current times the photon and Z propagators and couplings, summed for the quark's
+chirality, which a massless line conserves), so a diagram counts the photon and the Z
+together: 1 / 2 / 8 / 50 diagrams for n = 0..3 (2 / 4 / 16 / 100 counting them apart).
+
 Feynman rules with the strong coupling stripped (every amplitude carries g_s^n):
 quark-gluon vertex i gamma^mu T^a, three-gluon vertex f^{abc} V^{mu nu rho},
 four-gluon vertex -i [f^{abe} f^{cde} L1 + f^{ace} f^{bde} L2 + f^{ade} f^{bce} L3],
@@ -33,6 +40,7 @@ from functools import lru_cache
 from .colour import I, MINUS_I, ONE, Gauss, Poly
 
 TOP, ATOP = 2, 3  # particle indices of t and tbar (0-based)
+EW = ("W",)  # the electroweak boson (photon and Z) as an element of a quark-line sequence
 
 
 # ------------------------------------------------------------------ gluon trees
@@ -41,6 +49,8 @@ TOP, ATOP = 2, 3  # particle indices of t and tbar (0-based)
 
 
 def leaves(t) -> frozenset:
+    if t == EW:
+        return frozenset()
     if t[0] == "L":
         return frozenset([t[1]])
     return frozenset().union(*(leaves(x) for x in t[1:] if isinstance(x, tuple)))
@@ -85,7 +95,7 @@ def trees(S: frozenset):
 
 def versions(t):
     """Expand the four-gluon vertices of a topology into their three structures."""
-    if t[0] == "L":
+    if t == EW or t[0] == "L":
         return [t]
     if t[0] == "3":
         return [("3", x, y) for x in versions(t[1]) for y in versions(t[2])]
@@ -122,6 +132,18 @@ def diagrams(gluons):
     return out
 
 
+def diagrams_dy(gluons):
+    """Diagrams of u ubar -> e+ e- + gluons: gluon trees along the quark line with the
+    electroweak boson inserted at any position (sequences read from the ubar end)."""
+    out = []
+    parts = list(ordered_set_partitions(gluons)) if gluons else [()]
+    for blocks in parts:
+        for ts in itertools.product(*(trees(b) for b in blocks)):
+            for pos in range(len(ts) + 1):
+                out.append(tuple(ts[:pos]) + (EW,) + tuple(ts[pos:]))
+    return out
+
+
 # ------------------------------------------------------------------ colour of wavefunctions
 
 
@@ -132,6 +154,8 @@ def tree_poly(v) -> Poly:
     three-gluon current:  f^{xyr} T^r = -i[X, Y], propagator -i      -> -(XY - YX)
     four-gluon current s: -i * (-[[.,.],.]) from f f T, propagator -i -> +[[X,Y],Z], [[X,Z],Y], [[Y,Z],X]
     """
+    if v == EW:
+        return Poly.unit()  # colourless
     if v[0] == "L":
         return Poly.letter(v[1])
     if v[0] == "3":
@@ -151,7 +175,7 @@ def tree_poly(v) -> Poly:
 @dataclass(frozen=True)
 class Node:
     key: tuple
-    kind: str  # 'ext_v', 'ext_i', 'ext_o', 'vvv', 'vvvv', 'psi', 'psibar', 'qq'
+    kind: str  # 'ext_v', 'ext_i', 'ext_o', 'ext_w', 'vvv', 'vvvv', 'psi', 'psibar', 'qq'
     args: tuple  # keys of input nodes
     mask: int  # set of external particles the wavefunction covers
     extra: tuple = ()
@@ -170,6 +194,7 @@ class Amp:
 class Graph:
     npar: int
     gluons: tuple
+    family: str = "tt"  # "tt": g g -> t tbar + n g; "dy": u ubar -> e+ e- + n g
     nodes: dict = field(default_factory=dict)  # key -> Node, insertion = topological order
     amps: list = field(default_factory=list)
     ndiag: int = 0
@@ -184,20 +209,31 @@ def _bit(k):
     return 1 << k
 
 
-def build_graph(ngluon_final: int) -> Graph:
-    """Call graph for g g -> t tbar + ngluon_final g.
+def build_graph(ngluon_final: int, family: str = "tt") -> Graph:
+    """Call graph for g g -> t tbar + ngluon_final g (family "tt") or for
+    u ubar -> e+ e- + ngluon_final g (family "dy").
 
-    Particle indices: 0, 1 incoming gluons; 2 top; 3 antitop; 4.. outgoing gluons.
+    Particle indices, tt: 0, 1 incoming gluons; 2 top; 3 antitop; 4.. outgoing gluons.  The
+    quark line runs from ubar(t) (row spinor) to v(tbar) (column spinor).
+    dy: 0 u (incoming); 1 ubar (incoming); 2 e+; 3 e-; 4.. outgoing gluons.  The quark line
+    runs from vbar(ubar) (row spinor) to u(u) (column spinor); the external node ("E", "W") is
+    the electroweak current of the lepton pair.
     """
     npar = 4 + ngluon_final
-    gluons = tuple([0, 1] + list(range(4, npar)))
-    g = Graph(npar=npar, gluons=gluons)
+    dy = family == "dy"
+    gluons = tuple(range(4, npar)) if dy else tuple([0, 1] + list(range(4, npar)))
+    row_end, col_end = (1, 0) if dy else (TOP, ATOP)
+    g = Graph(npar=npar, gluons=gluons, family=family)
     for k in gluons:
         g.add(Node(("E", k), "ext_v", (), _bit(k)))
-    g.add(Node(("E", TOP), "ext_o", (), _bit(TOP)))
-    g.add(Node(("E", ATOP), "ext_i", (), _bit(ATOP)))
+    g.add(Node(("E", row_end), "ext_o", (), _bit(row_end)))
+    g.add(Node(("E", col_end), "ext_i", (), _bit(col_end)))
+    if dy:
+        g.add(Node(("E", "W"), "ext_w", (), _bit(2) | _bit(3)))
 
     def tree_node(v):
+        if v == EW:
+            return ("E", "W")
         if v[0] == "L":
             return ("E", v[1])
         if v[0] == "3":
@@ -210,7 +246,7 @@ def build_graph(ngluon_final: int) -> Graph:
     def psi_node(seq):
         """Spinor current: the trees in seq attached to v(tbar), seq read from the top end."""
         if not seq:
-            return ("E", ATOP)
+            return ("E", col_end)
         inner = psi_node(seq[1:])
         t = tree_node(seq[0])
         return g.add(Node(("F", seq), "psi", (inner, t), g.nodes[inner].mask | g.nodes[t].mask))
@@ -218,7 +254,7 @@ def build_graph(ngluon_final: int) -> Graph:
     def psibar_node(seq):
         """Barred spinor current: ubar(t) with the trees in seq attached, seq read from the top end."""
         if not seq:
-            return ("E", TOP)
+            return ("E", row_end)
         inner = psibar_node(seq[:-1])
         t = tree_node(seq[-1])
         return g.add(Node(("Fb", seq), "psibar", (inner, t), g.nodes[inner].mask | g.nodes[t].mask))
@@ -226,9 +262,10 @@ def build_graph(ngluon_final: int) -> Graph:
     def psi_poly(seq):
         p = Poly.unit()
         for v in seq:
-            p = p * tree_poly(v)
-        # each attachment: vertex i and propagator i -> -1
-        return p.scale(Gauss((-1) ** len(seq), 0))
+            # a gluon attachment: vertex i and propagator i -> -1; the electroweak boson:
+            # propagator i (its vertex factor, the same in every diagram, is left out)
+            p = (p * tree_poly(v)).scale(I if v == EW else Gauss(-1, 0))
+        return p
 
     def missing(seq, bar):
         """Number of fermion currents that closing with this sequence would add."""
@@ -242,14 +279,14 @@ def build_graph(ngluon_final: int) -> Graph:
         return cnt
 
     qq_key = None
-    diags = diagrams(gluons)
+    diags = diagrams_dy(gluons) if dy else diagrams(gluons)
     g.ndiag = len(diags)
     # close short quark lines first so that longer ones find their currents
     order = sorted(range(len(diags)), key=lambda d: (len(diags[d]), d))
     for d in order:
         topo = diags[d]
         for vs in itertools.product(*(versions(t) for t in topo)):
-            if len(vs) == 1:
+            if len(vs) == 1 and not dy:
                 root = vs[0]
                 if qq_key is None:
                     qq_key = g.add(Node(("Q",), "qq", (("E", TOP), ("E", ATOP)), _bit(TOP) | _bit(ATOP)))
@@ -278,8 +315,9 @@ def build_graph(ngluon_final: int) -> Graph:
             fb = psibar_node(bar)
             f = psi_node(right)
             t = tree_node(mid)
-            col = (psi_poly(bar) * tree_poly(mid) * psi_poly(right)).scale(I)
-            g.amps.append(Amp("ffv", (fb, f, t), (), col, d))
+            # the closing vertex: i for a gluon; the electroweak vertex factor is left out
+            colour = (psi_poly(bar) * tree_poly(mid) * psi_poly(right)).scale(ONE if mid == EW else I)
+            g.amps.append(Amp("ffv", (fb, f, t), (), colour, d))
     return g
 
 

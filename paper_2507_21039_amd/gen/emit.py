@@ -39,7 +39,9 @@ FLOPS["ffv_psibar_k"] = FLOPS["ffv_psibar"] - 10
 FLOPS["vvv_amp_k"] = FLOPS["vvv_amp"] - 12
 VK_SIZE = {"vvv": 12, "psi": 5, "amp3": 12}  # doubles per vertex kit
 VK_FLOPS = {"vvv": 24, "psi": 7, "amp3": 12}  # per event, in the table
-EXT_FLOPS = {"vxxxxx": 20, "ixxxxx": 30, "oxxxxx": 30}  # includes sqrt/div as one each
+EXT_FLOPS = {"vxxxxx": 20, "ixxxxx": 30, "oxxxxx": 30,  # includes sqrt/div as one each
+             "ewkit": 2 * 30 + 120 + 40}  # lepton spinors, lepton current, photon + Z couplings
+EW_ITEMS = 8  # electroweak current per (quark, e+, e-) helicity, 8 doubles each
 DEN_FLOPS = 9  # momentum square (7) and the reciprocal of (Q^2 - m^2) (2)
 
 
@@ -78,7 +80,7 @@ def _closure(g, keys):
 
 
 NODE_FLOPS = {"vvv": "vvv_vec_k", "vvvv": "vvvv_vec", "psi": "ffv_psi_k", "psibar": "ffv_psibar_k", "qq": "ffv_vec"}
-KIT_FLOPS = {"ext_v": 0, "ext_o": 0, "ext_i": 0}  # a wavefunction is read from its per-event kit
+KIT_FLOPS = {"ext_v": 0, "ext_o": 0, "ext_i": 0, "ext_w": 0}  # a wavefunction is read from its per-event kit
 
 
 UNIT = "@@UNIT@@"
@@ -261,7 +263,9 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
             k = key[1]
             kind = g.nodes[key].kind
             nm = f"e{k}_{len(out_lines)}"
-            if kind == "ext_v":
+            if kind == "ext_w":
+                out_lines.append(f"    const vw4<T> {nm} = ew_from_kit<T>(tab + KOFFW, hel(0), hel(2), hel(3));")
+            elif kind == "ext_v":
                 nsv = -1 if k < 2 else 1
                 out_lines.append(f"    const vw4<T> {nm} = vxxxxx_kit<T>(tab + KOFF{k}, hel({k}), {nsv});")
             elif kind == "ext_o":
@@ -394,7 +398,7 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
                 if next_use(x, t) >= 1 << 30:
                     del live[x]
         flops_exec += 2 * jamp_terms
-        ext_name = {"ext_v": "vxxxxx", "ext_o": "oxxxxx", "ext_i": "ixxxxx"}
+        ext_name = {"ext_v": "vxxxxx", "ext_o": "oxxxxx", "ext_i": "ixxxxx", "ext_w": "ewkit"}
         flops_dag += 2 * jamp_terms + sum(EXT_FLOPS[ext_name[g.nodes[k].kind]] for k in g.nodes if k[0] == "E")
         assert not jslot
         if jbudget:
@@ -424,17 +428,21 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
         lines_f, flops_exec_f, _, _ = emit_schedule(budget[1], order_f)
 
     nq, nd = len(qidx), len(didx)
-    ext = [k for k in range(npar)]
+    dy = g.family == "dy"
+    ext = [k for k in range(npar) if ("E", k) in g.nodes]  # particles with a kit of their own
     koff = {}
     off = 4 * nq + nd
     for k in ext:
         koff[k] = off
         off += 10 if g.nodes[("E", k)].kind == "ext_v" else 16  # both helicities
+    if dy:
+        koff["W"] = off
+        off += 8 * EW_ITEMS
     voff = off
     ntab = off + vk_off[0]
     def finish(lines, pf):
         lines = [l.replace("DOFF", str(4 * nq)).replace("VOFF", str(voff)) for l in lines]
-        for k in ext:
+        for k in koff:
             lines = [l.replace(f"KOFF{k}", str(koff[k])) for l in lines]
         return "\n".join(prefetch_units(lines, bool(pf), kits=(pf != "table")))
 
@@ -479,9 +487,24 @@ struct {name}_c{c} {{
     dmassive = [0] * nd
     for m, (i, massive) in didx.items():
         dmask[i], dmassive[i] = m, int(massive)
-    kind_code = {"ext_v": 0, "ext_o": 1, "ext_i": 2}
-    kits = [(koff[k], kind_code[g.nodes[("E", k)].kind], k) for k in ext]
-    flops_table = DEN_FLOPS * nd + 4 * nq + 40 * npar
+    # kit kinds: 0 vector; fermions 1 ubar (outgoing), 2 v (outgoing), 3 vbar (incoming),
+    # 4 u (incoming); -1 none (the leptons of the Drell-Yan family live in the electroweak kit)
+    kind_code = {"ext_v": 0, "ext_o": 3 if dy else 1, "ext_i": 4 if dy else 2}
+    kits = [(koff[k], kind_code[g.nodes[("E", k)].kind], k) if k in koff else (0, -1, k) for k in range(npar)]
+    flops_table = DEN_FLOPS * nd + 4 * nq + 40 * len(ext)
+    qmass = "0.0" if dy else "prm.mT"  # mass of the quark line
+    row_end = 1 if dy else TOP  # particle of the barred spinor at the quark line's end
+    fmass = "0.0" if dy else "k < 2 ? 0.0 : prm.mT"  # masses of the external fermions
+    ew_items = ""
+    if dy:
+        ew_items = (f"    if (j >= nq + nd + {npar} + nvk) {{\n"
+                    "      // the electroweak current of the lepton pair (u-quark charge 2/3, electron -1)\n"
+                    "      const EwCouplings c{prm.cA * (-2.0 / 3.0), prm.cZ, prm.gLu, prm.gRu, prm.gL, prm.gR, prm.mZ, prm.wZ};\n"
+                    f"      const int item = j - nq - nd - {npar} - nvk;\n"
+                    f"      ew_kit(p[2], p[3], c, item, tab + {koff['W']} + 8 * item);\n"
+                    "      return;\n"
+                    "    }\n")
+    flops_table += 0  # the electroweak kit is counted per helicity, with the external states
 
     # colour sum with symmetric integer numerators
     cs = []
@@ -496,7 +519,7 @@ struct {name}_c{c} {{
         cs_flops += 4 * len(terms) + 4
 
     nvk = len(vk_list)
-    nitems = nq + nd + npar + nvk
+    nitems = nq + nd + npar + nvk + (EW_ITEMS if dy else 0)
     flops_table += sum(VK_FLOPS[x[0]] for x in vk_list)
     vk_kind_code = {"vvv": 0, "psi": 1, "amp3": 2}
     numer_list = ", ".join(str(N[i][j]) for i in range(ncol) for j in range(ncol))
@@ -549,7 +572,7 @@ struct {name}_c{c} {{
 
 """
     hdr = f"""// Generated by paper_2507_21039_amd.gen for {label}.  Do not edit.
-// {g.ndiag} Feynman diagrams, {len(g.amps)} amplitude terms (each four-gluon vertex split into its
+// {g.ndiag} Feynman diagrams{" (photon and Z exchange counted together)" if dy else ""}, {len(g.amps)} amplitude terms (each four-gluon vertex split into its
 // three structures), {len(g.nodes)} wavefunctions, {ncol} colour flows; at most {budget[0]} (double) or
 // {budget[1]} (float) off-shell wavefunctions live at once (others are recomputed when needed again).
 #pragma once
@@ -565,7 +588,7 @@ struct {name} {{
   static constexpr int ndiag = {g.ndiag};
   static constexpr int namp = {len(g.amps)};
   static constexpr int gs_power = {2 * len(gl)};  // |M|^2 carries g_s^gs_power
-  static constexpr double iden = {iden_qcd(len(gl) - 2)};  // spin and colour average, identical gluons
+  static constexpr double iden = {iden_dy(len(gl)) if dy else iden_qcd(len(gl) - 2)};  // spin and colour average, identical gluons
   static constexpr double colour_denom = {D};
   static constexpr double flops_per_hel = {flops_dag + cs_flops};  // each wavefunction counted once
   static constexpr double flops_per_hel_executed = {flops_exec_d + cs_flops};  // with recomputation (double)
@@ -581,7 +604,7 @@ struct {name} {{
   static constexpr unsigned dmask[{max(nd, 1)}] = {{{", ".join(map(str, dmask))}}};
   static constexpr int dmassive[{max(nd, 1)}] = {{{", ".join(map(str, dmassive))}}};
   static constexpr int kit_off[{npar}] = {{{", ".join(str(k[0]) for k in kits)}}};
-  static constexpr int kit_kind[{npar}] = {{{", ".join(str(k[1]) for k in kits)}}};  // 0 vector, 1 ubar, 2 v
+  static constexpr int kit_kind[{npar}] = {{{", ".join(str(k[1]) for k in kits)}}};  // 0 vector, 1 ubar, 2 v, 3 vbar, 4 u, -1 none
 
   // vertex kits after the external-state kits: kind 0 three-gluon current (den (Qa - Qb),
   // den (Qa + 2 Qb), den (2 Qa + Qb) with den = 1 / Q^2 of mask 2), kind 1 quark propagator
@@ -596,8 +619,17 @@ struct {name} {{
   static constexpr int vk_off[{max(nvk, 1)}] = {{{", ".join(str(x[5]) for x in vk_list) or "0"}}};
 
   // sum of the incoming momenta of the particles in mask m (outgoing ones negated), each
-  // component as a compensated sum (exact for up to {npar} terms); k: a factor applied to every term
+  // component as a compensated sum (exact for up to {npar} terms); k: a factor applied to every term.
+  // An internal line has two sides; momenta given in double precision conserve momentum only up
+  // to rounding, so the two sums differ slightly, by 1e-12 relative in Q^2 of an almost
+  // on-shell line.  Every line therefore takes the sum over the side without particle {row_end}
+  // (the barred spinor of the quark line), whichever current it is built in: a mask holding
+  // that particle is replaced by its complement, negated.
   HME_FN static void mask_sum(const double (&p)[{npar}][4], unsigned m, dd* Q, double k = 1.0) {{
+    if (m >> {row_end} & 1u) {{
+      m = ~m & {(1 << npar) - 1}u;
+      k = -k;
+    }}
     Q[0] = Q[1] = Q[2] = Q[3] = dd{{0.0, 0.0}};
 #pragma unroll
     for (int j = 0; j < {npar}; ++j) {{
@@ -613,13 +645,13 @@ struct {name} {{
     dd A[4], B[4], C[4];
     mask_sum(p, vk_m0[v], A);
     if (vk_kind[v] == 1) {{
-      const double den = 1.0 / dd_minkowski_sq(A, prm.mT);
+      const double den = 1.0 / dd_minkowski_sq(A, {qmass});
       const double ds = den * vk_sign[v];
       o[0] = S(ds * dd_val(dd_add(A[0], A[3])));
       o[1] = S(ds * dd_val(dd_add(A[0], dd_neg(A[3]))));
       o[2] = S(ds * dd_val(A[1]));
       o[3] = S(ds * dd_val(A[2]));
-      o[4] = S(den * prm.mT);
+      o[4] = S(den * {qmass});
       return;
     }}
     mask_sum(p, vk_m1[v], B);
@@ -645,7 +677,7 @@ struct {name} {{
   // item j of the table (j < nitems); the lanes of an event compute disjoint items
   template <class S>
   HME_FN static void table_entry(const double (&p)[{npar}][4], const ProcParams& prm, int j, S* tab) {{
-    if (j >= nq + nd + {npar}) {{
+{ew_items}    if (j >= nq + nd + {npar}) {{
       const int v = j - nq - nd - {npar};
       vertex_kit(p, prm, v, tab + voff + vk_off[v]);
       return;
@@ -656,7 +688,7 @@ struct {name} {{
       for (int k = 0; k < {npar}; ++k) {{
         if (j - nq - nd != k) continue;
         if (kit_kind[k] == 0) vector_kit(p[k], k < 2 ? -1 : 1, tab + kit_off[k]);
-        else fermion_kit(p[k], k < 2 ? 0.0 : prm.mT, kit_kind[k], tab + kit_off[k]);
+        else if (kit_kind[k] > 0) fermion_kit(p[k], {fmass}, kit_kind[k], tab + kit_off[k]);
       }}
       return;
     }}
@@ -668,7 +700,7 @@ struct {name} {{
 #pragma unroll
       for (int mu = 0; mu < 4; ++mu) tab[4 * j + mu] = S(sg * dd_val(Q[mu]));
     }} else {{
-      tab[4 * nq + (j - nq)] = S(1.0 / dd_minkowski_sq(Q, dmassive[j - nq] ? prm.mT : 0.0));
+      tab[4 * nq + (j - nq)] = S(1.0 / dd_minkowski_sq(Q, dmassive[j - nq] ? {qmass} : 0.0));
     }}
   }}
 
@@ -697,6 +729,11 @@ struct {name} {{
 
 def iden_qcd(nfinal_gluons: int) -> float:
     return 4.0 * 64.0 * math.factorial(nfinal_gluons)
+
+
+def iden_dy(nfinal_gluons: int) -> float:
+    """u ubar initial state: 4 spin states, 9 colour states; identical final gluons."""
+    return 4.0 * 9.0 * math.factorial(nfinal_gluons)
 
 
 def emit_eemumu(name: str = "P_eemumu") -> tuple[str, dict]:

@@ -9,6 +9,10 @@
 #include "../../paper_2507_21039_amd/csrc/procs/ggtt.h"
 #include "../../paper_2507_21039_amd/csrc/procs/ggttg.h"
 #include "../../paper_2507_21039_amd/csrc/procs/ggttgg.h"
+#include "../../paper_2507_21039_amd/csrc/procs/uuee.h"
+#include "../../paper_2507_21039_amd/csrc/procs/uueeg.h"
+#include "../../paper_2507_21039_amd/csrc/procs/uueegg.h"
+#include "../../paper_2507_21039_amd/csrc/procs/uueeggg.h"
 
 namespace {
 template <class Proc, class T>
@@ -58,6 +62,10 @@ extern "C" int hostcheck_jamps(int process, const double* card, const double* mo
     case 1: jamps<hme::P_ggtt>(prm, mom, h, out); break;
     case 2: jamps<hme::P_ggttg>(prm, mom, h, out); break;
     case 3: jamps<hme::P_ggttgg>(prm, mom, h, out); break;
+    case 5: jamps<hme::P_uuee>(prm, mom, h, out); break;
+    case 6: jamps<hme::P_uueeg>(prm, mom, h, out); break;
+    case 7: jamps<hme::P_uueegg>(prm, mom, h, out); break;
+    case 8: jamps<hme::P_uueeggg>(prm, mom, h, out); break;
     default: return -1;
   }
   return 0;
@@ -79,6 +87,14 @@ extern "C" int hostcheck_me2(int process, int precision, const double* card, dou
                 : run<hme::P_ggttg, float>(prm, alpha_s, nevt, mom, out, per_hel); break;
     case 3: f64 ? run<hme::P_ggttgg, double>(prm, alpha_s, nevt, mom, out, per_hel)
                 : run<hme::P_ggttgg, float>(prm, alpha_s, nevt, mom, out, per_hel); break;
+    case 5: f64 ? run<hme::P_uuee, double>(prm, alpha_s, nevt, mom, out, per_hel)
+                : run<hme::P_uuee, float>(prm, alpha_s, nevt, mom, out, per_hel); break;
+    case 6: f64 ? run<hme::P_uueeg, double>(prm, alpha_s, nevt, mom, out, per_hel)
+                : run<hme::P_uueeg, float>(prm, alpha_s, nevt, mom, out, per_hel); break;
+    case 7: f64 ? run<hme::P_uueegg, double>(prm, alpha_s, nevt, mom, out, per_hel)
+                : run<hme::P_uueegg, float>(prm, alpha_s, nevt, mom, out, per_hel); break;
+    case 8: f64 ? run<hme::P_uueeggg, double>(prm, alpha_s, nevt, mom, out, per_hel)
+                : run<hme::P_uueeggg, float>(prm, alpha_s, nevt, mom, out, per_hel); break;
     default: return -1;
   }
   return 0;

@@ -42,7 +42,8 @@ def compare(w, p_dev, w_dev, p_host, w_host):
 
 
 @pytest.mark.parametrize("name,nevt,first", [("eemumu", 16384, 0), ("ggtt", 20011, 7), ("ggttg", 12007, 100),
-                                             ("ggttgg", 6007, 3), ("ggttggg", 4099, 65000)])
+                                             ("ggttgg", 6007, 3), ("ggttggg", 4099, 65000), ("uueeg", 6007, 9),
+                                             ("uueeggg", 4099, 1000)])
 def test_rambo_matches_host(name, nevt, first):
     w = configs.WORKLOADS[name]
     p_dev, w_dev = device_events(w, nevt, first)
