@@ -104,6 +104,19 @@ int hme_create(int process, const hme_sm_card* card, int precision, int device, 
  * consecutive sub-batches of 8192 events. */
 int hme_compute(hme_handle* h, double alpha_s, int64_t nevt, const double* momenta, double* me2, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): hme_compute with the same arguments,
+ * results and errors, that allocates nothing.  The jamp workspace of HME_GGTTGGG comes from a
+ * 256 MiB device array inside the library (one per device, held until the process ends,
+ * its address looked up once per device by hme_create) instead of hipMallocAsync: batches
+ * run in sub-batches of as many events as it holds (320 at 0.81 MB per event).  A process
+ * whose workspace for 4 events exceeds 256 MiB is rejected with HME_E_BUDGET.  Other
+ * processes use no workspace and run exactly as in hme_compute.  Every call on a device
+ * shares that device's array: calls that overlap in time on one device (different streams,
+ * threads or handles) race and give undefined results; calls in one stream are ordered. */
+int hme_compute_noalloc(hme_handle* h, double alpha_s, int64_t nevt, const double* momenta, double* me2,
+                        void* hip_stream);
+
 /* Fill `info` with the handle's process constants. */
 int hme_query(const hme_handle* h, hme_info* info);
 

@@ -30,7 +30,7 @@ HME_OK, HME_E_ARG, HME_E_HIP, HME_E_OOM, HME_E_BUDGET, HME_E_TIMEOUT, HME_E_UNSU
 EXPORTED = ("hme_create", "hme_compute", "hme_query", "hme_good_helicities", "hme_destroy", "hme_last_error",
             "hme_server_create", "hme_submit", "hme_wait", "hme_wait_timed", "hme_server_stats_get",
             "hme_server_destroy", "hme_rambo", "hme_weighted_sum", "hme_compute_select", "hme_compute_alphas",
-            "hme_submit_after", "hme_flat_cross_section")
+            "hme_submit_after", "hme_flat_cross_section", "hme_compute_noalloc")
 
 
 class SmCard(ctypes.Structure):
@@ -75,6 +75,7 @@ def lib():
         L.hme_create.argtypes = [ctypes.c_int, ctypes.POINTER(SmCard), ctypes.c_int, ctypes.c_int,
                                  ctypes.POINTER(vp)]
         L.hme_compute.argtypes = [vp, ctypes.c_double, ctypes.c_int64, vp, vp, vp]
+        L.hme_compute_noalloc.argtypes = [vp, ctypes.c_double, ctypes.c_int64, vp, vp, vp]
         L.hme_query.argtypes = [vp, ctypes.POINTER(Info)]
         L.hme_good_helicities.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int]
         L.hme_destroy.argtypes = [vp]
@@ -99,7 +100,7 @@ def lib():
         for name in ("hme_create", "hme_compute", "hme_query", "hme_good_helicities", "hme_destroy",
                      "hme_server_create", "hme_submit", "hme_wait", "hme_wait_timed", "hme_server_stats_get",
                      "hme_server_destroy", "hme_rambo", "hme_weighted_sum", "hme_compute_select",
-                     "hme_compute_alphas", "hme_submit_after", "hme_flat_cross_section"):
+                     "hme_compute_alphas", "hme_submit_after", "hme_flat_cross_section", "hme_compute_noalloc"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -194,6 +195,11 @@ class Handle:
     def compute_ptr(self, alpha_s: float, nevt: int, momenta_ptr: int, me2_ptr: int, stream_ptr: int = 0):
         _check(lib().hme_compute(self._h, float(alpha_s), int(nevt), ctypes.c_void_p(momenta_ptr),
                                  ctypes.c_void_p(me2_ptr), ctypes.c_void_p(stream_ptr)))
+
+    def compute_noalloc_ptr(self, alpha_s: float, nevt: int, momenta_ptr: int, me2_ptr: int, stream_ptr: int = 0):
+        """hme_compute_noalloc: as compute_ptr, with the library's static device scratch."""
+        _check(lib().hme_compute_noalloc(self._h, float(alpha_s), int(nevt), ctypes.c_void_p(momenta_ptr),
+                                         ctypes.c_void_p(me2_ptr), ctypes.c_void_p(stream_ptr)))
 
     def compute(self, momenta, out=None, alpha_s: float = 0.118, stream=None):
         """momenta: torch float64 device tensor [nevt, npar, 4]; returns |M|^2 [nevt] (float64, same device)."""

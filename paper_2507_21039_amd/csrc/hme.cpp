@@ -6,6 +6,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <random>
 #include <string>
 #include <vector>
@@ -78,6 +79,39 @@ int fail(int code, const std::string& msg) {
 namespace hme {
 void set_last_error(const std::string& msg) { g_last_error = msg; }
 }  // namespace hme
+
+// Device scratch of hme_compute_noalloc: the jamp workspace of a process evaluated in pieces,
+// for callers that cannot allocate.  One copy per device, held from the library's first use
+// of that device until the process ends.  In host code `scratch` names a host-side stand-in,
+// never the device copy: kernels and copies take the address kept in g_scratch_dev.
+constexpr size_t kScratchBytes = size_t(256) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};  // device address of `scratch` per device (null until looked up)
+
+// Looks up this device's copy of `scratch` once; the device must be current.
+hipError_t scratch_lookup(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!ptr) return hipErrorInvalidSymbol;
+  g_scratch_dev[device] = ptr;
+  return hipSuccess;
+}
+
+void* scratch_of(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return device >= 0 && device < kMaxDevices ? g_scratch_dev[device] : nullptr;
+}
+
+}  // namespace
 
 namespace {
 
@@ -184,6 +218,7 @@ int hme_create(int process, const hme_sm_card* card, int precision, int device, 
 
   if (P.info().nchunk > 0 && precision != HME_MIXED_FAST)
     return fail(HME_E_UNSUPPORTED, "hme_create: this process is built for HME_MIXED_FAST only");
+  if ((e = scratch_lookup(device)) != hipSuccess) return hip_fail(e, "hme_create: scratch address");
 
   auto* h = new hme_handle;
   h->process = process;
@@ -329,6 +364,35 @@ int hme_compute(hme_handle* h, double alpha_s, int64_t nevt, const double* momen
   if (!(alpha_s > 0)) return fail(HME_E_ARG, "hme_compute: alpha_s must be positive");
   return compute_impl("hme_compute", h, hme::handle_norm(h, alpha_s), nevt, momenta, me2, hip_stream,
                       hme::SelectArgs{});
+}
+
+int hme_compute_noalloc(hme_handle* h, double alpha_s, int64_t nevt, const double* momenta, double* me2,
+                        void* hip_stream) {
+  if (!h) return fail(HME_E_ARG, "hme_compute_noalloc: handle is NULL");
+  if (nevt < 0) return fail(HME_E_ARG, "hme_compute_noalloc: nevt < 0");
+  if (nevt == 0) return HME_OK;
+  if (!momenta || !me2) return fail(HME_E_ARG, "hme_compute_noalloc: NULL momenta or me2");
+  if ((reinterpret_cast<uintptr_t>(momenta) | reinterpret_cast<uintptr_t>(me2)) & 7u)
+    return fail(HME_E_ARG, "hme_compute_noalloc: pointers must be 8-byte aligned");
+  if (!(alpha_s > 0)) return fail(HME_E_ARG, "hme_compute_noalloc: alpha_s must be positive");
+  DeviceGuard guard(h->device);
+  if (guard.err != hipSuccess) return hip_fail(guard.err, "hme_compute_noalloc: hipSetDevice");
+  void* ws = nullptr;
+  int64_t ws_events = 0;
+  if (hme::handle_chunked(h)) {
+    // sub-batches as large as the scratch holds, a multiple of the colour kernel's 4 events per block
+    const int64_t per_event = hme::handle_ws_bytes_per_event(h);
+    ws_events = (int64_t)(kScratchBytes / (size_t)per_event) / 4 * 4;
+    if (ws_events < 4)
+      return fail(HME_E_BUDGET, "hme_compute_noalloc: the workspace of 4 events exceeds the 256 MiB scratch");
+    if (ws_events > nevt) ws_events = nevt;
+    ws = scratch_of(h->device);
+    if (!ws) return fail(HME_E_HIP, "hme_compute_noalloc: no scratch address for this device");
+  }
+  const hipError_t e = hme::launch_for_handle(h, nevt, nullptr, momenta, me2, hme::handle_norm(h, alpha_s),
+                                              static_cast<hipStream_t>(hip_stream), ws, ws_events);
+  if (e != hipSuccess) return hip_fail(e, "hme_compute_noalloc: launch");
+  return HME_OK;
 }
 
 int hme_compute_alphas(hme_handle* h, const double* alpha_s, int64_t nevt, const double* momenta, double* me2,
