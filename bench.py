@@ -117,7 +117,8 @@ def cpu_baseline(proc, p, gpu_out, card, target_s=12.0):
 
 def ggttggg_leg(card, steps=3, warmup=1):
     """gg -> ttbar ggg alone (the served mix's largest process): 65536 RAMBO events at 2 TeV, seed 5,
-    MIXED_FAST (the only precision it is built for), timed like the main workload."""
+    in its three precisions (the paper's FP64 against mixed contrast is about this process), timed
+    like the main workload; MIXED_FAST is the headline of this leg."""
     import torch
 
     import oracle
@@ -127,25 +128,38 @@ def ggttggg_leg(card, steps=3, warmup=1):
     p = w.momenta()
     mom = torch.from_numpy(p).cuda()
     out = torch.empty(w.nevt, dtype=torch.float64, device="cuda")
-    with hme.Handle(hme.GGTTGGG, card, hme.MIXED_FAST) as h:
-        info = h.query()
-        gpu_s, wall_s = time_steps(h, mom, out, steps, warmup)
-    got = out.cpu().numpy()
+    res, outs = {}, {}
+    for prec in (hme.MIXED_FAST, hme.FP64, hme.MIXED_PAPER):
+        name = hme.PRECISION_NAMES[prec]
+        with hme.Handle(hme.GGTTGGG, card, prec) as h:
+            info = h.query()
+            gpu_s, _ = time_steps(h, mom, out, steps, warmup)
+        per = gpu_s / steps
+        tflops = info["flops_per_event"] * w.nevt / per / 1e12
+        peak = PEAK_FP32_VALU if prec == hme.MIXED_FAST else PEAK_FP64_VALU
+        outs[name] = out.cpu().numpy().copy()
+        res[name] = {"value": w.nevt / per, "ms_per_step": per * 1e3, "achieved_tflops": tflops,
+                     "frac_of_valu_peak": tflops * 1e12 / peak, "valu_peak_tflops": peak / 1e12,
+                     "workspace_bytes_per_event": info["workspace_bytes_per_event"]}
+        log(f"[bench] gg->ttbar ggg {name}: {w.nevt / per:.4g} events/s, {per * 1e3:.2f} ms")
+    for name in ("mixed_fast", "mixed_paper"):
+        rel = np.abs(outs[name] / outs["fp64"] - 1)
+        res[name].update(max_rel_diff_vs_fp64=float(rel.max()), p99_rel_diff_vs_fp64=float(np.quantile(rel, 0.99)))
     idx = np.linspace(0, w.nevt - 1, 64).astype(int)
     threads = oracle.default_threads()
     t0 = time.perf_counter()
     ref = oracle.me2(configs.GGTTGGG, p[idx], card, nthreads=threads)
     dt = time.perf_counter() - t0
-    per = gpu_s / steps
-    tflops = info["flops_per_event"] * w.nevt / per / 1e12
-    return {"value": w.nevt * steps / gpu_s, "unit": "events/s", "ms_per_step": per * 1e3, "steps": steps,
+    fast = res["mixed_fast"]
+    return {"value": fast["value"], "unit": "events/s", "ms_per_step": fast["ms_per_step"], "steps": steps,
             "workload": f"gg->ttbar ggg, {w.nevt} RAMBO events at sqrt(s)=2 TeV, no cuts, seed 5",
             "dtype": "f32 vertices/propagators/jamps, bf16x3-split MFMA colour sum with f32 accumulation, "
                      "f64 externals and sums",
             "diagrams": 1240, "helicities": 128, "good_helicities": info["ngoodhel"], "colour_flows": 120,
-            "achieved_tflops": tflops, "frac_of_valu_peak": tflops * 1e12 / PEAK_FP32_VALU,
-            "max_rel_diff_vs_oracle_64_events": float(np.max(np.abs(got[idx] / ref - 1))),
-            "workspace_bytes_per_event": info["workspace_bytes_per_event"],
+            "achieved_tflops": fast["achieved_tflops"], "frac_of_valu_peak": fast["frac_of_valu_peak"],
+            "precisions": res,
+            "max_rel_diff_vs_oracle_64_events": {k: float(np.max(np.abs(v[idx] / ref - 1))) for k, v in outs.items()},
+            "workspace_bytes_per_event": fast["workspace_bytes_per_event"],
             "cpu_baseline": {"value": len(idx) / dt, "unit": "events/s", "cores": threads, "kind": "oracle",
                              "sample": f"{len(idx)} evenly spaced events of the same batch, FP64 oracle, {dt:.1f} s"}}
 
@@ -215,9 +229,12 @@ def select_leg(card, steps=3, warmup=1):
         t = {}
         with hme.Handle(w.process, card, prec) as h:
             alphas = 0.1 + 0.05 * rh  # one strong coupling per event
-            for name, fn in (("compute", lambda: h.compute(mom, out, 0.118, stream)),
-                             ("select", lambda: h.compute_select(mom, rh, rc, 0.118, stream)),
-                             ("alphas", lambda: h.compute_alphas(mom, alphas, out, stream))):
+            legs = [("compute", lambda: h.compute(mom, out, 0.118, stream)),
+                    ("select", lambda: h.compute_select(mom, rh, rc, 0.118, stream)),
+                    ("alphas", lambda: h.compute_alphas(mom, alphas, out, stream))]
+            if w.process != hme.GGTTGGG:
+                legs.append(("channels", lambda: h.compute_channels(mom, 0.118, stream)))
+            for name, fn in legs:
                 for _ in range(warmup):
                     fn()
                 a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -231,6 +248,8 @@ def select_leg(card, steps=3, warmup=1):
                     "ms_select": t["select"], "overhead": t["select"] / t["compute"] - 1,
                     "ms_per_event_alpha_s": t["alphas"], "overhead_per_event_alpha_s": t["alphas"] / t["compute"] - 1,
                     "events_per_s_select": w.nevt / t["select"] * 1e3}
+        if "channels" in t:
+            res[key].update(ms_channels=t["channels"], overhead_channels=t["channels"] / t["compute"] - 1)
     return res
 
 
@@ -375,8 +394,8 @@ def main():
     ap.add_argument("--no-configs", action="store_true", help="skip the C1-C3 and Drell-Yan legs")
     ap.add_argument("--pmc", action="store_true",
                     help="counter-collection mode: one FP64 and one MIXED_FAST gg->ttbar gg launch, one "
-                         "8192-event gg->ttbar ggg call, then a plain 256 MiB device copy (known traffic, "
-                         "for calibrating FETCH_SIZE / WRITE_SIZE); no JSON line")
+                         "8192-event gg->ttbar ggg call, then a plain 256 MiB device copy and a 256 MiB "
+                         "read-only sum (known traffic, for calibrating FETCH_SIZE / WRITE_SIZE); no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); events are independent and "
@@ -408,9 +427,11 @@ def main():
         src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")  # 256 MiB
         dst = torch.empty_like(src)
         dst.copy_(src)
+        # read-only calibration: a reduction reads the 256 MiB once and writes a few bytes
+        total = src.sum()
         torch.cuda.synchronize()
-        log("[bench] pmc mode: FP64 and MIXED_FAST gg->ttbar gg launches, one 8192-event gg->ttbar ggg "
-            "call, 256 MiB copy done")
+        log(f"[bench] pmc mode: FP64 and MIXED_FAST gg->ttbar gg launches, one 8192-event gg->ttbar ggg "
+            f"call, 256 MiB copy, 256 MiB read-only sum ({float(total):.0f}) done")
         return
     results = {}
     for prec, name in ((hme.FP64, "fp64"), (hme.MIXED_FAST, "mixed_fast"), (hme.MIXED_PAPER, "mixed_paper")):
@@ -495,6 +516,7 @@ def main():
         line["select"] = select_leg(card)
         log(f"[bench] select overhead: " + ", ".join(f"{k} {v['overhead'] * 100:.2f}%"
                                                      for k, v in line["select"].items()))
+        log(f"[bench] channel weights overhead (gg->ttbar gg): {line['select']['ggttgg']['overhead_channels'] * 100:.2f}%")
     if not args.no_served:
         log("[bench] served mix (Poisson, 200 requests/s)")
         line["served"] = served_leg(card, hme.MIXED_FAST)

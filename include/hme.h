@@ -46,8 +46,7 @@ typedef struct {
 } hme_sm_card;
 
 /* HME_GGTTGGG (1240 diagrams, 120 colour flows) is evaluated in pieces over a jamp
- * workspace (see hme_compute) and only at HME_MIXED_FAST; other precisions return
- * HME_E_UNSUPPORTED from hme_create. */
+ * workspace (see hme_compute), at every precision. */
 /* HME_UUEE .. HME_UUEEGGG: the Drell-Yan family u ubar -> e+ e- + n g (n = 0..3), the paper's
  * second standalone workload (section "SIMT GPU results"): massless quarks and leptons, the
  * lepton pair through a photon and a Z in the s channel, particles 0 u, 1 ubar (incoming),
@@ -97,11 +96,12 @@ int hme_create(int process, const hme_sm_card* card, int precision, int device, 
  * pointers, 8-byte aligned, [nevt][npar][4] and [nevt] doubles.  alpha_s is the
  * strong coupling for this call.  nevt = 0 is a successful no-op; any nevt >= 1
  * is valid (partial wavefronts are masked).  Not thread-safe per handle.
- * HME_GGTTGGG also takes a device workspace of min(nevt, 8192) events times
+ * HME_GGTTGGG also takes a device workspace of min(nevt, S) events times
  * hme_info.workspace_bytes_per_event (partial-jamp slots x good helicities x the size of a
- * complex jamp: 789 x 128 x 8 bytes = 0.81 MB per event in single precision), allocated and released on
- * `hip_stream` in stream order (HME_E_OOM if that fails); larger batches run as
- * consecutive sub-batches of 8192 events. */
+ * complex jamp: 789 x 128 x 8 bytes = 0.81 MB per event at HME_MIXED_FAST, twice that in the
+ * double-precision modes), allocated and released on `hip_stream` in stream order (HME_E_OOM if
+ * that fails); larger batches run as consecutive sub-batches of S events, S = 8192 at
+ * HME_MIXED_FAST and 4096 at HME_FP64 and HME_MIXED_PAPER (8 GiB of workspace at most). */
 int hme_compute(hme_handle* h, double alpha_s, int64_t nevt, const double* momenta, double* me2, void* hip_stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight
@@ -116,6 +116,20 @@ int hme_compute(hme_handle* h, double alpha_s, int64_t nevt, const double* momen
  * threads or handles) race and give undefined results; calls in one stream are ordered. */
 int hme_compute_noalloc(hme_handle* h, double alpha_s, int64_t nevt, const double* momenta, double* me2,
                         void* hip_stream);
+
+/* Same as hme_compute, and also the single-diagram-enhancement channel weights of every event
+ * (the paper's section "Event generation interface": with |M|^2, an event generator's
+ * multi-channel integration reads one weight per Feynman diagram).  channel_weights: device
+ * array [nevt][ndiag] doubles (hme_info.ndiag, diagrams in the generator's order), 8-byte
+ * aligned.  Weight of diagram d: W_d / sum_d' W_d', with W_d the sum over good helicities and
+ * over the diagram's amplitude terms of |a|^2, a the term with its colour factor stripped (a
+ * diagram with a four-gluon vertex has one term per colour structure; for the Drell-Yan family
+ * a diagram is the photon and the Z exchange together), accumulated in single precision.
+ * |M|^2 is computed as in hme_compute (equal up to rounding: the compiler may fuse the
+ * operations differently).  HME_E_UNSUPPORTED for HME_EEMUMU and HME_GGTTGGG; other errors as
+ * hme_compute. */
+int hme_compute_channels(hme_handle* h, double alpha_s, int64_t nevt, const double* momenta, double* me2,
+                         double* channel_weights, void* hip_stream);
 
 /* Fill `info` with the handle's process constants. */
 int hme_query(const hme_handle* h, hme_info* info);
@@ -218,9 +232,8 @@ int hme_flat_cross_section(const double* sums, int64_t npoints, double sqrt_s, d
  * also applies each request's alpha_s normalisation).  Batches on different
  * slots overlap on the device.  Per-event arithmetic does not depend on the
  * batch, so a request's |M|^2 are bitwise those of hme_compute on it alone.
- * HME_GGTTGGG is served only at HME_MIXED_FAST (hme_submit returns
- * HME_E_UNSUPPORTED otherwise); its jamp workspace, for sub-batches of up to 4096
- * events, takes at most half of each slot, and its requests must fit beside it.
+ * HME_GGTTGGG's jamp workspace, for sub-batches of up to 4096 events, takes at most half
+ * of each slot, and its requests must fit beside it.
  * The server is thread-safe. */
 
 typedef struct hme_server hme_server;

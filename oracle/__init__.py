@@ -61,6 +61,9 @@ def lib():
             L.oracle_partial_amps_dy.argtypes = [ctypes.c_int, dp, dp, ip, ctypes.c_int, ctypes.c_int, dp]
             L.oracle_dressed_amp_dy.argtypes = [ctypes.c_int, dp, dp, ip, ip, ctypes.c_int, ctypes.c_int,
                                                 ctypes.c_int, dp]
+            L.oracle_diagram_keys.argtypes = [ctypes.c_int, ctypes.c_char_p, ctypes.c_int]
+            L.oracle_channel_weights.argtypes = [ctypes.c_int, dp, ctypes.c_int64, dp, dp, ctypes.c_int]
+            L.oracle_diagram_sum.argtypes = [ctypes.c_int, dp, dp, ip, ip, ctypes.c_int, ctypes.c_int, dp]
             L.oracle_external.argtypes = [ctypes.c_int, dp, ctypes.c_double, ctypes.c_int, dp]
             L.oracle_gamma.argtypes = [ctypes.c_int, dp]
             L.oracle_su3.argtypes = [dp, dp]
@@ -241,3 +244,40 @@ def cross_section(me2_values, weights, sqrt_s: float):
     mean = v.sum() / n
     var = max((v * v).sum() / n - mean * mean, 0.0)
     return float(mean / flux * GEV2_TO_PB), float(np.sqrt(var / n) / flux * GEV2_TO_PB)
+
+
+def diagram_keys(process: int) -> list:
+    """Keys of the process's tree diagrams in the order of channel_weights (gluon g<particle>,
+    three-gluon vertex (x,y), four-gluon vertex [x,y,z], electroweak boson W; elements of the
+    quark line from its barred end, joined by ';')."""
+    buf = ctypes.create_string_buffer(1 << 20)
+    n = lib().oracle_diagram_keys(process, buf, len(buf))
+    if n < 0:
+        raise ValueError("no quark-line diagrams for this process")
+    return buf.value.decode().split("\n")
+
+
+def channel_weights(process: int, momenta, card, nthreads: int | None = None) -> np.ndarray:
+    """Per event and diagram: sum over spins and over the diagram's terms of |value|^2 (colour
+    stripped, g_s = 1), diagrams in the order of diagram_keys; [nevt, ndiag]."""
+    mom = np.ascontiguousarray(momenta, dtype=np.float64)
+    card = np.ascontiguousarray(card, dtype=np.float64)
+    nd = len(diagram_keys(process))
+    out = np.empty((mom.shape[0], nd), dtype=np.float64)
+    if lib().oracle_channel_weights(process, _dp(card), mom.shape[0], _dp(mom), _dp(out),
+                                    nthreads or default_threads()) != 0:
+        raise ValueError("bad arguments")
+    return out
+
+
+def diagram_sum(process: int, momentum, card, spins, col, row: int, column: int) -> complex:
+    """Sum over diagrams and terms of colour factor x value for explicit colours (equals the
+    colour-dressed amplitude)."""
+    mom = np.ascontiguousarray(momentum, dtype=np.float64)
+    card = np.ascontiguousarray(card, dtype=np.float64)
+    sp = np.ascontiguousarray(spins, dtype=np.int32)
+    cl = np.ascontiguousarray(col if len(col) else [0], dtype=np.int32)
+    out = np.empty(2)
+    if lib().oracle_diagram_sum(process, _dp(card), _dp(mom), _ip(sp), _ip(cl), row, column, _dp(out)) != 0:
+        raise ValueError("bad arguments")
+    return complex(out[0], out[1])

@@ -39,7 +39,9 @@
 #include <complex>
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <string>
 #include <numeric>
 #include <vector>
 #ifdef _OPENMP
@@ -1237,6 +1239,292 @@ template <class R> int me2_batch(int proc, const double* card, double alpha_s, i
 
 }  // namespace
 
+// ------------------------------------------- Feynman diagrams one by one (channel weights)
+//
+// Every tree diagram of g g -> t tbar + n g and of u ubar -> e+ e- + n g is enumerated
+// explicitly and evaluated on its own, with the colour factors stripped from the Feynman rules
+// (strong coupling 1): quark-gluon vertex i gamma^mu (T^a stripped); three-gluon vertex
+// V^{mu nu rho} (f^{abc} stripped); four-gluon vertex -i L_s for each of its three colour
+// structures f^{abe} f^{cde}, f^{ace} f^{bde}, f^{ade} f^{bce} (so a diagram with m four-gluon
+// vertices is 3^m terms); gluon propagator -i g / Q^2; quark propagator i (K-slash + m) /
+// (K^2 - m^2); for Drell-Yan the electroweak insertion of the recursion above (photon and Z
+// exchange together).  The colour factor of each term, from explicit generators and structure
+// constants, is kept beside it, so that the sum over terms of colour x value is the amplitude
+// for given colours (checked against the colour-dressed recursion).
+//
+// A diagram is a sequence of gluon trees along the quark line, read from the barred spinor (the
+// top, or the ubar), with the electroweak boson at one position for Drell-Yan; a tree is a
+// gluon, a three-gluon vertex joining two trees or a four-gluon vertex joining three (children
+// unordered).  Keys name diagrams independently of the enumeration order: a gluon is g<particle
+// index>, a three-gluon vertex (x,y), a four-gluon vertex [x,y,z] (children's keys sorted), the
+// boson W, and a diagram its elements joined by ';' from the barred end.
+
+struct Tree {
+  int kind;  // 1 gluon, 3 or 4: vertex joining the children c
+  int leaf;  // gluon index (kind 1)
+  int c[3];
+};
+
+struct DiagramList {
+  std::vector<Tree> pool;
+  std::vector<std::vector<int>> seq;  // tree indices from the barred end; -1 is the electroweak boson
+  std::vector<std::string> key;
+};
+
+const std::vector<int>& trees_over(int mask, std::vector<Tree>& pool, std::map<int, std::vector<int>>& memo) {
+  auto it = memo.find(mask);
+  if (it != memo.end()) return it->second;
+  std::vector<int> out;
+  const int low = mask & -mask;
+  if (mask == low) {
+    pool.push_back(Tree{1, __builtin_ctz(mask), {-1, -1, -1}});
+    out.push_back((int)pool.size() - 1);
+  } else {
+    // unordered splits into two parts (the first holds the lowest gluon), then into three
+    for (int a = (mask - 1) & mask; a > 0; a = (a - 1) & mask) {
+      if (!(a & low)) continue;
+      const int b = mask ^ a;
+      const std::vector<int> ta = trees_over(a, pool, memo), tb = trees_over(b, pool, memo);
+      for (int x : ta)
+        for (int y : tb) {
+          pool.push_back(Tree{3, -1, {x, y, -1}});
+          out.push_back((int)pool.size() - 1);
+        }
+    }
+    for (int a = (mask - 1) & mask; a > 0; a = (a - 1) & mask) {
+      if (!(a & low)) continue;
+      const int rest = mask ^ a, low2 = rest & -rest;
+      for (int b = (rest - 1) & rest; b > 0; b = (b - 1) & rest) {
+        if (!(b & low2)) continue;
+        const int c = rest ^ b;
+        const std::vector<int> ta = trees_over(a, pool, memo), tb = trees_over(b, pool, memo),
+                               tc = trees_over(c, pool, memo);
+        for (int x : ta)
+          for (int y : tb)
+            for (int z : tc) {
+              pool.push_back(Tree{4, -1, {x, y, z}});
+              out.push_back((int)pool.size() - 1);
+            }
+      }
+    }
+  }
+  return memo[mask] = out;
+}
+
+std::string tree_key(const std::vector<Tree>& pool, int t, const int* particle) {
+  const Tree& x = pool[t];
+  if (x.kind == 1) return "g" + std::to_string(particle[x.leaf]);
+  std::vector<std::string> k;
+  for (int i = 0; i < x.kind - 1; ++i) k.push_back(tree_key(pool, x.c[i], particle));
+  std::sort(k.begin(), k.end());
+  std::string s = x.kind == 3 ? "(" : "[";
+  for (size_t i = 0; i < k.size(); ++i) s += (i ? "," : "") + k[i];
+  return s + (x.kind == 3 ? ")" : "]");
+}
+
+void ordered_partitions(int rem, std::vector<int>& cur, std::vector<std::vector<int>>& out) {
+  if (!rem) {
+    out.push_back(cur);
+    return;
+  }
+  for (int s = rem; s > 0; s = (s - 1) & rem) {
+    cur.push_back(s);
+    ordered_partitions(rem ^ s, cur, out);
+    cur.pop_back();
+  }
+}
+
+// n gluons; dy: Drell-Yan (boson inserted at every position).  particle[g]: particle index of gluon g.
+DiagramList enumerate_diagrams(int n, bool dy, const int* particle) {
+  DiagramList D;
+  std::map<int, std::vector<int>> memo;
+  std::vector<std::vector<int>> parts;
+  std::vector<int> cur;
+  ordered_partitions((1 << n) - 1, cur, parts);
+  for (const auto& blocks : parts) {
+    std::vector<std::vector<int>> choice(blocks.size());
+    for (size_t i = 0; i < blocks.size(); ++i) choice[i] = trees_over(blocks[i], D.pool, memo);
+    std::vector<size_t> idx(blocks.size(), 0);
+    while (true) {
+      std::vector<int> s;
+      for (size_t i = 0; i < blocks.size(); ++i) s.push_back(choice[i][idx[i]]);
+      for (size_t pos = 0; pos <= (dy ? s.size() : 0); ++pos) {
+        std::vector<int> q = s;
+        if (dy) q.insert(q.begin() + pos, -1);
+        std::string k;
+        for (size_t i = 0; i < q.size(); ++i) k += (i ? ";" : "") + (q[i] < 0 ? std::string("W") : tree_key(D.pool, q[i], particle));
+        D.seq.push_back(q);
+        D.key.push_back(k);
+      }
+      size_t i = 0;
+      while (i < idx.size() && ++idx[i] == choice[i].size()) idx[i++] = 0;
+      if (i == idx.size()) break;
+    }
+  }
+  return D;
+}
+
+// one term of a gluon tree: its current (propagator included; the polarisation for a gluon),
+// colour vector, incoming momentum
+template <class R> struct TreeTerm {
+  V4<R> J;
+  std::array<R, 8> C;
+  std::array<R, 4> Q;
+};
+
+template <class R>
+std::vector<TreeTerm<R>> tree_terms(const std::vector<Tree>& pool, int t, const V4<R>* eps, const R (*q)[4],
+                                    const int* col) {
+  const Tree& x = pool[t];
+  const SU3<R>& S = su3<R>();
+  const cx<R> I(0, 1);
+  std::vector<TreeTerm<R>> out;
+  if (x.kind == 1) {
+    TreeTerm<R> w;
+    w.J = eps[x.leaf];
+    w.C.fill(0);
+    w.C[col ? col[x.leaf] : 0] = 1;
+    for (int i = 0; i < 4; ++i) w.Q[i] = q[x.leaf][i];
+    out.push_back(w);
+    return out;
+  }
+  std::vector<std::vector<TreeTerm<R>>> ch;
+  for (int i = 0; i < x.kind - 1; ++i) ch.push_back(tree_terms(pool, x.c[i], eps, q, col));
+  if (x.kind == 3) {
+    for (const auto& a : ch[0])
+      for (const auto& b : ch[1]) {
+        TreeTerm<R> w;
+        for (int i = 0; i < 4; ++i) w.Q[i] = a.Q[i] + b.Q[i];
+        const R Q2 = w.Q[0] * w.Q[0] - w.Q[1] * w.Q[1] - w.Q[2] * w.Q[2] - w.Q[3] * w.Q[3];
+        const V4<R> v = vertex3(a.J, a.Q.data(), b.J, b.Q.data());
+        for (int i = 0; i < 4; ++i) w.J[i] = -I * v[i] / Q2;
+        for (int e = 0; e < 8; ++e) {
+          R c = 0;
+          for (int i = 0; i < 8; ++i)
+            for (int j = 0; j < 8; ++j) c += S.f[i][j][e] * a.C[i] * b.C[j];
+          w.C[e] = c;
+        }
+        out.push_back(w);
+      }
+    return out;
+  }
+  for (const auto& a : ch[0])
+    for (const auto& b : ch[1])
+      for (const auto& c : ch[2]) {
+        V4<R> L[3];
+        vertex4(a.J, b.J, c.J, L);
+        std::array<R, 4> Qs;
+        for (int i = 0; i < 4; ++i) Qs[i] = a.Q[i] + b.Q[i] + c.Q[i];
+        const R Q2 = Qs[0] * Qs[0] - Qs[1] * Qs[1] - Qs[2] * Qs[2] - Qs[3] * Qs[3];
+        for (int s = 0; s < 3; ++s) {
+          TreeTerm<R> w;
+          w.Q = Qs;
+          // vertex -i L_s, propagator -i / Q^2
+          for (int i = 0; i < 4; ++i) w.J[i] = -L[s][i] / Q2;
+          for (int r = 0; r < 8; ++r) {
+            R acc = 0;
+            for (int i = 0; i < 8; ++i) {
+              if (a.C[i] == 0) continue;
+              for (int j = 0; j < 8; ++j) {
+                if (b.C[j] == 0) continue;
+                for (int k = 0; k < 8; ++k) {
+                  if (c.C[k] == 0) continue;
+                  R ff = 0;
+                  for (int e = 0; e < 8; ++e)
+                    ff += s == 0 ? S.f[i][j][e] * S.f[k][r][e]
+                                 : s == 1 ? S.f[i][k][e] * S.f[j][r][e] : S.f[i][r][e] * S.f[j][k][e];
+                  acc += ff * a.C[i] * b.C[j] * c.C[k];
+                }
+              }
+            }
+            w.C[r] = acc;
+          }
+          out.push_back(w);
+        }
+      }
+  return out;
+}
+
+// The terms of one diagram for one spin configuration: calls f(value, colour) for every term,
+// colour the 3 x 3 matrix of the quark line (rows: the barred end's colour).  tt: legs of
+// g g -> t tbar + n g; dy: legs of u ubar -> e+ e- + n g (exactly one of them non-null).
+template <class R, class F>
+void diagram_terms(const DiagramList& D, int d, const QcdLegs<R>* tt, const DyLegs<R>* dy, const int* col, F&& f) {
+  const SU3<R>& S = su3<R>();
+  const cx<R> I(0, 1);
+  const auto& s = D.seq[d];
+  const int k = (int)s.size();
+  std::vector<std::vector<TreeTerm<R>>> el(k);
+  for (int i = 0; i < k; ++i)
+    if (s[i] >= 0) el[i] = tt ? tree_terms(D.pool, s[i], tt->eps, tt->q, col) : tree_terms(D.pool, s[i], dy->eps, dy->q, col);
+  std::vector<size_t> idx(k, 0);
+  while (true) {
+    // from the unbarred end: spinor, then for each element from the last to the first its
+    // vertex, with a propagator between consecutive elements
+    Spinor<R> psi = tt ? tt->v4 : dy->u1;
+    std::array<R, 4> K;
+    for (int i = 0; i < 4; ++i) K[i] = tt ? tt->q4[i] : dy->p1[i];
+    std::array<std::array<cx<R>, 3>, 3> M{};  // colour of the elements to the right
+    for (int a = 0; a < 3; ++a) M[a][a] = 1;
+    for (int i = k - 1; i >= 0; --i) {
+      if (i < k - 1) {
+        // propagator with the momentum of the side toward the unbarred end
+        if (tt) {
+          V4<R> Kc = real4<R>(K.data());
+          Mat<R> prop = slash(Kc);
+          for (int a = 0; a < 4; ++a) prop[a][a] += tt->mT;
+          const R den = K[0] * K[0] - K[1] * K[1] - K[2] * K[2] - K[3] * K[3] - tt->mT * tt->mT;
+          const Spinor<R> t = mat_vec(prop, psi);
+          for (int a = 0; a < 4; ++a) psi[a] = I * t[a] / den;
+        } else {
+          psi = massless_prop(K.data(), psi);
+        }
+      }
+      if (s[i] < 0) {
+        psi = mat_vec(dy->ew, psi);
+        for (int a = 0; a < 4; ++a) K[a] -= dy->qv[a];
+      } else {
+        const TreeTerm<R>& w = el[i][idx[i]];
+        const Spinor<R> t = mat_vec(slash(w.J), psi);
+        for (int a = 0; a < 4; ++a) psi[a] = I * t[a];
+        for (int a = 0; a < 4; ++a) K[a] += w.Q[a];
+        std::array<std::array<cx<R>, 3>, 3> TM{};
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) {
+            cx<R> acc = 0;
+            for (int c = 0; c < 3; ++c) {
+              cx<R> tc = 0;
+              for (int g = 0; g < 8; ++g) tc += w.C[g] * S.T[g][a][c];
+              acc += tc * M[c][b];
+            }
+            TM[a][b] = acc;
+          }
+        M = TM;
+      }
+    }
+    const cx<R> value = row_col(tt ? tt->ubar3 : dy->vbar2, psi);
+    f(value, M);
+    int i = 0;
+    while (i < k && (s[i] < 0 || ++idx[i] == el[i].size())) {
+      idx[i] = 0;
+      ++i;
+    }
+    if (i == k) break;
+  }
+}
+
+int diagram_setup(int proc, int& npar, bool& dy, DiagramList& D) {
+  npar = npar_of(proc);
+  dy = proc == P_UUEE || proc == P_UUEEG || proc == P_UUEEGG || proc == P_UUEEGGG;
+  const bool tt = proc == P_GGTT || proc == P_GGTTG || proc == P_GGTTGG || proc == P_GGTTGGG;
+  if (!(dy || tt)) return -1;
+  const int n = dy ? npar - 4 : npar - 2;
+  int particle[8];
+  for (int g = 0; g < n; ++g) particle[g] = dy ? g + 4 : (g < 2 ? g : g + 2);
+  D = enumerate_diagrams(n, dy, particle);
+  return 0;
+}
+
 extern "C" {
 
 // |M|^2 for nevt events, momenta [nevt][npar][4] (E, px, py, pz) in GeV.
@@ -1429,6 +1717,85 @@ int oracle_dressed_amp_dy(int npar, const double* card, const double* mom, const
   dressed_amp_dy(L, col ? col : none, i1, a, D);
   out[0] = a[j2].real();
   out[1] = a[j2].imag();
+  return 0;
+}
+
+// Diagram keys of a process (see "Feynman diagrams one by one"), joined by newlines into buf
+// (cap bytes, NUL-terminated); returns the number of diagrams, or -(bytes needed) if cap is too
+// small, or -1 for a process without a quark line.
+int oracle_diagram_keys(int proc, char* buf, int cap) {
+  int npar;
+  bool dy;
+  DiagramList D;
+  if (diagram_setup(proc, npar, dy, D) != 0) return -1;
+  std::string all;
+  for (size_t d = 0; d < D.key.size(); ++d) all += (d ? "\n" : "") + D.key[d];
+  if ((int)all.size() + 1 > cap) return -(int)(all.size() + 1);
+  std::memcpy(buf, all.c_str(), all.size() + 1);
+  return (int)D.key.size();
+}
+
+// Channel weights: out[e][d] = sum over every spin configuration and over the terms of diagram d
+// of |value|^2 (colour stripped, g_s = 1, no normalisation), diagrams in the order of
+// oracle_diagram_keys.  Returns 0, or -1 for a process without a quark line.
+int oracle_channel_weights(int proc, const double* card, int64_t nevt, const double* mom, double* out,
+                           int nthreads) {
+  int npar;
+  bool dy;
+  DiagramList D;
+  if (!card || !mom || !out || nevt < 0 || diagram_setup(proc, npar, dy, D) != 0) return -1;
+  const Couplings<double> cp = make_couplings<double>(card);
+  const int nd = (int)D.seq.size();
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic) num_threads(nthreads > 0 ? nthreads : 1)
+#endif
+  for (int64_t e = 0; e < nevt; ++e) {
+    const double* p = mom + e * npar * 4;
+    double* w = out + e * nd;
+    for (int d = 0; d < nd; ++d) w[d] = 0;
+    int spins[8];
+    for (int h = 0; h < (1 << npar); ++h) {
+      for (int k = 0; k < npar; ++k) spins[k] = h >> (npar - 1 - k) & 1;
+      if (dy) {
+        const DyLegs<double> L = dy_legs(p, npar, cp, spins, -1);
+        for (int d = 0; d < nd; ++d)
+          diagram_terms<double>(D, d, nullptr, &L, nullptr, [&](cx<double> v, const auto&) { w[d] += std::norm(v); });
+      } else {
+        const QcdLegs<double> L = qcd_legs(p, npar, cp.mT, spins, -1);
+        for (int d = 0; d < nd; ++d)
+          diagram_terms<double>(D, d, &L, nullptr, nullptr, [&](cx<double> v, const auto&) { w[d] += std::norm(v); });
+      }
+    }
+  }
+  return 0;
+}
+
+// Sum over every diagram and term of colour factor x value for explicit colours: gluon colours
+// col[] (0..7), row colour (the top, or the ubar) and column colour (the antitop, or the u),
+// spins as oracle_dressed_amp / oracle_dressed_amp_dy; out = (re, im).  Equals the colour-dressed
+// amplitude.
+int oracle_diagram_sum(int proc, const double* card, const double* mom, const int* spins, const int* col, int row,
+                       int column, double* out) {
+  int npar;
+  bool dy;
+  DiagramList D;
+  if (!card || !mom || !spins || !out || row < 0 || row > 2 || column < 0 || column > 2 ||
+      diagram_setup(proc, npar, dy, D) != 0)
+    return -1;
+  const Couplings<double> cp = make_couplings<double>(card);
+  const int none[1] = {0};
+  const int* c = col ? col : none;
+  cx<double> acc = 0;
+  auto add = [&](cx<double> v, const std::array<std::array<cx<double>, 3>, 3>& M) { acc += M[row][column] * v; };
+  if (dy) {
+    const DyLegs<double> L = dy_legs(mom, npar, cp, spins, -1);
+    for (size_t d = 0; d < D.seq.size(); ++d) diagram_terms<double>(D, (int)d, nullptr, &L, c, add);
+  } else {
+    const QcdLegs<double> L = qcd_legs(mom, npar, cp.mT, spins, -1);
+    for (size_t d = 0; d < D.seq.size(); ++d) diagram_terms<double>(D, (int)d, &L, nullptr, c, add);
+  }
+  out[0] = acc.real();
+  out[1] = acc.imag();
   return 0;
 }
 

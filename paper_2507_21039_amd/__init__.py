@@ -30,7 +30,7 @@ HME_OK, HME_E_ARG, HME_E_HIP, HME_E_OOM, HME_E_BUDGET, HME_E_TIMEOUT, HME_E_UNSU
 EXPORTED = ("hme_create", "hme_compute", "hme_query", "hme_good_helicities", "hme_destroy", "hme_last_error",
             "hme_server_create", "hme_submit", "hme_wait", "hme_wait_timed", "hme_server_stats_get",
             "hme_server_destroy", "hme_rambo", "hme_weighted_sum", "hme_compute_select", "hme_compute_alphas",
-            "hme_submit_after", "hme_flat_cross_section", "hme_compute_noalloc")
+            "hme_submit_after", "hme_flat_cross_section", "hme_compute_noalloc", "hme_compute_channels")
 
 
 class SmCard(ctypes.Structure):
@@ -76,6 +76,7 @@ def lib():
                                  ctypes.POINTER(vp)]
         L.hme_compute.argtypes = [vp, ctypes.c_double, ctypes.c_int64, vp, vp, vp]
         L.hme_compute_noalloc.argtypes = [vp, ctypes.c_double, ctypes.c_int64, vp, vp, vp]
+        L.hme_compute_channels.argtypes = [vp, ctypes.c_double, ctypes.c_int64, vp, vp, vp, vp]
         L.hme_query.argtypes = [vp, ctypes.POINTER(Info)]
         L.hme_good_helicities.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int]
         L.hme_destroy.argtypes = [vp]
@@ -100,7 +101,8 @@ def lib():
         for name in ("hme_create", "hme_compute", "hme_query", "hme_good_helicities", "hme_destroy",
                      "hme_server_create", "hme_submit", "hme_wait", "hme_wait_timed", "hme_server_stats_get",
                      "hme_server_destroy", "hme_rambo", "hme_weighted_sum", "hme_compute_select",
-                     "hme_compute_alphas", "hme_submit_after", "hme_flat_cross_section", "hme_compute_noalloc"):
+                     "hme_compute_alphas", "hme_submit_after", "hme_flat_cross_section", "hme_compute_noalloc",
+                     "hme_compute_channels"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -200,6 +202,26 @@ class Handle:
         """hme_compute_noalloc: as compute_ptr, with the library's static device scratch."""
         _check(lib().hme_compute_noalloc(self._h, float(alpha_s), int(nevt), ctypes.c_void_p(momenta_ptr),
                                          ctypes.c_void_p(me2_ptr), ctypes.c_void_p(stream_ptr)))
+
+    def compute_channels(self, momenta, alpha_s: float = 0.118, stream=None):
+        """|M|^2 and the single-diagram-enhancement channel weights (hme_compute_channels).
+
+        Returns (me2 float64 [nevt], weights float64 [nevt, ndiag]) on the momenta's device.
+        """
+        import torch
+        if momenta.device.type != "cuda" or momenta.dtype != torch.float64 or not momenta.is_contiguous():
+            raise ValueError("momenta must be a contiguous float64 GPU tensor")
+        if momenta.dim() != 3 or momenta.shape[1] != NPAR[self.process] or momenta.shape[2] != 4:
+            raise ValueError(f"momenta must be [nevt, {NPAR[self.process]}, 4]")
+        n = momenta.shape[0]
+        nd = self.query()["ndiag"]
+        me2 = torch.empty(n, dtype=torch.float64, device=momenta.device)
+        w = torch.empty((n, nd), dtype=torch.float64, device=momenta.device)
+        s = stream if stream is not None else torch.cuda.current_stream(momenta.device)
+        _check(lib().hme_compute_channels(self._h, float(alpha_s), n, ctypes.c_void_p(momenta.data_ptr()),
+                                          ctypes.c_void_p(me2.data_ptr()), ctypes.c_void_p(w.data_ptr()),
+                                          ctypes.c_void_p(s.cuda_stream)))
+        return me2, w
 
     def compute(self, momenta, out=None, alpha_s: float = 0.118, stream=None):
         """momenta: torch float64 device tensor [nevt, npar, 4]; returns |M|^2 [nevt] (float64, same device)."""

@@ -464,6 +464,37 @@ template <class T, class S> HME_FN sp4<T> ixxxxx_kit(const volatile HME_LDS S* k
   return spinor_from<T>(load_kit<T, 8>(kit + (lam > 0 ? 0 : 8)));
 }
 
+// Observer of the amplitude terms in the generated code: term(d, a) for each term a of diagram
+// d.  The default does nothing (and costs nothing).
+struct NoObserver {
+  template <class C> HME_FN void term(int, const C&) const {}
+};
+
+// Recycled wavefunctions (helicity recycling): a wavefunction built from two external states
+// is computed once per event for each of its 4 helicity pairs and stored in the table as its
+// 4 complex components; a lane reads the pair of its helicity.
+template <class W, class S> HME_FN void store_wf(const W& x, S* o) {
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    o[2 * mu] = x.c[mu].r;
+    o[2 * mu + 1] = x.c[mu].i;
+  }
+}
+template <class T, class S> HME_FN vw4<T> recycled_vw4(const volatile HME_LDS S* p, int off) {
+  const kitv<T, 8> k = load_kit<T, 8>(p + off);
+  vw4<T> w;
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) w.c[mu] = {k.v[2 * mu], k.v[2 * mu + 1]};
+  return w;
+}
+template <class T, class S> HME_FN sp4<T> recycled_sp4(const volatile HME_LDS S* p, int off) {
+  const kitv<T, 8> k = load_kit<T, 8>(p + off);
+  sp4<T> w;
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) w.c[mu] = {k.v[2 * mu], k.v[2 * mu + 1]};
+  return w;
+}
+
 // ------------------------------------------------------------------ vertices with per-event kits
 // The helicity-independent parts of a vertex (momentum combinations, propagator factor) are
 // computed once per event into the table; these variants read them instead of forming them

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -216,8 +217,6 @@ int hme_create(int process, const hme_sm_card* card, int precision, int device, 
   DeviceGuard guard(device);
   if (guard.err != hipSuccess) return hip_fail(guard.err, "hme_create: hipSetDevice");
 
-  if (P.info().nchunk > 0 && precision != HME_MIXED_FAST)
-    return fail(HME_E_UNSUPPORTED, "hme_create: this process is built for HME_MIXED_FAST only");
   if ((e = scratch_lookup(device)) != hipSuccess) return hip_fail(e, "hme_create: scratch address");
 
   auto* h = new hme_handle;
@@ -307,9 +306,11 @@ int handle_npar(const hme_handle* h) { return h->info.npar; }
 
 bool handle_chunked(const hme_handle* h) { return h->info.nchunk > 0; }
 
-// workspace bytes per event of a sub-batch (0 for a process evaluated in one kernel)
+// workspace bytes per event of a sub-batch (0 for a process evaluated in one kernel): a complex
+// partial jamp per slot and good helicity, in the type of the amplitudes
 int64_t handle_ws_bytes_per_event(const hme_handle* h) {
-  return handle_chunked(h) ? (int64_t)h->info.nslot * (int64_t)h->goodhel.size() * 2 * (int64_t)sizeof(float) : 0;
+  const int64_t real = h->precision == HME_MIXED_FAST ? (int64_t)sizeof(float) : (int64_t)sizeof(double);
+  return handle_chunked(h) ? (int64_t)h->info.nslot * (int64_t)h->goodhel.size() * 2 * real : 0;
 }
 
 hipError_t launch_for_handle(const hme_handle* h, int64_t nevt_grid, const int64_t* nevt_dev, const double* mom,
@@ -340,7 +341,9 @@ static int compute_impl(const char* who, hme_handle* h, double norm, int64_t nev
   hipError_t e;
   if (hme::handle_chunked(h)) {
     // jamp workspace, allocated and released in stream order
-    ws_events = nevt < hme::kChunkSubBatch ? nevt : hme::kChunkSubBatch;
+    // at most 8192 events and 8 GiB per sub-batch (4096 events in double precision)
+    const int64_t cap = std::min<int64_t>(hme::kChunkSubBatch, (int64_t(8) << 30) / hme::handle_ws_bytes_per_event(h));
+    ws_events = nevt < cap ? nevt : cap;
     const size_t bytes = (size_t)ws_events * (size_t)hme::handle_ws_bytes_per_event(h);
     if ((e = hipMallocAsync(&ws, bytes, stream)) != hipSuccess)
       return fail(HME_E_OOM, w + ": workspace: " + hipGetErrorString(e));
@@ -426,8 +429,27 @@ int hme_compute_select(hme_handle* h, double alpha_s, int64_t nevt, const double
       ((reinterpret_cast<uintptr_t>(sel_hel) | reinterpret_cast<uintptr_t>(sel_col)) & 3u))
     return fail(HME_E_ARG, "hme_compute_select: misaligned buffer");
   if (!(alpha_s > 0)) return fail(HME_E_ARG, "hme_compute_select: alpha_s must be positive");
+  if (h->info.nchunk > 0 && h->precision == HME_FP64)
+    return fail(HME_E_UNSUPPORTED, "hme_compute_select: gg -> ttbar ggg chooses at HME_MIXED_FAST or HME_MIXED_PAPER");
   return compute_impl("hme_compute_select", h, hme::handle_norm(h, alpha_s), nevt, momenta, me2, hip_stream,
                       hme::SelectArgs{rnd_hel, rnd_col, sel_hel, sel_col});
+}
+
+int hme_compute_channels(hme_handle* h, double alpha_s, int64_t nevt, const double* momenta, double* me2,
+                         double* channel_weights, void* hip_stream) {
+  if (!h) return fail(HME_E_ARG, "hme_compute_channels: handle is NULL");
+  if (nevt < 0) return fail(HME_E_ARG, "hme_compute_channels: nevt < 0");
+  if (h->info.nchunk > 0 || h->process == HME_EEMUMU)
+    return fail(HME_E_UNSUPPORTED, "hme_compute_channels: no channel weights for this process");
+  if (nevt == 0) return HME_OK;
+  if (!momenta || !me2 || !channel_weights) return fail(HME_E_ARG, "hme_compute_channels: NULL buffer");
+  if ((reinterpret_cast<uintptr_t>(momenta) | reinterpret_cast<uintptr_t>(me2) |
+       reinterpret_cast<uintptr_t>(channel_weights)) & 7u)
+    return fail(HME_E_ARG, "hme_compute_channels: pointers must be 8-byte aligned");
+  if (!(alpha_s > 0)) return fail(HME_E_ARG, "hme_compute_channels: alpha_s must be positive");
+  hme::SelectArgs sel{};
+  sel.chan_w = channel_weights;
+  return compute_impl("hme_compute_channels", h, hme::handle_norm(h, alpha_s), nevt, momenta, me2, hip_stream, sel);
 }
 
 int hme_query(const hme_handle* h, hme_info* info) {

@@ -44,6 +44,25 @@ struct SelectArgs {
   const double* rnd_col = nullptr;
   int* sel_hel = nullptr;
   int* sel_col = nullptr;
+  double* chan_w = nullptr;  // channel weights [nevt][ndiag] (a kernel variant of its own)
+};
+
+// Single-diagram-enhancement channel weights (section "Event generation interface": what an
+// event generator's multi-channel integration reads besides |M|^2): for each Feynman diagram d,
+// W_d = sum over good helicities and over the diagram's amplitude terms of |a|^2 (colour
+// stripped; a diagram with a four-gluon vertex has one term per colour structure), normalised to
+// sum to 1 over the diagrams.  The observer sums each term's |a|^2 over the event's LPE lanes
+// (one helicity each) and one lane adds it to the event's LDS row.
+template <class T, int LPE> struct ChannelObserver {
+  volatile HME_LDS double* w;
+  bool valid;
+  int sub;
+  HME_FN void term(int d, const cx<T>& a) const {
+    float s = valid ? (float)a.r * (float)a.r + (float)a.i * (float)a.i : 0.f;
+#pragma unroll
+    for (int off = LPE / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (sub == 0) w[d] += (double)s;
+  }
 };
 
 // Sums over the 64 lanes of a wavefront of v[c] for every c < K (K a power of two), by
@@ -185,15 +204,35 @@ HME_FN void choose_helicity_and_flow(const cx<T> (&jamp)[Proc::ncol], bool valid
   }
 }
 
-template <class Proc, class T, int LPE, bool Select = false>
+// The per-event table, built by the event's LPE lanes (an aligned segment of one wavefront):
+// first the compensated momentum sums into ms (8 doubles each), then the table items from them,
+// then the recycled wavefunctions from the items.
+// A barrier over the block must follow before the table is read.
+template <class Proc, int LPE, class S>
+HME_FN void build_event_table(const double (&p)[Proc::npar][4], const ProcParams& prm, int sub, double* ms, S* tab) {
+  for (int i = sub; i < Proc::nsum; i += LPE) Proc::momentum_sum(p, i, ms);
+  wave_lds_sync();
+  for (int j = sub; j < Proc::nitems; j += LPE) Proc::table_entry(p, prm, j, ms, tab);
+  if constexpr (Proc::nrec > 0) {
+    // helicity recycling: the two-state wavefunctions for every helicity pair, from the kits
+    wave_lds_sync();
+    for (int i = sub; i < 4 * Proc::nrec; i += LPE) Proc::template recycled_entry<S>(i, (tab_of<S>)tab, tab);
+  }
+}
+
+// Mode 0: |M|^2; 1: also the helicity and colour-flow choice; 2: also the channel weights.
+template <class Proc, class T, int LPE, int Mode = 0>
 __global__ void __launch_bounds__(256, me2_min_waves<T>())
     me2_kernel(const double* __restrict__ mom, double* __restrict__ out, int64_t nevt,
                const int* __restrict__ goodhel, int ngood, ProcParams prm, double norm, int colour_f32,
                const int64_t* __restrict__ nevt_dev, SelectArgs sel) {
+  constexpr bool Select = Mode == 1, Channels = Mode == 2;
   constexpr int EPW = 64 / LPE;   // events per wavefront
   constexpr int EPB = 256 / LPE;  // events per block
-  // per-event table of momentum sums and propagator denominators, shared by the event's lanes
+  // per-event table of momentum sums and propagator denominators, shared by the event's lanes,
+  // and the compensated momentum sums it is built from
   __shared__ T table[EPB * (Proc::ntab > 0 ? Proc::ntab : 1)];
+  __shared__ double msums[EPB * 8 * (Proc::nsum > 0 ? Proc::nsum : 1)];
   // with single-precision amplitudes, the colour sums of processes with 24 or more flows run
   // on the matrix cores (one event per wavefront, the 64 lanes are 64 helicity columns)
   constexpr bool kMfmaColour = LPE == 64 && Proc::ncol >= 24 && sizeof(T) == 4;
@@ -201,6 +240,8 @@ __global__ void __launch_bounds__(256, me2_min_waves<T>())
   __shared__ __attribute__((aligned(16))) __bf16 cnl[kMfmaColour ? ColourTiles<Proc>::words : 8];
   // flow weights of the selection variant (one array per wavefront, events of 64 lanes)
   __shared__ double wsel[4][Select && LPE == 64 && Proc::ncol >= 16 ? Proc::ncol : 1];
+  // channel weights of the events of the block
+  __shared__ double wch[Channels ? EPB : 1][Channels ? Proc::ndiag : 1];
   const int lane = threadIdx.x & 63;
   // the event count comes from device memory when a captured graph launches a batch of
   // varying size with a fixed grid; blocks past the end leave at once
@@ -215,18 +256,28 @@ __global__ void __launch_bounds__(256, me2_min_waves<T>())
   double p[Proc::npar][4];
   load_event<Proc>(mom, evc, p);
   T* tab = table + (threadIdx.x / LPE) * Proc::ntab;
-  for (int j = sub; j < Proc::nitems; j += LPE) Proc::table_entry(p, prm, j, tab);
+  double* ms = msums + (threadIdx.x / LPE) * 8 * Proc::nsum;
+  build_event_table<Proc, LPE>(p, prm, sub, ms, tab);
   if constexpr (kMfmaColour) colour_tiles_fill<Proc>(cnh, cnl, threadIdx.x, 256);
   __syncthreads();
   double acc = 0.0;
-  if constexpr (Select) {
+  if constexpr (Mode != 0) {
     // one helicity per lane (the launcher checks ngood <= LPE); every lane runs, a lane past
     // the last good helicity evaluates the last one again and contributes zero
     const bool valid = sub < ngood;
     cx<T> jamp[Proc::ncol];
 #pragma unroll
     for (int c = 0; c < Proc::ncol; ++c) jamp[c] = {T(0), T(0)};
-    Proc::template amplitudes<T>(p, prm, (unsigned)goodhel[valid ? sub : ngood - 1], (tab_of<T>)tab, jamp);
+    const unsigned hsel = (unsigned)goodhel[valid ? sub : ngood - 1];
+    [[maybe_unused]] volatile HME_LDS double* wd = nullptr;
+    if constexpr (Channels) {
+      wd = (volatile HME_LDS double*)&wch[threadIdx.x / LPE][0];
+      for (int d = sub; d < Proc::ndiag; d += LPE) wd[d] = 0.0;
+      wave_lds_sync();
+      Proc::template amplitudes<T>(p, prm, hsel, (tab_of<T>)tab, jamp, ChannelObserver<T, LPE>{wd, valid, sub});
+    } else {
+      Proc::template amplitudes<T>(p, prm, hsel, (tab_of<T>)tab, jamp);
+    }
     double mh;
     if constexpr (kMfmaColour) {
       mh = (double)colour_sum_wave<Proc>(jamp, NumerLds<Proc>{(const HME_LDS __bf16*)cnh, (const HME_LDS __bf16*)cnl});
@@ -239,8 +290,19 @@ __global__ void __launch_bounds__(256, me2_min_waves<T>())
       mh = (double)Proc::template colour_sum<T>(jamp);
     }
     acc = valid ? mh : 0.0;
-    choose_helicity_and_flow<Proc, T, LPE>(jamp, valid, mh, sub, ev, evc, nevt, goodhel, ngood, sel,
-                                           (volatile HME_LDS double*)&wsel[wib][0]);
+    if constexpr (Select)
+      choose_helicity_and_flow<Proc, T, LPE>(jamp, valid, mh, sub, ev, evc, nevt, goodhel, ngood, sel,
+                                             (volatile HME_LDS double*)&wsel[wib][0]);
+    if constexpr (Channels) {
+      // normalise the event's row and write it
+      wave_lds_sync();
+      double tot = 0.0;
+      for (int d = sub; d < Proc::ndiag; d += LPE) tot += wd[d];
+#pragma unroll
+      for (int off = LPE / 2; off > 0; off >>= 1) tot += __shfl_xor(tot, off, 64);
+      if (ev < nevt)
+        for (int d = sub; d < Proc::ndiag; d += LPE) sel.chan_w[ev * Proc::ndiag + d] = wd[d] / tot;
+    }
   } else if constexpr (kMfmaColour) {
     // every lane runs every pass (the matrix cores take the whole wavefront); a lane past the
     // last good helicity evaluates the last one again and drops its result (each helicity
@@ -283,11 +345,12 @@ template <class Proc>
 __global__ void __launch_bounds__(64) hel_kernel(const double* __restrict__ mom, int nev, ProcParams prm,
                                                  double* __restrict__ out) {
   __shared__ double table[Proc::ntab > 0 ? Proc::ntab : 1];
+  __shared__ double msums[8 * (Proc::nsum > 0 ? Proc::nsum : 1)];
   const int ev = blockIdx.x;
   if (ev >= nev) return;  // uniform per block
   double p[Proc::npar][4];
   load_event<Proc>(mom, ev, p);
-  for (int j = threadIdx.x; j < Proc::nitems; j += blockDim.x) Proc::table_entry(p, prm, j, table);
+  build_event_table<Proc, 64>(p, prm, threadIdx.x, msums, table);
   __syncthreads();
   for (int h = threadIdx.x; h < Proc::nhel; h += blockDim.x) {
     cx<double> jamp[Proc::ncol];
@@ -342,15 +405,30 @@ template <class Proc, class T, int LPE> hipError_t launch_lpe(const LaunchArgs& 
   constexpr int EPB = threads / LPE;  // events per block
   const int64_t blocks = (a.nevt + EPB - 1) / EPB;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  if (a.sel.sel_hel) {
-    if (a.ngood > LPE) return hipErrorInvalidValue;  // the choice needs one helicity per lane
-    me2_kernel<Proc, T, LPE, true><<<dim3((unsigned)blocks), dim3(threads), 0, a.stream>>>(
-        a.mom, a.out, a.nevt, a.goodhel, a.ngood, a.prm, a.norm, a.colour_f32, a.nevt_dev, a.sel);
+  if (a.sel.sel_hel || a.sel.chan_w) {
+    // the choice and the channel weights need one helicity per lane, and one of them per call
+    if (a.ngood > LPE || (a.sel.sel_hel && a.sel.chan_w)) return hipErrorInvalidValue;
+    if (a.sel.sel_hel)
+      me2_kernel<Proc, T, LPE, 1><<<dim3((unsigned)blocks), dim3(threads), 0, a.stream>>>(
+          a.mom, a.out, a.nevt, a.goodhel, a.ngood, a.prm, a.norm, a.colour_f32, a.nevt_dev, a.sel);
+    else
+      me2_kernel<Proc, T, LPE, 2><<<dim3((unsigned)blocks), dim3(threads), 0, a.stream>>>(
+          a.mom, a.out, a.nevt, a.goodhel, a.ngood, a.prm, a.norm, a.colour_f32, a.nevt_dev, a.sel);
   } else {
-    me2_kernel<Proc, T, LPE, false><<<dim3((unsigned)blocks), dim3(threads), 0, a.stream>>>(
+    me2_kernel<Proc, T, LPE, 0><<<dim3((unsigned)blocks), dim3(threads), 0, a.stream>>>(
         a.mom, a.out, a.nevt, a.goodhel, a.ngood, a.prm, a.norm, a.colour_f32, a.nevt_dev, a.sel);
   }
   return hipGetLastError();
+}
+
+// LDS of a block of me2_kernel with LPE lanes per event (the per-event tables and sums of its
+// 256 / LPE events, the channel-weight rows): a lane count whose block would not fit in 64 KiB
+// is not built, and its events take the next larger lane count (lanes past the last good
+// helicity idle).
+template <class Proc, class T, int LPE> constexpr bool lpe_fits() {
+  constexpr size_t per_event = sizeof(T) * (Proc::ntab > 0 ? Proc::ntab : 1) + 64 * (Proc::nsum > 0 ? Proc::nsum : 1) +
+                               8 * Proc::ndiag;
+  return (256 / LPE) * per_event <= (size_t)64 << 10;
 }
 
 template <class Proc, class T> hipError_t launch_me2(const LaunchArgs& a) {
@@ -360,9 +438,15 @@ template <class Proc, class T> hipError_t launch_me2(const LaunchArgs& a) {
     return launch_lpe<Proc, T, 64>(a);
   } else {
     switch (lanes_per_event(a.ngood)) {
-      case 4: return launch_lpe<Proc, T, 4>(a);
-      case 8: return launch_lpe<Proc, T, 8>(a);
-      case 16: return launch_lpe<Proc, T, 16>(a);
+      case 4:
+        if constexpr (lpe_fits<Proc, T, 4>()) return launch_lpe<Proc, T, 4>(a);
+        [[fallthrough]];
+      case 8:
+        if constexpr (lpe_fits<Proc, T, 8>()) return launch_lpe<Proc, T, 8>(a);
+        [[fallthrough]];
+      case 16:
+        if constexpr (lpe_fits<Proc, T, 16>()) return launch_lpe<Proc, T, 16>(a);
+        [[fallthrough]];
       case 32: return launch_lpe<Proc, T, 32>(a);
       default: return launch_lpe<Proc, T, 64>(a);
     }

@@ -39,32 +39,32 @@ HME_FN int64_t sub_batch_events(int64_t nevt, const int64_t* nevt_dev, int64_t e
 }
 
 // Where a piece's partial jamps go: slot `slot` of this lane's (event, helicity) column,
-// written once with a plain store (no other code writes it).
-struct WorkspaceSink {
-  cx<float>* base;
+// written once with a plain store (no other code writes it).  T: the type of the amplitudes
+// (float for HME_MIXED_FAST, double for HME_FP64 and HME_MIXED_PAPER).
+template <class T> struct WorkspaceSink {
+  cx<T>* base;
   int64_t stride;  // entries between consecutive slots (the number of good helicities)
-  HME_FN void put(int slot, cx<float> v) const { base[slot * stride] = v; }
+  HME_FN void put(int slot, cx<T> v) const { base[slot * stride] = v; }
 };
 
-// the per-event table in LDS, built by the event's lanes (as in me2_kernel)
-template <class Proc, int LPE, class S>
-HME_FN void build_table(const double (&p)[Proc::npar][4], const ProcParams& prm, int sub, S* tab) {
-  for (int j = sub; j < Proc::nitems; j += LPE) Proc::table_entry(p, prm, j, tab);
-}
-
-// Pieces are compiled for 2 waves per SIMD (at most 256 VGPRs): the generator's budgets keep
-// them within it or a few registers above, which the compiler then spills; one wave per SIMD
-// with AGPRs costs far more (measured: 1.1-1.3 ms against 0.63-0.8 ms per 8,192 events).
+// Single-precision pieces are compiled for 2 waves per SIMD (at most 256 VGPRs): the generator's
+// budgets keep them within it or a few registers above, which the compiler then spills; one wave
+// per SIMD with AGPRs costs far more for them (measured: 1.1-1.3 ms against 0.63-0.8 ms per
+// 8,192 events).  Double-precision pieces run the same schedule (the same partial-jamp slots)
+// with twice the registers, at one wave per SIMD.
 #ifndef HME_PIECE_WAVES
 #define HME_PIECE_WAVES 2
 #endif
-template <class Proc, class Chunk, int LPE>
-__global__ void __launch_bounds__(256, HME_PIECE_WAVES)
-    chunk_kernel(const double* __restrict__ mom, cx<float>* __restrict__ ws, int64_t nevt,
+template <class T> constexpr int piece_waves() { return sizeof(T) == 4 ? HME_PIECE_WAVES : 1; }
+
+template <class Proc, class Chunk, int LPE, class T>
+__global__ void __launch_bounds__(256, piece_waves<T>())
+    chunk_kernel(const double* __restrict__ mom, cx<T>* __restrict__ ws, int64_t nevt,
                  const int* __restrict__ goodhel, int ngood, ProcParams prm, const int64_t* __restrict__ nevt_dev,
                  int64_t e0) {
   constexpr int EPW = 64 / LPE, EPB = 256 / LPE;
-  __shared__ float table[EPB * Proc::ntab];
+  __shared__ T table[EPB * Proc::ntab];
+  __shared__ double msums[EPB * 8 * Proc::nsum];
   const int lane = threadIdx.x & 63;
   nevt = sub_batch_events(nevt, nevt_dev, e0);
   if ((int64_t)blockIdx.x * EPB >= nevt) return;  // uniform per block
@@ -74,22 +74,23 @@ __global__ void __launch_bounds__(256, HME_PIECE_WAVES)
   const int64_t evc = ev < nevt ? ev : nevt - 1;  // ragged tail: recompute the last event, store nothing
   double p[Proc::npar][4];
   load_event<Proc>(mom, evc, p);
-  float* tab = table + (threadIdx.x / LPE) * Proc::ntab;
-  build_table<Proc, LPE>(p, prm, sub, tab);
+  T* tab = table + (threadIdx.x / LPE) * Proc::ntab;
+  build_event_table<Proc, LPE>(p, prm, sub, msums + (threadIdx.x / LPE) * 8 * Proc::nsum, tab);
   __syncthreads();
   if (ev >= nevt) return;  // no barrier follows
-  cx<float>* w = ws + (size_t)ev * Proc::nslot * ngood;
+  cx<T>* w = ws + (size_t)ev * Proc::nslot * ngood;
   for (int k = sub; k < ngood; k += LPE) {
-    WorkspaceSink sink{w + k, ngood};
-    Chunk::template amplitudes<float>(prm, (unsigned)goodhel[k], (tab_of<float>)tab, sink);
+    WorkspaceSink<T> sink{w + k, ngood};
+    Chunk::template amplitudes<T>(prm, (unsigned)goodhel[k], (tab_of<T>)tab, sink);
   }
 }
 
 // colour sum of the workspace jamps; per_hel = 0: out[ev] = norm * sum over helicities,
 // per_hel = 1: out[ev * ngood + k] = colour sum of good helicity k (unnormalised)
-template <class Proc, int LPE>
+// S: the workspace type, C: the type of the colour sum (VALU)
+template <class Proc, int LPE, class S, class C>
 __global__ void __launch_bounds__(256)
-    colour_kernel(const cx<float>* __restrict__ ws, double* __restrict__ out, int64_t nevt, int ngood,
+    colour_kernel(const cx<S>* __restrict__ ws, double* __restrict__ out, int64_t nevt, int ngood,
                   double norm, int per_hel, const int64_t* __restrict__ nevt_dev, int64_t e0) {
   constexpr int EPW = 64 / LPE, EPB = 256 / LPE;
   const int lane = threadIdx.x & 63;
@@ -99,12 +100,12 @@ __global__ void __launch_bounds__(256)
   const int64_t ev = ((int64_t)blockIdx.x * 4 + wib) * EPW + lane / LPE;
   const int sub = lane % LPE;
   const int64_t evc = ev < nevt ? ev : nevt - 1;
-  const cx<float>* w = ws + (size_t)evc * Proc::nslot * ngood;
+  const cx<S>* w = ws + (size_t)evc * Proc::nslot * ngood;
   double acc = 0.0;
   for (int k = sub; k < ngood; k += LPE) {
-    cx<float> jamp[Proc::ncol];
-    Proc::template gather<float, float>(w + k, ngood, jamp);
-    const double v = (double)Proc::template colour_sum<float>(jamp);
+    cx<C> jamp[Proc::ncol];
+    Proc::template gather<C, S>(w + k, ngood, jamp);
+    const double v = (double)Proc::template colour_sum<C>(jamp);
     if (per_hel && ev < nevt) out[(size_t)ev * ngood + k] = v;
     acc += v;
   }
@@ -120,9 +121,9 @@ __global__ void __launch_bounds__(256)
 // first event.  (Measured: with the choice this kernel takes about three times its plain
 // time, most of that already with the helicity part alone; a separate kernel for the flow
 // weights, gathering the jamps again, was slower.)
-template <class Proc, bool Select = false>
+template <class Proc, bool Select, class S>
 __global__ void __launch_bounds__(256)
-    colour_mfma_kernel(const cx<float>* __restrict__ ws, double* __restrict__ out, int64_t nevt, int ngood,
+    colour_mfma_kernel(const cx<S>* __restrict__ ws, double* __restrict__ out, int64_t nevt, int ngood,
                        double norm, int per_hel, const int64_t* __restrict__ nevt_dev, int64_t e0,
                        const int* __restrict__ goodhel, SelectArgs sel) {
   constexpr int NCOL = Proc::ncol;
@@ -138,7 +139,7 @@ __global__ void __launch_bounds__(256)
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t ev = (int64_t)blockIdx.x * 4 + wib;
   if (ev >= nevt) return;  // wave-uniform; no barrier follows
-  const cx<float>* w = ws + (size_t)ev * Proc::nslot * ngood;
+  const cx<S>* w = ws + (size_t)ev * Proc::nslot * ngood;
   double acc = 0.0;
   [[maybe_unused]] double mpass[Select ? NPASS : 1];
   if constexpr (Select) {
@@ -149,7 +150,7 @@ __global__ void __launch_bounds__(256)
     const int k = g + lane;
     const bool valid = k < ngood;
     cx<float> jamp[NCOL];
-    Proc::template gather<float, float>(w + (valid ? k : 0), ngood, jamp);
+    Proc::template gather<float, S>(w + (valid ? k : 0), ngood, jamp);
     if (!valid) {
 #pragma unroll
       for (int f = 0; f < NCOL; ++f) jamp[f] = {0.f, 0.f};
@@ -205,7 +206,7 @@ __global__ void __launch_bounds__(256)
 
 struct ChunkArgs {
   const double* mom;  // momenta of the sub-batch's first event
-  cx<float>* ws;      // workspace, nevt * nslot * ngood entries
+  void* ws;           // workspace, nevt * nslot * ngood entries of cx<float> (f64 = 0) or cx<double>
   int64_t nevt;       // events in the sub-batch
   const int* goodhel;
   int ngood;
@@ -213,6 +214,7 @@ struct ChunkArgs {
   hipStream_t stream;
   const int64_t* nevt_dev;  // if set: the batch's event count (device), of which this sub-batch
   int64_t e0;               // starts at event e0
+  int f64 = 0;              // double-precision amplitudes and workspace
 };
 
 template <class Proc> constexpr int chunk_lpe() { return Proc::nhel >= 64 ? 64 : 32; }
@@ -221,14 +223,19 @@ template <class Proc, class Chunk> hipError_t launch_chunk(const ChunkArgs& a) {
   constexpr int LPE = chunk_lpe<Proc>(), EPB = 256 / LPE;
   const int64_t blocks = (a.nevt + EPB - 1) / EPB;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  chunk_kernel<Proc, Chunk, LPE><<<dim3((unsigned)blocks), dim3(256), 0, a.stream>>>(
-      a.mom, a.ws, a.nevt, a.goodhel, a.ngood, a.prm, a.nevt_dev, a.e0);
+  if (a.f64)
+    chunk_kernel<Proc, Chunk, LPE, double><<<dim3((unsigned)blocks), dim3(256), 0, a.stream>>>(
+        a.mom, static_cast<cx<double>*>(a.ws), a.nevt, a.goodhel, a.ngood, a.prm, a.nevt_dev, a.e0);
+  else
+    chunk_kernel<Proc, Chunk, LPE, float><<<dim3((unsigned)blocks), dim3(256), 0, a.stream>>>(
+        a.mom, static_cast<cx<float>*>(a.ws), a.nevt, a.goodhel, a.ngood, a.prm, a.nevt_dev, a.e0);
   return hipGetLastError();
 }
 
-// colour sum of the workspace: on the matrix cores (mfma != 0) or on the vector ALUs
-template <class Proc>
-hipError_t launch_colour(const cx<float>* ws, double* out, int64_t nevt, int ngood, double norm, int per_hel,
+// colour sum of the workspace (cx<S>): on the matrix cores (mfma != 0, single precision) or on
+// the vector ALUs in the type C
+template <class Proc, class S, class C>
+hipError_t launch_colour(const cx<S>* ws, double* out, int64_t nevt, int ngood, double norm, int per_hel,
                          const int64_t* nevt_dev, int64_t e0, hipStream_t s, int mfma, const int* goodhel = nullptr,
                          const SelectArgs& sel = SelectArgs{}) {
   constexpr int LPE = chunk_lpe<Proc>(), EPB = 256 / LPE;
@@ -238,14 +245,14 @@ hipError_t launch_colour(const cx<float>* ws, double* out, int64_t nevt, int ngo
   if (mfma) {
     static_assert(LPE == 64, "the matrix-core colour sum takes one event per wavefront");
     if (sel.sel_hel)
-      colour_mfma_kernel<Proc, true><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(ws, out, nevt, ngood, norm, per_hel,
-                                                                                   nevt_dev, e0, goodhel, sel);
+      colour_mfma_kernel<Proc, true, S><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(ws, out, nevt, ngood, norm,
+                                                                                      per_hel, nevt_dev, e0, goodhel, sel);
     else
-      colour_mfma_kernel<Proc, false><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(ws, out, nevt, ngood, norm,
-                                                                                    per_hel, nevt_dev, e0, goodhel, sel);
+      colour_mfma_kernel<Proc, false, S><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(ws, out, nevt, ngood, norm,
+                                                                                       per_hel, nevt_dev, e0, goodhel, sel);
   } else {
-    colour_kernel<Proc, LPE><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(ws, out, nevt, ngood, norm, per_hel,
-                                                                           nevt_dev, e0);
+    colour_kernel<Proc, LPE, S, C><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(ws, out, nevt, ngood, norm, per_hel,
+                                                                                 nevt_dev, e0);
   }
   return hipGetLastError();
 }

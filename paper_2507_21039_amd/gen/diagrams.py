@@ -144,6 +144,27 @@ def diagrams_dy(gluons):
     return out
 
 
+def tree_key(t) -> str:
+    """Name of a gluon tree independent of enumeration order: g<particle>, (x,y) for a three-gluon
+    vertex, [x,y,z] for a four-gluon vertex (children's names sorted); W for the electroweak boson."""
+    if t == EW:
+        return "W"
+    if t[0] == "L":
+        return f"g{t[1]}"
+    ks = sorted(tree_key(x) for x in t[1:] if isinstance(x, tuple))
+    return ("(" if t[0] == "3" else "[") + ",".join(ks) + (")" if t[0] == "3" else "]")
+
+
+def diagram_keys(ngluon_final: int, family: str = "tt") -> list:
+    """Names of the diagrams in the generator's order (the columns of the channel weights): the
+    elements of the quark line from its barred end (the top, or the ubar), joined by ';'."""
+    if family == "dy":
+        ds = diagrams_dy(tuple(range(4, 4 + ngluon_final)))
+    else:
+        ds = diagrams(tuple([0, 1] + list(range(4, 4 + ngluon_final))))
+    return [";".join(tree_key(t) for t in d) for d in ds]
+
+
 # ------------------------------------------------------------------ colour of wavefunctions
 
 

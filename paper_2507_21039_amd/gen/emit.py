@@ -148,7 +148,7 @@ def prefetch_units(lines, enable, kits: bool = True):
 
 
 def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chunks: int = 0,
-             file_stem: str = "", jbudget: int = 32, order=None):
+             file_stem: str = "", jbudget: int = 32, order=None, recycle: bool = False):
     """Emit the process header.
 
     budget: number of off-shell wavefunctions kept live at once, for the double and the
@@ -167,6 +167,9 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
     the jamps of the flows it touches; the main header then holds the table and the colour
     sum only.  Used where one straight-line kernel would be too large to compile and to keep
     its jamps in registers.  jbudget: flows a piece accumulates in registers at once.
+    recycle: helicity recycling.  A wavefunction built from two external states takes only 4
+    values per event (one per helicity pair), so the event's lanes compute those once into the
+    per-event table and every lane reads the one of its helicities instead of computing it.
     """
     if isinstance(budget, int):
         budget = (budget, budget)
@@ -210,6 +213,34 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
 
     from .diagrams import schedule, schedule_cached
     node_cost = {kind: FLOPS[NODE_FLOPS[kind]] for kind in NODE_FLOPS}
+
+    # recycled wavefunctions: two external arguments (gluons, quark ends), 4 helicity pairs each
+    rec = {}  # node key -> index
+    if recycle:
+        for key, n in g.nodes.items():
+            if key[0] != "E" and all(a[0] == "E" and g.nodes[a].kind in ("ext_v", "ext_o", "ext_i")
+                                     for a in n.args) and len(n.args) == 2:
+                rec[key] = len(rec)
+    # recycled wavefunctions: kind (0 three-gluon current, 1 spinor current, 2 barred spinor
+    # current, 3 quark pair), the particles of the two external arguments, and the offset of
+    # the vertex kit (kinds 0-2, in the vertex-kit region) or the index of the denominator (3);
+    # their kits are registered here, before the schedules
+    rec_info = []
+    for key in rec:
+        n = g.nodes[key]
+        pa, pb = (x[1] for x in n.args)
+        if n.kind == "vvv":
+            ma, mb = g.nodes[n.args[0]].mask, g.nodes[n.args[1]].mask
+            vkit("vvv", ma, mb, n.mask)
+            kk = vkidx[("vvv", ma, mb, n.mask, 1)]
+        elif n.kind in ("psi", "psibar"):
+            sg = 1 if n.kind == "psi" else -1
+            vkit("psi", n.mask, sign=sg)
+            kk = vkidx[("psi", n.mask, 0, 0, sg)]
+        else:
+            den(n.mask, False)
+            kk = didx[n.mask][0]
+        rec_info.append(({"vvv": 0, "psi": 1, "psibar": 2, "qq": 3}[n.kind], pa, pb, kk))
 
     def pick_order(spec):
         if spec is None:
@@ -278,11 +309,18 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
         def arg(key, pre):
             if key[0] == "E":
                 return ext_expr(key, pre)
+            if key in rec:  # the lane's helicity pair of a recycled wavefunction
+                a, b = (k[1] for k in g.nodes[key].args)
+                typ = "sp4" if g.nodes[key].kind in ("psi", "psibar") else "vw4"
+                nm = f"r{rec[key]}_{len(pre)}"
+                pre.append(f"    const {typ}<T> {nm} = recycled_{typ}<T>(tab + ROFF + {32 * rec[key]}, "
+                           f"(hel({a}) > 0 ? 16 : 0) + (hel({b}) > 0 ? 8 : 0));")
+                return nm
             return live[key]
 
         def need(key, pinned):
             nonlocal flops_exec, flops_dag
-            if key[0] == "E" or key in live:
+            if key[0] == "E" or key in live or key in rec:
                 return
             n = g.nodes[key]
             for a in n.args:
@@ -371,6 +409,8 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
             lines.append(f"  {{  // diagram {amp.diagram + 1}")
             lines.extend(pre)
             lines.append(f"    const cx<T> a = {call};")
+            if not jbudget:
+                lines.append(f"    obs.term({amp.diagram}, a);")
             if jbudget:
                 mine = set(amp.colour.terms)
                 for w, c in sorted(amp.colour.terms.items(), key=lambda x: widx[x[0]]):
@@ -439,9 +479,12 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
         koff["W"] = off
         off += 8 * EW_ITEMS
     voff = off
-    ntab = off + vk_off[0]
+    roff = off + vk_off[0]  # recycled wavefunctions: 4 helicity pairs x 8 reals each
+    ntab = roff + 32 * len(rec)
+
     def finish(lines, pf):
-        lines = [l.replace("DOFF", str(4 * nq)).replace("VOFF", str(voff)) for l in lines]
+        lines = [l.replace("DOFF", str(4 * nq)).replace("VOFF", str(voff)).replace("ROFF", str(roff))
+                 for l in lines]
         for k in koff:
             lines = [l.replace(f"KOFF{k}", str(koff[k])) for l in lines]
         return "\n".join(prefetch_units(lines, bool(pf), kits=(pf != "table")))
@@ -492,6 +535,9 @@ struct {name}_c{c} {{
     kind_code = {"ext_v": 0, "ext_o": 3 if dy else 1, "ext_i": 4 if dy else 2}
     kits = [(koff[k], kind_code[g.nodes[("E", k)].kind], k) if k in koff else (0, -1, k) for k in range(npar)]
     flops_table = DEN_FLOPS * nd + 4 * nq + 40 * len(ext)
+    flops_table += 4 * sum(FLOPS[NODE_FLOPS[g.nodes[k].kind]] for k in rec)  # each helicity pair once
+    rec_rows = [(kind, pa, pb, koff[pa], koff[pb], kk) for kind, pa, pb, kk in rec_info]
+    nrec = len(rec)
     qmass = "0.0" if dy else "prm.mT"  # mass of the quark line
     row_end = 1 if dy else TOP  # particle of the barred spinor at the quark line's end
     fmass = "0.0" if dy else "k < 2 ? 0.0 : prm.mT"  # masses of the external fermions
@@ -520,6 +566,23 @@ struct {name}_c{c} {{
 
     nvk = len(vk_list)
     nitems = nq + nd + npar + nvk + (EW_ITEMS if dy else 0)
+    # the momentum sums the table reads, one per internal line: a mask and its complement
+    # are the two sides of one line, and the sum is always taken over the side without the
+    # barred spinor's particle (a mask holding it reads that sum negated)
+    full = (1 << npar) - 1
+    sum_masks = []
+
+    def slot(m):
+        neg = bool(m >> row_end & 1)
+        c = (~m & full) if neg else m
+        if c not in sum_masks:
+            sum_masks.append(c)
+        return 2 * sum_masks.index(c) + int(neg)
+
+    qcode = [slot(m) for m in qmask]
+    dcode = [slot(m) for m in dmask]
+    vk_c = [[slot(x[1 + i]) if (i == 0 or x[0] != "psi") else 0 for x in vk_list] for i in range(3)]
+    nsum = len(sum_masks)
     flops_table += sum(VK_FLOPS[x[0]] for x in vk_list)
     vk_kind_code = {"vvv": 0, "psi": 1, "amp3": 2}
     numer_list = ", ".join(str(N[i][j]) for i in range(ncol) for j in range(ncol))
@@ -546,25 +609,26 @@ struct {name}_c{c} {{
         amp_section = f"""  static constexpr int nchunk = 0, nslot = 0;  // one kernel evaluates every amplitude term
 
   // jamps of one helicity (jamp[] must be zeroed by the caller); the schedule depends on the
-  // arithmetic type (budget {budget[0]} / prefetch "{prefetch[0]}" for double, {budget[1]} / "{prefetch[1]}" for float)
-  template <class T>
+  // arithmetic type (budget {budget[0]} / prefetch "{prefetch[0]}" for double, {budget[1]} / "{prefetch[1]}" for float).
+  // obs.term(d, a) sees every amplitude term a of diagram d (the default observer does nothing).
+  template <class T, class Obs = NoObserver>
   HME_FN static void amplitudes(const double (&p)[{npar}][4], const ProcParams& prm, unsigned h,
-                                tab_of<T> tab, cx<T> (&jamp)[{ncol}]) {{
+                                tab_of<T> tab, cx<T> (&jamp)[{ncol}], Obs obs = Obs{{}}) {{
     if constexpr (sizeof(T) == 8)
-      amplitudes_d<T>(prm, h, tab, jamp);
+      amplitudes_d<T>(prm, h, tab, jamp, obs);
     else
-      amplitudes_f<T>(prm, h, tab, jamp);
+      amplitudes_f<T>(prm, h, tab, jamp, obs);
   }}
 
-  template <class T>
-  HME_FN static void amplitudes_d(const ProcParams& prm, unsigned h, tab_of<T> tab, cx<T> (&jamp)[{ncol}]) {{
+  template <class T, class Obs>
+  HME_FN static void amplitudes_d(const ProcParams& prm, unsigned h, tab_of<T> tab, cx<T> (&jamp)[{ncol}], Obs& obs) {{
     auto hel = [h](int k) {{ return (h >> ({npar - 1} - k) & 1u) ? 1 : -1; }};
     const T mT = T(prm.mT);
 {body_d}
   }}
 
-  template <class T>
-  HME_FN static void amplitudes_f(const ProcParams& prm, unsigned h, tab_of<T> tab, cx<T> (&jamp)[{ncol}]) {{
+  template <class T, class Obs>
+  HME_FN static void amplitudes_f(const ProcParams& prm, unsigned h, tab_of<T> tab, cx<T> (&jamp)[{ncol}], Obs& obs) {{
     auto hel = [h](int k) {{ return (h >> ({npar - 1} - k) & 1u) ? 1 : -1; }};
     const T mT = T(prm.mT);
 {body_f}
@@ -598,10 +662,11 @@ struct {name} {{
   // negated for barred currents), {nd} propagator denominators 1/(Q^2 - m^2), and for every
   // external particle a kit holding its state for either helicity (gluon: the five nonzero real
   // parts of eps or conj(eps); fermion: the four complex components of ubar or v).
+  // Momentum sums are read through codes 2 s + n: sum s of sum_mask (n = 1: negated).
   static constexpr int nq = {nq}, nd = {nd}, nitems = {nitems}, ntab = {ntab};
-  static constexpr unsigned qmask[{max(nq, 1)}] = {{{", ".join(map(str, qmask))}}};
+  static constexpr short qcode[{max(nq, 1)}] = {{{", ".join(map(str, qcode)) or "0"}}};
   static constexpr int qsign[{max(nq, 1)}] = {{{", ".join(map(str, qsign))}}};
-  static constexpr unsigned dmask[{max(nd, 1)}] = {{{", ".join(map(str, dmask))}}};
+  static constexpr short dcode[{max(nd, 1)}] = {{{", ".join(map(str, dcode)) or "0"}}};
   static constexpr int dmassive[{max(nd, 1)}] = {{{", ".join(map(str, dmassive))}}};
   static constexpr int kit_off[{npar}] = {{{", ".join(str(k[0]) for k in kits)}}};
   static constexpr int kit_kind[{npar}] = {{{", ".join(str(k[1]) for k in kits)}}};  // 0 vector, 1 ubar, 2 v, 3 vbar, 4 u, -1 none
@@ -612,38 +677,98 @@ struct {name} {{
   // kind 2 three-gluon amplitude (Qa - Qb, Qb - Qc, Qc - Qa)
   static constexpr int nvk = {nvk}, voff = {voff};
   static constexpr int vk_kind[{max(nvk, 1)}] = {{{", ".join(str(vk_kind_code[x[0]]) for x in vk_list) or "0"}}};
-  static constexpr unsigned vk_m0[{max(nvk, 1)}] = {{{", ".join(str(x[1]) for x in vk_list) or "0"}}};
-  static constexpr unsigned vk_m1[{max(nvk, 1)}] = {{{", ".join(str(x[2]) for x in vk_list) or "0"}}};
-  static constexpr unsigned vk_m2[{max(nvk, 1)}] = {{{", ".join(str(x[3]) for x in vk_list) or "0"}}};
+  static constexpr short vk_c0[{max(nvk, 1)}] = {{{", ".join(map(str, vk_c[0])) or "0"}}};
+  static constexpr short vk_c1[{max(nvk, 1)}] = {{{", ".join(map(str, vk_c[1])) or "0"}}};
+  static constexpr short vk_c2[{max(nvk, 1)}] = {{{", ".join(map(str, vk_c[2])) or "0"}}};
   static constexpr int vk_sign[{max(nvk, 1)}] = {{{", ".join(str(x[4]) for x in vk_list) or "1"}}};
   static constexpr int vk_off[{max(nvk, 1)}] = {{{", ".join(str(x[5]) for x in vk_list) or "0"}}};
 
-  // sum of the incoming momenta of the particles in mask m (outgoing ones negated), each
-  // component as a compensated sum (exact for up to {npar} terms); k: a factor applied to every term.
-  // An internal line has two sides; momenta given in double precision conserve momentum only up
-  // to rounding, so the two sums differ slightly, by 1e-12 relative in Q^2 of an almost
-  // on-shell line.  Every line therefore takes the sum over the side without particle {row_end}
-  // (the barred spinor of the quark line), whichever current it is built in: a mask holding
-  // that particle is replaced by its complement, negated.
-  HME_FN static void mask_sum(const double (&p)[{npar}][4], unsigned m, dd* Q, double k = 1.0) {{
-    if (m >> {row_end} & 1u) {{
-      m = ~m & {(1 << npar) - 1}u;
-      k = -k;
+  // helicity recycling: {nrec} wavefunctions built from two external states, stored for each
+  // helicity pair after the vertex kits (8 reals per pair: the 4 complex components); kind 0
+  // three-gluon current, 1 spinor current, 2 barred spinor current, 3 quark pair; particles and
+  // kit offsets of the two arguments; vertex-kit offset (kinds 0-2) or denominator index (3)
+  static constexpr int nrec = {nrec}, roff = {roff};
+  static constexpr int rec_kind[{max(nrec, 1)}] = {{{", ".join(str(x[0]) for x in rec_rows) or "0"}}};
+  static constexpr int rec_pa[{max(nrec, 1)}] = {{{", ".join(str(x[1]) for x in rec_rows) or "0"}}};
+  static constexpr int rec_pb[{max(nrec, 1)}] = {{{", ".join(str(x[2]) for x in rec_rows) or "0"}}};
+  static constexpr int rec_oa[{max(nrec, 1)}] = {{{", ".join(str(x[3]) for x in rec_rows) or "0"}}};
+  static constexpr int rec_ob[{max(nrec, 1)}] = {{{", ".join(str(x[4]) for x in rec_rows) or "0"}}};
+  static constexpr int rec_k[{max(nrec, 1)}] = {{{", ".join(str(x[5]) for x in rec_rows) or "0"}}};
+
+  // item i < 4 nrec: recycled wavefunction i / 4 for the helicity pair i % 4 (bit 1: first
+  // argument +1, bit 0: second +1), from the kits in t, written into w (the same table)
+  template <class S> HME_FN static void recycled_entry(int i, tab_of<S> t, S* w) {{
+    using T = S;
+    const int r = i >> 2, ha = (i & 2) ? 1 : -1, hb = (i & 1) ? 1 : -1;
+    const int na = rec_pa[r] < 2 ? -1 : 1, nb = rec_pb[r] < 2 ? -1 : 1;
+    S* o = w + roff + 32 * r + 8 * (i & 3);
+    const auto tab = t;
+    switch (rec_kind[r]) {{
+      case 0:
+        store_wf(vvv_vec_k<T>(vxxxxx_kit<T>(tab + rec_oa[r], ha, na), vxxxxx_kit<T>(tab + rec_ob[r], hb, nb),
+                              load_kit<T, 12>(tab + voff + rec_k[r])), o);
+        break;
+      case 1:
+        store_wf(ffv_psi_k<T>(ixxxxx_kit<T>(tab + rec_oa[r], ha), vxxxxx_kit<T>(tab + rec_ob[r], hb, nb),
+                              load_kit<T, 5>(tab + voff + rec_k[r])), o);
+        break;
+      case 2:
+        store_wf(ffv_psibar_k<T>(oxxxxx_kit<T>(tab + rec_oa[r], ha), vxxxxx_kit<T>(tab + rec_ob[r], hb, nb),
+                                 load_kit<T, 5>(tab + voff + rec_k[r])), o);
+        break;
+      default:
+        store_wf(ffv_vec<T>(oxxxxx_kit<T>(tab + rec_oa[r], ha), ixxxxx_kit<T>(tab + rec_ob[r], hb),
+                            dv<T>(tab, {4 * nq} + rec_k[r])), o);
+        break;
     }}
-    Q[0] = Q[1] = Q[2] = Q[3] = dd{{0.0, 0.0}};
+  }}
+
+  // Sums of incoming momenta (outgoing ones negated) over the masks the table needs, each
+  // component as an unevaluated sum hi + lo (two-sum chain: as accurate as a sum in twice the
+  // precision).  An internal line has two sides; momenta given in double precision conserve
+  // momentum only up to rounding, so the two sums differ slightly, by 1e-12 relative in Q^2 of
+  // an almost on-shell line.  Every line therefore takes the sum over the side without particle
+  // {row_end} (the barred spinor of the quark line), whichever current it is built in.
+  static constexpr int nsum = {nsum};
+  static constexpr unsigned sum_mask[{max(nsum, 1)}] = {{{", ".join(map(str, sum_masks)) or "0"}}};
+
+  // sum i (i < nsum) into o[8 i .. 8 i + 7] as (hi, lo) per component; the lanes of an event
+  // compute disjoint sums before any table item reads them
+  HME_FN static void momentum_sum(const double (&p)[{npar}][4], int i, double* o) {{
+    _Pragma("clang fp contract(off)")
+    const unsigned m = sum_mask[i];
+    double hi[4] = {{0.0, 0.0, 0.0, 0.0}}, lo[4] = {{0.0, 0.0, 0.0, 0.0}};
 #pragma unroll
     for (int j = 0; j < {npar}; ++j) {{
-      const double s = (m >> j & 1u) ? (j < 2 ? k : -k) : 0.0;
+      const double s = (m >> j & 1u) ? (j < 2 ? 1.0 : -1.0) : 0.0;
 #pragma unroll
-      for (int mu = 0; mu < 4; ++mu) Q[mu] = dd_add(Q[mu], two_prod(s, p[j][mu]));
+      for (int mu = 0; mu < 4; ++mu) {{
+        const dd t = two_sum(hi[mu], s * p[j][mu]);  // s p is exact
+        hi[mu] = t.hi;
+        lo[mu] += t.lo;
+      }}
     }}
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {{
+      const dd t = quick_two_sum(hi[mu], lo[mu]);
+      o[8 * i + 2 * mu] = t.hi;
+      o[8 * i + 2 * mu + 1] = t.lo;
+    }}
+  }}
+
+  // the momentum sum of code c (2 s + n) from the sums in `sums`
+  HME_FN static void mask_sum(const double* sums, int c, dd* Q) {{
+    const double* q = sums + 8 * (c >> 1);
+    const double g = (c & 1) ? -1.0 : 1.0;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) Q[mu] = dd{{g * q[2 * mu], g * q[2 * mu + 1]}};
   }}
 
   // the quantities below are formed in compensated arithmetic and rounded once
   // (differences of momentum sums, and Q^2 - m^2 of almost on-shell propagators)
-  template <class S> HME_FN static void vertex_kit(const double (&p)[{npar}][4], const ProcParams& prm, int v, S* o) {{
+  template <class S> HME_FN static void vertex_kit(const double* sums, const ProcParams& prm, int v, S* o) {{
     dd A[4], B[4], C[4];
-    mask_sum(p, vk_m0[v], A);
+    mask_sum(sums, vk_c0[v], A);
     if (vk_kind[v] == 1) {{
       const double den = 1.0 / dd_minkowski_sq(A, {qmass});
       const double ds = den * vk_sign[v];
@@ -654,8 +779,8 @@ struct {name} {{
       o[4] = S(den * {qmass});
       return;
     }}
-    mask_sum(p, vk_m1[v], B);
-    mask_sum(p, vk_m2[v], C);
+    mask_sum(sums, vk_c1[v], B);
+    mask_sum(sums, vk_c2[v], C);
     if (vk_kind[v] == 0) {{
       const double den = 1.0 / dd_minkowski_sq(C, 0.0);
 #pragma unroll
@@ -674,12 +799,14 @@ struct {name} {{
     }}
   }}
 
-  // item j of the table (j < nitems); the lanes of an event compute disjoint items
+  // item j of the table (j < nitems), from the event and its momentum sums; the lanes of an
+  // event compute disjoint items
   template <class S>
-  HME_FN static void table_entry(const double (&p)[{npar}][4], const ProcParams& prm, int j, S* tab) {{
+  HME_FN static void table_entry(const double (&p)[{npar}][4], const ProcParams& prm, int j, const double* sums,
+                                 S* tab) {{
 {ew_items}    if (j >= nq + nd + {npar}) {{
       const int v = j - nq - nd - {npar};
-      vertex_kit(p, prm, v, tab + voff + vk_off[v]);
+      vertex_kit(sums, prm, v, tab + voff + vk_off[v]);
       return;
     }}
     if (j >= nq + nd) {{
@@ -694,7 +821,7 @@ struct {name} {{
     }}
     const bool isq = j < nq;
     dd Q[4];
-    mask_sum(p, isq ? qmask[j] : dmask[j - nq], Q);
+    mask_sum(sums, isq ? qcode[j] : dcode[j - nq], Q);
     if (isq) {{
       const double sg = qsign[j];
 #pragma unroll
@@ -767,12 +894,15 @@ struct {name} {{
   static constexpr double flops_per_hel = {flops};
   static constexpr double flops_per_event = 20.0;  // s, 1/s, Z propagator denominator
 
-  static constexpr int nq = 0, nd = 0, nitems = 0, ntab = 0;  // no per-event table
-  template <class S> HME_FN static void table_entry(const double (&)[4][4], const ProcParams&, int, S*) {{}}
+  static constexpr int nq = 0, nd = 0, nitems = 0, ntab = 0, nsum = 0, nrec = 0;  // no per-event table
+  template <class S> HME_FN static void recycled_entry(int, tab_of<S>, S*) {{}}
+  HME_FN static void momentum_sum(const double (&)[4][4], int, double*) {{}}
+  template <class S>
+  HME_FN static void table_entry(const double (&)[4][4], const ProcParams&, int, const double*, S*) {{}}
 
-  template <class T>
+  template <class T, class Obs = NoObserver>
   HME_FN static void amplitudes(const double (&p)[4][4], const ProcParams& prm, unsigned h,
-                                tab_of<T>, cx<T> (&jamp)[1]) {{
+                                tab_of<T>, cx<T> (&jamp)[1], Obs obs = Obs{{}}) {{
     auto hel = [h](int k) {{ return (h >> (3 - k) & 1u) ? 1 : -1; }};
     const sp4<T> w0 = cast<T>(oxxxxx(p[0], 0.0, hel(0), -1));  // vbar(e+)
     const sp4<T> w1 = cast<T>(ixxxxx(p[1], 0.0, hel(1), +1));  // u(e-)

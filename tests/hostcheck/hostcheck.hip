@@ -25,7 +25,10 @@ void run(const hme::ProcParams& prm, double alpha_s, int64_t nevt, const double*
     for (int k = 0; k < Proc::npar; ++k)
       for (int mu = 0; mu < 4; ++mu) p[k][mu] = mom[(e * Proc::npar + k) * 4 + mu];
     T tab[Proc::ntab > 0 ? Proc::ntab : 1];
-    for (int j = 0; j < Proc::nitems; ++j) Proc::table_entry(p, prm, j, tab);
+    double sums[8 * (Proc::nsum > 0 ? Proc::nsum : 1)];
+    for (int i = 0; i < Proc::nsum; ++i) Proc::momentum_sum(p, i, sums);
+    for (int j = 0; j < Proc::nitems; ++j) Proc::table_entry(p, prm, j, sums, tab);
+    for (int i = 0; i < 4 * Proc::nrec; ++i) Proc::template recycled_entry<T>(i, (hme::tab_of<T>)tab, tab);
     double acc = 0;
     for (int h = 0; h < Proc::nhel; ++h) {
       hme::cx<T> jamp[Proc::ncol];
@@ -44,13 +47,60 @@ void jamps(const hme::ProcParams& prm, const double* mom, int h, double* out) {
   for (int k = 0; k < Proc::npar; ++k)
     for (int mu = 0; mu < 4; ++mu) p[k][mu] = mom[k * 4 + mu];
   double tab[Proc::ntab > 0 ? Proc::ntab : 1];
-  for (int j = 0; j < Proc::nitems; ++j) Proc::table_entry(p, prm, j, tab);
+  double sums[8 * (Proc::nsum > 0 ? Proc::nsum : 1)];
+  for (int i = 0; i < Proc::nsum; ++i) Proc::momentum_sum(p, i, sums);
+  for (int j = 0; j < Proc::nitems; ++j) Proc::table_entry(p, prm, j, sums, tab);
+  for (int i = 0; i < 4 * Proc::nrec; ++i) Proc::template recycled_entry<double>(i, (hme::tab_ptr)tab, tab);
   hme::cx<double> jamp[Proc::ncol];
   for (auto& j : jamp) j = {0.0, 0.0};
   Proc::template amplitudes<double>(p, prm, (unsigned)h, (hme::tab_ptr)tab, jamp);
   for (int c = 0; c < Proc::ncol; ++c) out[2 * c] = jamp[c].r, out[2 * c + 1] = jamp[c].i;
 }
+struct HostChannels {
+  double* w;
+  template <class C> void term(int d, const C& a) const { w[d] += (double)a.r * a.r + (double)a.i * a.i; }
+};
+
+// per-diagram sum over all helicities and terms of |a|^2 (unnormalised), FP64
+template <class Proc>
+void channels(const hme::ProcParams& prm, int64_t nevt, const double* mom, double* out) {
+  for (int64_t e = 0; e < nevt; ++e) {
+    double p[Proc::npar][4];
+    for (int k = 0; k < Proc::npar; ++k)
+      for (int mu = 0; mu < 4; ++mu) p[k][mu] = mom[(e * Proc::npar + k) * 4 + mu];
+    double tab[Proc::ntab > 0 ? Proc::ntab : 1];
+    double sums[8 * (Proc::nsum > 0 ? Proc::nsum : 1)];
+    for (int i = 0; i < Proc::nsum; ++i) Proc::momentum_sum(p, i, sums);
+    for (int j = 0; j < Proc::nitems; ++j) Proc::table_entry(p, prm, j, sums, tab);
+    for (int i = 0; i < 4 * Proc::nrec; ++i) Proc::template recycled_entry<double>(i, (hme::tab_ptr)tab, tab);
+    double* w = out + e * Proc::ndiag;
+    for (int d = 0; d < Proc::ndiag; ++d) w[d] = 0;
+    for (int h = 0; h < Proc::nhel; ++h) {
+      hme::cx<double> jamp[Proc::ncol];
+      for (auto& j : jamp) j = {0.0, 0.0};
+      Proc::template amplitudes<double>(p, prm, (unsigned)h, (hme::tab_ptr)tab, jamp, HostChannels{w});
+    }
+  }
+}
 }  // namespace
+
+extern "C" int hostcheck_channels(int process, const double* card, int64_t nevt, const double* mom, double* out) {
+  hme_sm_card c{card[0], card[1], card[2], card[3], card[4], card[5]};
+  hme::ProcParams prm;
+  std::string why;
+  if (!hme::derive_params(c, prm, why)) return -1;
+  switch (process) {
+    case 1: channels<hme::P_ggtt>(prm, nevt, mom, out); break;
+    case 2: channels<hme::P_ggttg>(prm, nevt, mom, out); break;
+    case 3: channels<hme::P_ggttgg>(prm, nevt, mom, out); break;
+    case 5: channels<hme::P_uuee>(prm, nevt, mom, out); break;
+    case 6: channels<hme::P_uueeg>(prm, nevt, mom, out); break;
+    case 7: channels<hme::P_uueegg>(prm, nevt, mom, out); break;
+    case 8: channels<hme::P_uueeggg>(prm, nevt, mom, out); break;
+    default: return -1;
+  }
+  return 0;
+}
 
 // the colour-flow amplitudes (jamps, FP64) of one event and one helicity
 extern "C" int hostcheck_jamps(int process, const double* card, const double* mom, int h, double* out) {

@@ -50,7 +50,10 @@ void run(const hme::ProcParams& prm, double alpha_s, int64_t nevt, const double*
     for (int k = 0; k < P::npar; ++k)
       for (int mu = 0; mu < 4; ++mu) p[k][mu] = mom[(e * P::npar + k) * 4 + mu];
     T tab[P::ntab];
-    for (int j = 0; j < P::nitems; ++j) P::table_entry(p, prm, j, tab);
+    double sums[8 * P::nsum];
+    for (int i = 0; i < P::nsum; ++i) P::momentum_sum(p, i, sums);
+    for (int j = 0; j < P::nitems; ++j) P::table_entry(p, prm, j, sums, tab);
+    for (int i = 0; i < 4 * P::nrec; ++i) P::template recycled_entry<T>(i, (hme::tab_of<T>)tab, tab);
     double acc = 0;
     for (int h = 0; h < P::nhel; ++h) {
       static hme::cx<T> slots[P::nslot];

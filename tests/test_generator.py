@@ -263,3 +263,24 @@ def test_compensated_helpers_are_not_contracted_on_the_device(tmp_path):
     # a fusion needs the add to allow contraction: no add or subtract in them may allow it
     flagged = re.findall(r"= (?:fadd|fsub) (?:[a-z]+ )*contract", body)
     assert not flagged, flagged[:4]
+
+
+CHANNEL_CASES = [(1, "ggtt", 0, "tt"), (2, "ggttg", 1, "tt"), (3, "ggttgg", 2, "tt"), (5, "uuee", 0, "dy"),
+                 (6, "uueeg", 1, "dy"), (7, "uueegg", 2, "dy"), (8, "uueeggg", 3, "dy")]
+
+
+@pytest.mark.parametrize("proc,key,ng,family", CHANNEL_CASES)
+def test_generated_channel_weights_match_oracle(hostlib, card, proc, key, ng, family):
+    """Per-diagram sums over helicities and terms of |a|^2 of the generated code (its amplitude
+    observer) against the oracle's diagram-by-diagram evaluation; diagrams matched by name."""
+    dp = ctypes.POINTER(ctypes.c_double)
+    hostlib.hostcheck_channels.argtypes = [ctypes.c_int, dp, ctypes.c_int64, dp, dp]
+    p = np.ascontiguousarray(configs.WORKLOADS[key].momenta(3, first_event=40))
+    gkeys = diagrams.diagram_keys(ng, family)
+    okeys = oracle.diagram_keys(proc)
+    assert sorted(gkeys) == sorted(okeys)
+    got = np.empty((len(p), len(gkeys)))
+    assert hostlib.hostcheck_channels(proc, card.ctypes.data_as(dp), len(p), p.ctypes.data_as(dp),
+                                      got.ctypes.data_as(dp)) == 0
+    want = oracle.channel_weights(proc, p, card)[:, [okeys.index(k) for k in gkeys]]
+    assert np.abs(got / want - 1).max() <= 1e-12

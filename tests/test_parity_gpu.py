@@ -285,11 +285,28 @@ def h7(card):
     h.close()
 
 
-def test_ggttggg_other_precisions_unsupported(card):
-    for prec in (hme.FP64, hme.MIXED_PAPER):
-        with pytest.raises(hme.HmeError) as e:
-            hme.Handle(hme.GGTTGGG, card, prec)
-        assert e.value.code == hme.HME_E_UNSUPPORTED
+@pytest.mark.parametrize("prec", [hme.FP64, hme.MIXED_PAPER])
+def test_ggttggg_double_precision_modes(card, prec):
+    """FP64 (double pieces and workspace, colour sum in double) and MIXED_PAPER (double pieces,
+    single-precision colour sum on the matrix cores) on 2,048 events against the stored oracle
+    values, with the FP64 gate (the long double oracle deciding) and the 1e-5 mixed gate; across
+    the 4,096-event sub-batch boundary the values are bitwise those of smaller calls."""
+    print(f"[gpu] ggttggg precision={prec}", flush=True)
+    p = configs.WORKLOADS["ggttggg"].momenta(2048)
+    ref = golden_values("ggttggg_2048", p)
+    with hme.Handle(hme.GGTTGGG, card, prec) as h:
+        got = run(h, p)
+        rel = np.abs(got / ref - 1)
+        print(f"  {dist(rel)}")
+        if prec == hme.FP64:
+            _, narb = fp64_gate(configs.GGTTGGG, p, got, ref, card)
+            print(f"  {narb} events arbitrated")
+        else:
+            assert rel.max() <= MIXED_TOL
+        q = configs.WORKLOADS["ggttggg"].momenta(4096 + 300, first_event=9000)
+        whole = run(h, q)
+        for a, b in [(0, 64), (4090, 4100), (4095, 4396)]:
+            assert np.array_equal(run(h, q[a:b]), whole[a:b]), (a, b)
 
 
 def test_ggttggg_constants(h7):

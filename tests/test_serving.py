@@ -177,11 +177,13 @@ def test_served_ggttggg_equals_alone(gpu_setup):
 
 
 @pytest.mark.gpu
-def test_ggttggg_not_served_in_fp64(gpu_setup):
+def test_ggttggg_workspace_must_fit_a_slot(gpu_setup):
+    """An 8 MiB slot cannot hold one 64-event group of gg -> ttbar ggg's double-precision
+    workspace (1.6 MB per event): its requests are refused for the budget, others are served."""
     torch, card, pools = gpu_setup
     with hme.Server(card, hme.FP64, hbm_budget_bytes=8 << 20, nstreams=1) as srv:
         p = torch.zeros((4, 7, 4), dtype=torch.float64, device="cuda")
         o = torch.zeros(4, dtype=torch.float64, device="cuda")
         with pytest.raises(hme.HmeError) as e:
             srv.submit(hme.GGTTGGG, p, o)
-        assert e.value.code == hme.HME_E_UNSUPPORTED
+        assert e.value.code == hme.HME_E_BUDGET
