@@ -448,6 +448,19 @@ def main():
         h.close()
         log(f"[bench] {name}: {results[name]['value']:.4g} events/s, {per_launch * 1e3:.3f} ms/step")
 
+    # the Feynman-diagram gauge variant of the same workload (gauge invariant |M|^2, fewer
+    # cancellations between diagrams in single precision)
+    fd = {}
+    for prec, name in ((hme.FP64, "fp64"), (hme.MIXED_FAST, "mixed_fast")):
+        with hme.Handle(hme.GGTTGG, card, prec | hme.GAUGE_FD) as h:
+            gpu_s, _ = time_steps(h, mom, out, args.steps, args.warmup)
+        per = gpu_s / args.steps
+        rel = np.abs(out.cpu().numpy() / results["fp64"]["out"] - 1)
+        fd[name] = {"value": nevt / per, "ms_per_step": per * 1e3, "max_rel_diff_vs_fp64": float(rel.max()),
+                    "p99_rel_diff_vs_fp64": float(np.quantile(rel, 0.99)),
+                    "median_rel_diff_vs_fp64": float(np.median(rel))}
+        log(f"[bench] fd gauge {name}: {nevt / per:.4g} events/s, max rel diff vs fp64 {rel.max():.3g}")
+
     f64 = results["fp64"]
     achieved = f64["flops_per_event"] * nevt / (f64["ms_per_step"] / 1e3)
     cf = counter_flops("fp64", nevt)
@@ -494,6 +507,7 @@ def main():
                 ("mixed_fast", "f32 vertices/propagators/jamps, bf16x3-split MFMA colour sum with f32 accumulation, "
                            "f64 externals and sums", PEAK_FP32_VALU),
                 ("mixed_paper", "f64 amplitudes and jamps, f32 colour algebra, f64 sums", PEAK_FP64_VALU))},
+        "fd_gauge": fd,
         "configs": None,
         "ggttggg": None,
         "e2e": None,

@@ -66,6 +66,14 @@ enum hme_process {
  *   algebra; helicity/event sums in double. */
 enum hme_precision { HME_FP64 = 0, HME_MIXED_FAST = 1, HME_MIXED_PAPER = 2, HME_MIXED = HME_MIXED_FAST };
 
+/* Flag OR'd into the precision of hme_create: internal gluon propagators in the Feynman-diagram
+ * gauge (Hagiwara, Kanzaki, Li, Mawatari and Nakamura, Eur. Phys. J. C 80 (2020) 584) instead of
+ * the Feynman gauge; the paper names it for single-precision stability (section "Numerical
+ * stability").  |M|^2 is gauge invariant: the same value up to rounding.  Built for HME_GGTTG
+ * and HME_GGTTGG (HME_E_UNSUPPORTED otherwise); not for hme_compute_channels (the weights of
+ * single diagrams depend on the gauge) nor the server. */
+enum { HME_GAUGE_FD = 0x100 };
+
 enum hme_status {
   HME_OK = 0,
   HME_E_ARG = -1,        /* null or misaligned pointer, negative size, unknown process or precision */

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libhme.so")
 EEMUMU, GGTT, GGTTG, GGTTGG, GGTTGGG = 0, 1, 2, 3, 4
 UUEE, UUEEG, UUEEGG, UUEEGGG = 5, 6, 7, 8  # u ubar -> e+ e- + n g (Drell-Yan family)
 FP64, MIXED_FAST, MIXED_PAPER = 0, 1, 2
+GAUGE_FD = 0x100  # OR into the precision: internal gluons in the Feynman-diagram gauge
 MIXED = MIXED_FAST
 PRECISION_NAMES = {FP64: "fp64", MIXED_FAST: "mixed_fast", MIXED_PAPER: "mixed_paper"}
 NPAR = {EEMUMU: 4, GGTT: 4, GGTTG: 5, GGTTGG: 6, GGTTGGG: 7, UUEE: 4, UUEEG: 5, UUEEGG: 6, UUEEGGG: 7}

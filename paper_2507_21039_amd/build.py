@@ -23,13 +23,17 @@ _KERNEL_DEPS = ["me2_kernels.h", "colour_mfma.h", "helas.h", "process.h"]
 _PROCS = ("eemumu", "ggtt", "ggttg", "ggttgg", "ggttggg", "uuee", "uueeg", "uueegg", "uueeggg")
 # g g -> t tbar g g g runs as pieces, one generated translation unit each
 PIECES = {"ggttggg": 12}
+# processes also built in the Feynman-diagram gauge
+_FD = ("ggttg", "ggttgg")
 SOURCES = ["hme.cpp", "server.hip", "rambo.hip"] + [f"proc_{p}.hip" for p in _PROCS] + [
+    f"proc_{p}_fd.hip" for p in _FD] + [
     f"procs/{p}_c{c}.hip" for p, n in PIECES.items() for c in range(n)]
 DEPS = {
     "hme.cpp": _KERNEL_DEPS + ["params.h", "../../include/hme.h"],
     "server.hip": ["../../include/hme.h"],
     "rambo.hip": ["../../include/hme.h"],
     **{f"proc_{p}.hip": _KERNEL_DEPS + [f"procs/{p}.h"] for p in _PROCS},
+    **{f"proc_{p}_fd.hip": _KERNEL_DEPS + [f"procs/{p}_fd.h"] for p in _FD},
     **{f"procs/{p}_c{c}.hip": _KERNEL_DEPS + ["piece_kernels.h", f"procs/{p}.h", f"procs/{p}_c{c}.h"]
        for p, n in PIECES.items() for c in range(n)},
 }

@@ -508,6 +508,18 @@ template <class T> HME_FN vw4<T> vvv_vec_k(const vw4<T>& a, const vw4<T>& b, con
   return J;
 }
 
+// Feynman-diagram gauge propagator of an internal gluon (Hagiwara, Kanzaki, Li, Mawatari and
+// Nakamura, Eur. Phys. J. C 80 (2020) 584): i/Q^2 [-g + (n Q + Q n)/(n.Q)] applied to the vertex,
+// i.e. the Feynman-gauge current J (propagator included) becomes J - nt (Q.J) - Q (nt.J) with
+// k = (nt, Q), nt = n / (n.Q), n = (sign Q0, -Q3vec / |Q3vec|).
+template <class T> HME_FN vw4<T> fd_project(const vw4<T>& J, const kitv<T, 8>& k) {
+  const cx<T> qj = mdot(k.v + 4, J), nj = mdot(k.v, J);
+  vw4<T> r;
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) r.c[mu] = rfma(-k.v[4 + mu], nj, rfma(-k.v[mu], qj, J.c[mu]));
+  return r;
+}
+
 // vvv_amp with k = (Qa - Qb, Qb - Qc, Qc - Qa).
 template <class T>
 HME_FN cx<T> vvv_amp_k(const vw4<T>& a, const vw4<T>& b, const vw4<T>& c, const kitv<T, 12>& k) {

@@ -31,6 +31,10 @@ HME_DECLARE(uueeg)
 HME_DECLARE(uueegg)
 HME_DECLARE(uueeggg)
 #undef HME_DECLARE
+ProcInfo info_ggttg_fd();
+hipError_t launch_me2_ggttg_fd(const LaunchArgs& a, int precision);
+ProcInfo info_ggttgg_fd();
+hipError_t launch_me2_ggttgg_fd(const LaunchArgs& a, int precision);
 
 struct ProcEntry {
   ProcInfo (*info)();
@@ -38,13 +42,15 @@ struct ProcEntry {
   hipError_t (*hel)(const double*, int, const ProcParams&, double*, hipStream_t);
   bool qcd;            // g g -> t tbar + n g: massive final quarks (otherwise every particle is massless)
   double sample_sqrt_s;  // energy of the internal helicity-filter sample
+  ProcInfo (*info_fd)() = nullptr;  // the process in the Feynman-diagram gauge, if built
+  hipError_t (*me2_fd)(const LaunchArgs&, int) = nullptr;
 };
 
 static const ProcEntry kProcs[] = {
     {info_eemumu, launch_me2_eemumu, launch_hel_eemumu, false, 500.0},
     {info_ggtt, launch_me2_ggtt, launch_hel_ggtt, true, 1000.0},
-    {info_ggttg, launch_me2_ggttg, launch_hel_ggttg, true, 1500.0},
-    {info_ggttgg, launch_me2_ggttgg, launch_hel_ggttgg, true, 2000.0},
+    {info_ggttg, launch_me2_ggttg, launch_hel_ggttg, true, 1500.0, info_ggttg_fd, launch_me2_ggttg_fd},
+    {info_ggttgg, launch_me2_ggttgg, launch_hel_ggttgg, true, 2000.0, info_ggttgg_fd, launch_me2_ggttgg_fd},
     {info_ggttggg, launch_me2_ggttggg, launch_hel_ggttggg, true, 2000.0},
     {info_uuee, launch_me2_uuee, launch_hel_uuee, false, 1000.0},
     {info_uueeg, launch_me2_uueeg, launch_hel_uueeg, false, 1000.0},
@@ -60,6 +66,7 @@ constexpr int kNumProcs = sizeof(kProcs) / sizeof(kProcs[0]);
 
 struct hme_handle {
   int process = 0, precision = 0, device = 0;
+  bool gauge_fd = false;  // internal gluons in the Feynman-diagram gauge
   hme::ProcInfo info{};
   hme::ProcParams prm{};
   std::vector<int> goodhel;
@@ -204,8 +211,12 @@ int hme_create(int process, const hme_sm_card* card, int precision, int device, 
   *out = nullptr;
   if (!card) return fail(HME_E_ARG, "hme_create: card is NULL");
   if (process < 0 || process >= hme::kNumProcs) return fail(HME_E_ARG, "hme_create: unknown process");
+  const bool gauge_fd = (precision & HME_GAUGE_FD) != 0;
+  precision &= ~HME_GAUGE_FD;
   if (precision != HME_FP64 && precision != HME_MIXED_FAST && precision != HME_MIXED_PAPER)
     return fail(HME_E_ARG, "hme_create: unknown precision");
+  if (gauge_fd && !hme::kProcs[process].me2_fd)
+    return fail(HME_E_UNSUPPORTED, "hme_create: this process is not built in the Feynman-diagram gauge");
   int ndev = 0;
   hipError_t e = hipGetDeviceCount(&ndev);
   if (e != hipSuccess) return hip_fail(e, "hme_create: hipGetDeviceCount");
@@ -223,7 +234,8 @@ int hme_create(int process, const hme_sm_card* card, int precision, int device, 
   h->process = process;
   h->precision = precision;
   h->device = device;
-  h->info = P.info();
+  h->info = gauge_fd ? P.info_fd() : P.info();
+  h->gauge_fd = gauge_fd;
   h->prm = prm;
 
   // good-helicity filter on the internal sample
@@ -318,7 +330,7 @@ hipError_t launch_for_handle(const hme_handle* h, int64_t nevt_grid, const int64
                              const SelectArgs& sel) {
   LaunchArgs a{mom, out, nevt_grid, h->d_goodhel, (int)h->goodhel.size(), h->prm, norm, s,
                h->precision == HME_MIXED_PAPER ? 1 : 0, nevt_dev, ws, ws_events, sel};
-  return kProcs[h->process].me2(a, h->precision);
+  return (h->gauge_fd ? kProcs[h->process].me2_fd : kProcs[h->process].me2)(a, h->precision);
 }
 
 hipError_t launch_for_handle(const hme_handle* h, int64_t nevt_grid, const int64_t* nevt_dev, const double* mom,
@@ -439,8 +451,8 @@ int hme_compute_channels(hme_handle* h, double alpha_s, int64_t nevt, const doub
                          double* channel_weights, void* hip_stream) {
   if (!h) return fail(HME_E_ARG, "hme_compute_channels: handle is NULL");
   if (nevt < 0) return fail(HME_E_ARG, "hme_compute_channels: nevt < 0");
-  if (h->info.nchunk > 0 || h->process == HME_EEMUMU)
-    return fail(HME_E_UNSUPPORTED, "hme_compute_channels: no channel weights for this process");
+  if (h->info.nchunk > 0 || h->process == HME_EEMUMU || h->gauge_fd)
+    return fail(HME_E_UNSUPPORTED, "hme_compute_channels: no channel weights for this process or gauge");
   if (nevt == 0) return HME_OK;
   if (!momenta || !me2 || !channel_weights) return fail(HME_E_ARG, "hme_compute_channels: NULL buffer");
   if ((reinterpret_cast<uintptr_t>(momenta) | reinterpret_cast<uintptr_t>(me2) |

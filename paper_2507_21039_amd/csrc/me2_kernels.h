@@ -52,16 +52,17 @@ struct SelectArgs {
 // W_d = sum over good helicities and over the diagram's amplitude terms of |a|^2 (colour
 // stripped; a diagram with a four-gluon vertex has one term per colour structure), normalised to
 // sum to 1 over the diagrams.  The observer sums each term's |a|^2 over the event's LPE lanes
-// (one helicity each) and one lane adds it to the event's LDS row.
+// (one helicity each) and adds it to the event's LDS row.
 template <class T, int LPE> struct ChannelObserver {
-  volatile HME_LDS double* w;
+  volatile HME_LDS float* w;
   bool valid;
-  int sub;
   HME_FN void term(int d, const cx<T>& a) const {
     float s = valid ? (float)a.r * (float)a.r + (float)a.i * (float)a.i : 0.f;
 #pragma unroll
     for (int off = LPE / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    if (sub == 0) w[d] += (double)s;
+    // every lane of the segment holds the sum and writes the same value: no branch in the
+    // straight-line amplitude code
+    w[d] = w[d] + s;
   }
 };
 
@@ -241,7 +242,7 @@ __global__ void __launch_bounds__(256, me2_min_waves<T>())
   // flow weights of the selection variant (one array per wavefront, events of 64 lanes)
   __shared__ double wsel[4][Select && LPE == 64 && Proc::ncol >= 16 ? Proc::ncol : 1];
   // channel weights of the events of the block
-  __shared__ double wch[Channels ? EPB : 1][Channels ? Proc::ndiag : 1];
+  __shared__ float wch[Channels ? EPB : 1][Channels ? Proc::ndiag : 1];
   const int lane = threadIdx.x & 63;
   // the event count comes from device memory when a captured graph launches a batch of
   // varying size with a fixed grid; blocks past the end leave at once
@@ -269,12 +270,12 @@ __global__ void __launch_bounds__(256, me2_min_waves<T>())
 #pragma unroll
     for (int c = 0; c < Proc::ncol; ++c) jamp[c] = {T(0), T(0)};
     const unsigned hsel = (unsigned)goodhel[valid ? sub : ngood - 1];
-    [[maybe_unused]] volatile HME_LDS double* wd = nullptr;
+    [[maybe_unused]] volatile HME_LDS float* wd = nullptr;
     if constexpr (Channels) {
-      wd = (volatile HME_LDS double*)&wch[threadIdx.x / LPE][0];
-      for (int d = sub; d < Proc::ndiag; d += LPE) wd[d] = 0.0;
+      wd = (volatile HME_LDS float*)&wch[threadIdx.x / LPE][0];
+      for (int d = sub; d < Proc::ndiag; d += LPE) wd[d] = 0.f;
       wave_lds_sync();
-      Proc::template amplitudes<T>(p, prm, hsel, (tab_of<T>)tab, jamp, ChannelObserver<T, LPE>{wd, valid, sub});
+      Proc::template amplitudes<T>(p, prm, hsel, (tab_of<T>)tab, jamp, ChannelObserver<T, LPE>{wd, valid});
     } else {
       Proc::template amplitudes<T>(p, prm, hsel, (tab_of<T>)tab, jamp);
     }
@@ -297,11 +298,11 @@ __global__ void __launch_bounds__(256, me2_min_waves<T>())
       // normalise the event's row and write it
       wave_lds_sync();
       double tot = 0.0;
-      for (int d = sub; d < Proc::ndiag; d += LPE) tot += wd[d];
+      for (int d = sub; d < Proc::ndiag; d += LPE) tot += (double)wd[d];
 #pragma unroll
       for (int off = LPE / 2; off > 0; off >>= 1) tot += __shfl_xor(tot, off, 64);
       if (ev < nevt)
-        for (int d = sub; d < Proc::ndiag; d += LPE) sel.chan_w[ev * Proc::ndiag + d] = wd[d] / tot;
+        for (int d = sub; d < Proc::ndiag; d += LPE) sel.chan_w[ev * Proc::ndiag + d] = (double)wd[d] / tot;
     }
   } else if constexpr (kMfmaColour) {
     // every lane runs every pass (the matrix cores take the whole wavefront); a lane past the

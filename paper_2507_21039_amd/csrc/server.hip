@@ -318,6 +318,7 @@ int hme_server_create(const hme_sm_card* card, int precision, int device, size_t
   *out = nullptr;
   if (!card) return srv_fail(HME_E_ARG, "hme_server_create: card is NULL");
   if (nstreams < 1 || nstreams > 8) return srv_fail(HME_E_ARG, "hme_server_create: nstreams must be 1..8");
+  if (precision & HME_GAUGE_FD) return srv_fail(HME_E_UNSUPPORTED, "hme_server_create: Feynman gauge only");
   if (hbm_budget_bytes < (size_t)nstreams * (1u << 20))
     return srv_fail(HME_E_BUDGET, "hme_server_create: budget below 1 MiB per stream");
   auto* s = new Server;

@@ -37,8 +37,9 @@ FLOPS["vvv_vec_k"] = FLOPS["vvv_vec"] - 18
 FLOPS["ffv_psi_k"] = FLOPS["ffv_psi"] - 10
 FLOPS["ffv_psibar_k"] = FLOPS["ffv_psibar"] - 10
 FLOPS["vvv_amp_k"] = FLOPS["vvv_amp"] - 12
-VK_SIZE = {"vvv": 12, "psi": 5, "amp3": 12}  # doubles per vertex kit
-VK_FLOPS = {"vvv": 24, "psi": 7, "amp3": 12}  # per event, in the table
+VK_SIZE = {"vvv": 12, "psi": 5, "amp3": 12, "fd": 8}  # doubles per vertex kit
+VK_FLOPS = {"vvv": 24, "psi": 7, "amp3": 12, "fd": 16}  # per event, in the table
+FD_FLOPS = 2 * 14 + 4 * 2 * 4  # the gauge projection of a gluon current: two dots, four updates
 EXT_FLOPS = {"vxxxxx": 20, "ixxxxx": 30, "oxxxxx": 30,  # includes sqrt/div as one each
              "ewkit": 2 * 30 + 120 + 40}  # lepton spinors, lepton current, photon + Z couplings
 EW_ITEMS = 8  # electroweak current per (quark, e+, e-) helicity, 8 doubles each
@@ -148,7 +149,7 @@ def prefetch_units(lines, enable, kits: bool = True):
 
 
 def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chunks: int = 0,
-             file_stem: str = "", jbudget: int = 32, order=None, recycle: bool = False):
+             file_stem: str = "", jbudget: int = 32, order=None, recycle: bool = False, gauge: str = "feynman"):
     """Emit the process header.
 
     budget: number of off-shell wavefunctions kept live at once, for the double and the
@@ -170,7 +171,13 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
     recycle: helicity recycling.  A wavefunction built from two external states takes only 4
     values per event (one per helicity pair), so the event's lanes compute those once into the
     per-event table and every lane reads the one of its helicities instead of computing it.
+    gauge: "feynman" (gluon propagator -i g/Q^2) or "fd", the Feynman-diagram gauge of Hagiwara,
+    Kanzaki, Li, Mawatari and Nakamura (Eur. Phys. J. C 80 (2020) 584): every internal gluon
+    current J becomes J - nt (Q.J) - Q (nt.J), nt = n / (n.Q), n = (sign Q0, -Q3vec / |Q3vec|),
+    which removes the gauge cancellations between diagrams that cost digits in single precision.
+    External gluons keep their helicity vectors (n.eps = 0 for them already).
     """
+    fd = gauge == "fd"
     if isinstance(budget, int):
         budget = (budget, budget)
     if isinstance(prefetch, str):
@@ -240,7 +247,11 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
         else:
             den(n.mask, False)
             kk = didx[n.mask][0]
-        rec_info.append(({"vvv": 0, "psi": 1, "psibar": 2, "qq": 3}[n.kind], pa, pb, kk))
+        fk = 0
+        if fd and n.kind in ("vvv", "qq"):
+            vkit("fd", n.mask)
+            fk = vkidx[("fd", n.mask, 0, 0, 1)]
+        rec_info.append(({"vvv": 0, "psi": 1, "psibar": 2, "qq": 3}[n.kind], pa, pb, kk, fk))
 
     def pick_order(spec):
         if spec is None:
@@ -331,15 +342,18 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
             v = f"w{node_ids[key]}" + (f"_{version[key]}" if version[key] else "")
             if n.kind == "vvv":
                 ma, mb = g.nodes[n.args[0]].mask, g.nodes[n.args[1]].mask
-                call = f"vw4<T> {v} = vvv_vec_k<T>({args[0]}, {args[1]}, {vkit('vvv', ma, mb, n.mask)});"
+                expr = f"vvv_vec_k<T>({args[0]}, {args[1]}, {vkit('vvv', ma, mb, n.mask)})"
+                call = f"vw4<T> {v} = " + (f"fd_project<T>({expr}, {vkit('fd', n.mask)});" if fd else expr + ";")
             elif n.kind == "vvvv":
-                call = f"vw4<T> {v} = vvvv_vec<{n.extra[0]}, T>({args[0]}, {args[1]}, {args[2]}, {den(n.mask, False)});"
+                expr = f"vvvv_vec<{n.extra[0]}, T>({args[0]}, {args[1]}, {args[2]}, {den(n.mask, False)})"
+                call = f"vw4<T> {v} = " + (f"fd_project<T>({expr}, {vkit('fd', n.mask)});" if fd else expr + ";")
             elif n.kind == "psi":
                 call = f"sp4<T> {v} = ffv_psi_k<T>({args[0]}, {args[1]}, {vkit('psi', n.mask)});"
             elif n.kind == "psibar":
                 call = f"sp4<T> {v} = ffv_psibar_k<T>({args[0]}, {args[1]}, {vkit('psi', n.mask, sign=-1)});"
             elif n.kind == "qq":
-                call = f"vw4<T> {v} = ffv_vec<T>({args[0]}, {args[1]}, {den(n.mask, False)});"
+                expr = f"ffv_vec<T>({args[0]}, {args[1]}, {den(n.mask, False)})"
+                call = f"vw4<T> {v} = " + (f"fd_project<T>({expr}, {vkit('fd', n.mask)});" if fd else expr + ";")
             else:
                 raise ValueError(n.kind)
             typ = call.split(" ", 1)[0]
@@ -350,7 +364,7 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
             lines.extend(pre)
             lines.append(f"    {name_rest.replace(v + ' =', v + ' =', 1)}")
             lines.append("  }")
-            f = FLOPS[NODE_FLOPS[n.kind]]
+            f = FLOPS[NODE_FLOPS[n.kind]] + (FD_FLOPS if fd and n.kind in ("vvv", "vvvv", "qq") else 0)
             flops_exec += f
             if key not in computed_once:
                 flops_dag += f
@@ -535,8 +549,9 @@ struct {name}_c{c} {{
     kind_code = {"ext_v": 0, "ext_o": 3 if dy else 1, "ext_i": 4 if dy else 2}
     kits = [(koff[k], kind_code[g.nodes[("E", k)].kind], k) if k in koff else (0, -1, k) for k in range(npar)]
     flops_table = DEN_FLOPS * nd + 4 * nq + 40 * len(ext)
-    flops_table += 4 * sum(FLOPS[NODE_FLOPS[g.nodes[k].kind]] for k in rec)  # each helicity pair once
-    rec_rows = [(kind, pa, pb, koff[pa], koff[pb], kk) for kind, pa, pb, kk in rec_info]
+    flops_table += 4 * sum(FLOPS[NODE_FLOPS[g.nodes[k].kind]] + (FD_FLOPS if fd and g.nodes[k].kind in ("vvv", "qq") else 0)
+                           for k in rec)  # each helicity pair once
+    rec_rows = [(kind, pa, pb, koff[pa], koff[pb], kk, fk) for kind, pa, pb, kk, fk in rec_info]
     nrec = len(rec)
     qmass = "0.0" if dy else "prm.mT"  # mass of the quark line
     row_end = 1 if dy else TOP  # particle of the barred spinor at the quark line's end
@@ -581,10 +596,10 @@ struct {name}_c{c} {{
 
     qcode = [slot(m) for m in qmask]
     dcode = [slot(m) for m in dmask]
-    vk_c = [[slot(x[1 + i]) if (i == 0 or x[0] != "psi") else 0 for x in vk_list] for i in range(3)]
+    vk_c = [[slot(x[1 + i]) if (i == 0 or x[0] in ("vvv", "amp3")) else 0 for x in vk_list] for i in range(3)]
     nsum = len(sum_masks)
     flops_table += sum(VK_FLOPS[x[0]] for x in vk_list)
-    vk_kind_code = {"vvv": 0, "psi": 1, "amp3": 2}
+    vk_kind_code = {"vvv": 0, "psi": 1, "amp3": 2, "fd": 3}
     numer_list = ", ".join(str(N[i][j]) for i in range(ncol) for j in range(ncol))
     assert all(abs(N[i][j]) < 32768 for i in range(ncol) for j in range(ncol))
     gather_code = ""
@@ -674,7 +689,8 @@ struct {name} {{
   // vertex kits after the external-state kits: kind 0 three-gluon current (den (Qa - Qb),
   // den (Qa + 2 Qb), den (2 Qa + Qb) with den = 1 / Q^2 of mask 2), kind 1 quark propagator
   // (den sign (K0 + K3, K0 - K3, K1, K2), den mT with K of mask 0 and den = 1 / (K^2 - mT^2)),
-  // kind 2 three-gluon amplitude (Qa - Qb, Qb - Qc, Qc - Qa)
+  // kind 2 three-gluon amplitude (Qa - Qb, Qb - Qc, Qc - Qa), kind 3 Feynman-diagram gauge
+  // projection of a gluon line (nt = n / (n.Q) with n = (sign Q0, -Q3vec / |Q3vec|), then Q)
   static constexpr int nvk = {nvk}, voff = {voff};
   static constexpr int vk_kind[{max(nvk, 1)}] = {{{", ".join(str(vk_kind_code[x[0]]) for x in vk_list) or "0"}}};
   static constexpr short vk_c0[{max(nvk, 1)}] = {{{", ".join(map(str, vk_c[0])) or "0"}}};
@@ -694,6 +710,8 @@ struct {name} {{
   static constexpr int rec_oa[{max(nrec, 1)}] = {{{", ".join(str(x[3]) for x in rec_rows) or "0"}}};
   static constexpr int rec_ob[{max(nrec, 1)}] = {{{", ".join(str(x[4]) for x in rec_rows) or "0"}}};
   static constexpr int rec_k[{max(nrec, 1)}] = {{{", ".join(str(x[5]) for x in rec_rows) or "0"}}};
+  static constexpr int rec_fd[{max(nrec, 1)}] = {{{", ".join(str(x[6]) for x in rec_rows) or "0"}}};  // gauge kit (kinds 0, 3)
+  static constexpr bool fd_gauge = {"true" if fd else "false"};  // Feynman-diagram gauge for internal gluons
 
   // item i < 4 nrec: recycled wavefunction i / 4 for the helicity pair i % 4 (bit 1: first
   // argument +1, bit 0: second +1), from the kits in t, written into w (the same table)
@@ -704,10 +722,13 @@ struct {name} {{
     S* o = w + roff + 32 * r + 8 * (i & 3);
     const auto tab = t;
     switch (rec_kind[r]) {{
-      case 0:
-        store_wf(vvv_vec_k<T>(vxxxxx_kit<T>(tab + rec_oa[r], ha, na), vxxxxx_kit<T>(tab + rec_ob[r], hb, nb),
-                              load_kit<T, 12>(tab + voff + rec_k[r])), o);
+      case 0: {{
+        vw4<T> x = vvv_vec_k<T>(vxxxxx_kit<T>(tab + rec_oa[r], ha, na), vxxxxx_kit<T>(tab + rec_ob[r], hb, nb),
+                                load_kit<T, 12>(tab + voff + rec_k[r]));
+        if constexpr (fd_gauge) x = fd_project<T>(x, load_kit<T, 8>(tab + voff + rec_fd[r]));
+        store_wf(x, o);
         break;
+      }}
       case 1:
         store_wf(ffv_psi_k<T>(ixxxxx_kit<T>(tab + rec_oa[r], ha), vxxxxx_kit<T>(tab + rec_ob[r], hb, nb),
                               load_kit<T, 5>(tab + voff + rec_k[r])), o);
@@ -716,10 +737,13 @@ struct {name} {{
         store_wf(ffv_psibar_k<T>(oxxxxx_kit<T>(tab + rec_oa[r], ha), vxxxxx_kit<T>(tab + rec_ob[r], hb, nb),
                                  load_kit<T, 5>(tab + voff + rec_k[r])), o);
         break;
-      default:
-        store_wf(ffv_vec<T>(oxxxxx_kit<T>(tab + rec_oa[r], ha), ixxxxx_kit<T>(tab + rec_ob[r], hb),
-                            dv<T>(tab, {4 * nq} + rec_k[r])), o);
+      default: {{
+        vw4<T> x = ffv_vec<T>(oxxxxx_kit<T>(tab + rec_oa[r], ha), ixxxxx_kit<T>(tab + rec_ob[r], hb),
+                              dv<T>(tab, {4 * nq} + rec_k[r]));
+        if constexpr (fd_gauge) x = fd_project<T>(x, load_kit<T, 8>(tab + voff + rec_fd[r]));
+        store_wf(x, o);
         break;
+      }}
     }}
   }}
 
@@ -769,6 +793,22 @@ struct {name} {{
   template <class S> HME_FN static void vertex_kit(const double* sums, const ProcParams& prm, int v, S* o) {{
     dd A[4], B[4], C[4];
     mask_sum(sums, vk_c0[v], A);
+    if (vk_kind[v] == 3) {{
+      // Feynman-diagram gauge: nt = n / (n.Q), n = (sign Q0, -Q3vec / |Q3vec|), n.Q = |Q0| + |Q3vec|;
+      // a line at rest (an s-channel gluon in the centre-of-mass frame) has no direction of its
+      // own and takes the z axis (any fixed direction is a gauge choice)
+      double q[4];
+#pragma unroll
+      for (int mu = 0; mu < 4; ++mu) q[mu] = dd_val(A[mu]);
+      const double qa = sqrt(q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+      const double nq = 1.0 / (fabs(q[0]) + qa);
+      o[0] = S((q[0] >= 0 ? 1.0 : -1.0) * nq);
+#pragma unroll
+      for (int mu = 1; mu < 4; ++mu) o[mu] = S(qa > 0 ? -q[mu] / qa * nq : (mu == 3 ? -nq : 0.0));
+#pragma unroll
+      for (int mu = 0; mu < 4; ++mu) o[4 + mu] = S(q[mu]);
+      return;
+    }}
     if (vk_kind[v] == 1) {{
       const double den = 1.0 / dd_minkowski_sq(A, {qmass});
       const double ds = den * vk_sign[v];

@@ -9,6 +9,8 @@
 #include "../../paper_2507_21039_amd/csrc/procs/ggtt.h"
 #include "../../paper_2507_21039_amd/csrc/procs/ggttg.h"
 #include "../../paper_2507_21039_amd/csrc/procs/ggttgg.h"
+#include "../../paper_2507_21039_amd/csrc/procs/ggttg_fd.h"
+#include "../../paper_2507_21039_amd/csrc/procs/ggttgg_fd.h"
 #include "../../paper_2507_21039_amd/csrc/procs/uuee.h"
 #include "../../paper_2507_21039_amd/csrc/procs/uueeg.h"
 #include "../../paper_2507_21039_amd/csrc/procs/uueegg.h"
@@ -137,6 +139,10 @@ extern "C" int hostcheck_me2(int process, int precision, const double* card, dou
                 : run<hme::P_ggttg, float>(prm, alpha_s, nevt, mom, out, per_hel); break;
     case 3: f64 ? run<hme::P_ggttgg, double>(prm, alpha_s, nevt, mom, out, per_hel)
                 : run<hme::P_ggttgg, float>(prm, alpha_s, nevt, mom, out, per_hel); break;
+    case 102: f64 ? run<hme::P_ggttg_fd, double>(prm, alpha_s, nevt, mom, out, per_hel)
+                  : run<hme::P_ggttg_fd, float>(prm, alpha_s, nevt, mom, out, per_hel); break;
+    case 103: f64 ? run<hme::P_ggttgg_fd, double>(prm, alpha_s, nevt, mom, out, per_hel)
+                  : run<hme::P_ggttgg_fd, float>(prm, alpha_s, nevt, mom, out, per_hel); break;
     case 5: f64 ? run<hme::P_uuee, double>(prm, alpha_s, nevt, mom, out, per_hel)
                 : run<hme::P_uuee, float>(prm, alpha_s, nevt, mom, out, per_hel); break;
     case 6: f64 ? run<hme::P_uueeg, double>(prm, alpha_s, nevt, mom, out, per_hel)

@@ -65,7 +65,8 @@ def _hostlib():
     os.makedirs(os.path.dirname(HOSTLIB), exist_ok=True)
     src = os.path.join(HERE, "hostcheck", "hostcheck.hip")
     deps = [src] + [os.path.join(HERE, "..", "paper_2507_21039_amd", "csrc", f)
-                    for f in ("helas.h", "params.h", "process.h", "procs/ggttgg.h", "procs/uueeggg.h")]
+                    for f in ("helas.h", "params.h", "process.h", "procs/ggttgg.h", "procs/uueeggg.h",
+                              "procs/ggttgg_fd.h")]
     if not os.path.exists(HOSTLIB) or os.path.getmtime(HOSTLIB) < max(os.path.getmtime(d) for d in deps):
         subprocess.run(["/opt/rocm/bin/hipcc", "-O1", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
                         "-x", "hip", src, "-o", HOSTLIB], check=True)
@@ -284,3 +285,17 @@ def test_generated_channel_weights_match_oracle(hostlib, card, proc, key, ng, fa
                                       got.ctypes.data_as(dp)) == 0
     want = oracle.channel_weights(proc, p, card)[:, [okeys.index(k) for k in gkeys]]
     assert np.abs(got / want - 1).max() <= 1e-12
+
+
+@pytest.mark.parametrize("proc,key,n", [(2, "ggttg", 2000), (3, "ggttgg", 300)])
+def test_feynman_diagram_gauge_on_host(hostlib, card, proc, key, n):
+    """The generated code in the Feynman-diagram gauge (internal gluon propagators with the light-like
+    gauge vector n = (sign Q0, -Q/|Q|)) equals the oracle, which works in the Feynman gauge: |M|^2 is
+    gauge invariant, so a mistake in the gauge terms shows as a difference.  Double precision within
+    2e-14 of the long double oracle; single precision within 1e-5."""
+    p = configs.WORKLOADS[key].momenta(n, first_event=300)
+    ld = oracle.me2(proc, p, card, extended=True)
+    fd64 = host_me2(hostlib, 100 + proc, 0, p, card)
+    fd32 = host_me2(hostlib, 100 + proc, 1, p, card)
+    assert np.abs(fd64 / ld - 1).max() <= 2e-14
+    assert np.abs(fd32 / ld - 1).max() <= 1e-5
