@@ -105,7 +105,7 @@ int hme_create(int process, const hme_sm_card* card, int precision, int device, 
  * strong coupling for this call.  nevt = 0 is a successful no-op; any nevt >= 1
  * is valid (partial wavefronts are masked).  Not thread-safe per handle.
  * HME_GGTTGGG also takes a device workspace of min(nevt, S) events times
- * hme_info.workspace_bytes_per_event (partial-jamp slots x good helicities x the size of a
+ * hme_info.workspace_bytes_per_event (partial-jamp slots x helicities x the size of a
  * complex jamp: 789 x 128 x 8 bytes = 0.81 MB per event at HME_MIXED_FAST, twice that in the
  * double-precision modes), allocated and released on `hip_stream` in stream order (HME_E_OOM if
  * that fails); larger batches run as consecutive sub-batches of S events, S = 8192 at
@@ -233,15 +233,21 @@ int hme_flat_cross_section(const double* sums, int64_t npoints, double sqrt_s, d
  *
  * The server owns `nstreams` slots; slot k owns hbm_budget_bytes / nstreams of
  * device memory (gathered momenta and |M|^2 of one batch) and its own stream.  A
- * scheduler thread takes the oldest pending request and, while they fit in a
- * free slot, later pending requests of the same process (continuous batching),
- * then launches the batch as one captured hipGraph per (process, slot, size
- * bucket): descriptor upload, gather kernel, |M|^2 kernel, scatter kernel (which
- * also applies each request's alpha_s normalisation).  Batches on different
- * slots overlap on the device.  Per-event arithmetic does not depend on the
- * batch, so a request's |M|^2 are bitwise those of hme_compute on it alone.
+ * scheduler thread takes the oldest pending part of a request that has no part on the
+ * device (else the oldest part) and, while they fit in a free slot, later pending parts of
+ * the same process (continuous batching); a request runs as one part, or as several when it
+ * is larger than a slot holds or, for HME_GGTTGGG, larger than 8192 events, so that large
+ * requests share the device with others instead of holding a slot for their whole length.
+ * Two limits keep slots open for requests that arrive meanwhile: HME_GGTTGGG batches hold
+ * at most half of the slots (at least one), and a further part of a request already on the
+ * device starts only while another slot stays free.  The scheduler then launches the batch as one
+ * captured hipGraph per (process, slot, size bucket): descriptor upload, gather
+ * kernel, |M|^2 kernel, scatter kernel (which also applies each request's alpha_s
+ * normalisation).  Batches on different slots overlap on the device.  Per-event
+ * arithmetic does not depend on the batch, so a request's |M|^2 are bitwise those of
+ * hme_compute on it alone.
  * HME_GGTTGGG's jamp workspace, for sub-batches of up to 4096 events, takes at most half
- * of each slot, and its requests must fit beside it.
+ * of each slot.
  * The server is thread-safe. */
 
 typedef struct hme_server hme_server;
@@ -258,8 +264,8 @@ int hme_server_create(const hme_sm_card* card, int precision, int device, size_t
 
 /* Queue |M|^2 of nevt events of `process`.  momenta_dev / me2_dev are caller-owned
  * device pointers that must stay valid until hme_wait returns for *req_id.
- * Returns HME_E_BUDGET if the request cannot fit in one slot; nothing is copied
- * at submit time.  The server's streams do not wait for any stream of the caller: the
+ * Returns HME_E_BUDGET if a slot cannot hold a single event of the process (a request larger
+ * than a slot runs in parts); nothing is copied at submit time.  The server's streams do not wait for any stream of the caller: the
  * momenta must already be complete in device memory (for instance the stream that wrote them
  * synchronized) when hme_submit is called; use hme_submit_after otherwise. */
 int hme_submit(hme_server* s, int process, double alpha_s, int64_t nevt, const double* momenta_dev, double* me2_dev,

@@ -31,7 +31,8 @@ namespace {
 
 constexpr int kNumProcesses = 9;  // every process of hme_process
 constexpr int64_t kMaxSubBatch = 4096;  // events per sub-batch of a process evaluated in pieces
-constexpr int kMaxBatchReq = 64;      // requests per batch
+constexpr int kMaxBatchReq = 64;      // request parts per batch
+constexpr int64_t kPiecePart = 8192;  // events per part of a request of a process evaluated in pieces
 constexpr int64_t kMinBucket = 256;   // smallest graph size bucket (events)
 
 struct ReqDesc {
@@ -81,7 +82,17 @@ struct Request {
   int status = HME_OK;
   std::string error;               // message of a failed batch, handed to the waiting thread
   hipEvent_t ready = nullptr;      // recorded on the producer stream at submit (hme_submit_after)
+  int parts_left = 0;              // parts not finished yet
+  int parts_running = 0;           // parts in a batch on the device now
   std::chrono::steady_clock::time_point t_submit, t_done;
+};
+
+// A contiguous range of a request's events, scheduled on its own: a request larger than a
+// slot, or a large request of a process evaluated in pieces, runs as several parts that can
+// share the device with other requests' parts.
+struct Part {
+  std::shared_ptr<Request> r;
+  int64_t offset, nevt;
 };
 
 struct Server;
@@ -89,7 +100,7 @@ struct Server;
 struct Batch {
   Server* srv;
   int slot;
-  std::vector<std::shared_ptr<Request>> reqs;
+  std::vector<Part> parts;
 };
 
 struct Slot {
@@ -100,6 +111,7 @@ struct Slot {
   BatchDesc* d_desc = nullptr;  // device copy of the descriptor
   BatchDesc* h_desc = nullptr; // pinned host descriptor
   bool busy = false;
+  bool heavy = false;  // busy with a process evaluated in pieces
   std::map<std::pair<int, int64_t>, hipGraphExec_t> graphs;  // (process, bucket) -> graph
   std::vector<hipGraph_t> graph_defs;
 };
@@ -119,7 +131,7 @@ struct Server : hme_server {
   std::mutex mu;
   std::condition_variable cv_sched;  // pending work or a freed slot
   std::condition_variable cv_done;   // a request completed
-  std::deque<std::shared_ptr<Request>> pending;
+  std::deque<Part> pending;
   std::unordered_map<uint64_t, std::shared_ptr<Request>> requests;
   uint64_t next_id = 1;
   int inflight = 0;
@@ -136,6 +148,13 @@ struct Server : hme_server {
       return (slot_bytes - ws_bytes - 512) / (npar * 32 + 8);
     }
     return (slot_bytes - 256) / (npar * 32 + 8);
+  }
+
+  // events per part (and per batch) of `process`: what a slot holds, at most kPiecePart for a
+  // process evaluated in pieces (so that its large requests interleave with other work)
+  int64_t part_events(int process) const {
+    const int64_t cap = capacity(process);
+    return hme::handle_ws_bytes_per_event(handles[process]) > 0 ? std::min(cap, kPiecePart) : cap;
   }
 
   static int64_t bucket_for(int64_t n, int64_t cap) {
@@ -204,13 +223,18 @@ struct Server : hme_server {
     const auto now = std::chrono::steady_clock::now();
     {
       std::lock_guard<std::mutex> lk(s->mu);
-      for (auto& r : b->reqs) {
-        r->done = true;
-        r->t_done = now;
+      for (auto& pt : b->parts) {
+        auto& r = pt.r;
+        r->parts_running--;
+        if (--r->parts_left == 0) {
+          r->done = true;
+          r->t_done = now;
+          s->stats.completed++;
+        }
       }
       s->slots[b->slot].busy = false;
+      s->slots[b->slot].heavy = false;
       s->inflight--;
-      s->stats.completed += b->reqs.size();
     }
     s->cv_done.notify_all();
     s->cv_sched.notify_all();
@@ -220,15 +244,46 @@ struct Server : hme_server {
   void fail_batch(Batch* b, hipError_t e) {
     const std::string msg = std::string("server batch: ") + hipGetErrorString(e);
     std::lock_guard<std::mutex> lk(mu);
-    for (auto& r : b->reqs) {
-      r->done = true;
+    for (auto& pt : b->parts) {
+      auto& r = pt.r;
+      r->parts_running--;
       r->status = HME_E_HIP;
       r->error = msg;
-      r->t_done = std::chrono::steady_clock::now();
+      if (--r->parts_left == 0) {
+        r->done = true;
+        r->t_done = std::chrono::steady_clock::now();
+        stats.completed++;
+      }
     }
     slots[b->slot].busy = false;
+    slots[b->slot].heavy = false;
     inflight--;
-    stats.completed += b->reqs.size();
+  }
+
+  // The pending part to start on a free slot, or pending.end().  Preference: the oldest part
+  // of a request with no part on the device, else the oldest part.  Two limits keep slots
+  // open for requests that arrive meanwhile: batches of a process evaluated in pieces (long
+  // ones, which take most of the device while they run) hold at most half of the slots, and a
+  // further part of a request already on the device starts only while another slot stays free.
+  std::deque<Part>::iterator pick_part() {
+    int nfree = 0, nheavy = 0;
+    for (const Slot& sl : slots) {
+      nfree += !sl.busy;
+      nheavy += sl.busy && sl.heavy;
+    }
+    const int nslots = (int)slots.size();
+    auto fresh = pending.end(), any = pending.end();
+    for (auto it = pending.begin(); it != pending.end(); ++it) {
+      if (nfree == 0) break;
+      const bool heavy = hme::handle_ws_bytes_per_event(handles[it->r->process]) > 0;
+      if (heavy && nslots > 1 && nheavy >= std::max(1, nslots / 2)) continue;
+      if (it->r->parts_running == 0) {
+        fresh = it;
+        break;
+      }
+      if (any == pending.end() && (nfree >= 2 || nslots == 1)) any = it;
+    }
+    return fresh != pending.end() ? fresh : any;
   }
 
   void run() {
@@ -237,29 +292,37 @@ struct Server : hme_server {
     std::unique_lock<std::mutex> lk(mu);
     for (;;) {
       int free_slot = -1;
+      std::deque<Part>::iterator hit;
       cv_sched.wait(lk, [&] {
+        if (stop && pending.empty()) return true;
         free_slot = -1;
         for (size_t k = 0; k < slots.size(); ++k)
           if (!slots[k].busy) {
             free_slot = (int)k;
             break;
           }
-        return (stop && pending.empty()) || (!pending.empty() && free_slot >= 0);
+        if (free_slot < 0) return false;
+        hit = pick_part();
+        return hit != pending.end();
       });
       if (pending.empty()) {
         if (stop) break;
         continue;
       }
-      // continuous batching: the oldest request first, then later ones of the same process
-      auto head = pending.front();
-      pending.pop_front();
+      // continuous batching: the chosen part, then later parts of the same process while
+      // they fit (a request's own parts only if nothing else is waiting)
+      const Part head = *hit;
+      pending.erase(hit);
       Batch* b = new Batch{this, free_slot, {head}};
-      const int64_t cap = capacity(head->process);
-      int64_t total = head->nevt;
-      for (auto it = pending.begin(); it != pending.end() && (int)b->reqs.size() < kMaxBatchReq;) {
-        if ((*it)->process == head->process && total + (*it)->nevt <= cap) {
-          total += (*it)->nevt;
-          b->reqs.push_back(*it);
+      head.r->parts_running++;
+      const int process = head.r->process;
+      const int64_t cap = part_events(process);
+      int64_t total = head.nevt;
+      for (auto it = pending.begin(); it != pending.end() && (int)b->parts.size() < kMaxBatchReq;) {
+        if (it->r->process == process && total + it->nevt <= cap && it->r != head.r) {
+          total += it->nevt;
+          it->r->parts_running++;
+          b->parts.push_back(*it);
           it = pending.erase(it);
         } else {
           ++it;
@@ -267,6 +330,7 @@ struct Server : hme_server {
       }
       Slot& sl = slots[free_slot];
       sl.busy = true;
+      sl.heavy = hme::handle_ws_bytes_per_event(handles[process]) > 0;
       inflight++;
       stats.batches++;
       stats.events += total;
@@ -274,22 +338,23 @@ struct Server : hme_server {
 
       BatchDesc* d = sl.h_desc;
       d->nevt_total = total;
-      d->nreq = (int64_t)b->reqs.size();
+      d->nreq = (int64_t)b->parts.size();
       int64_t off = 0;
-      for (size_t i = 0; i < b->reqs.size(); ++i) {
-        const auto& r = b->reqs[i];
-        d->req[i] = ReqDesc{r->mom, r->out, r->nevt, off, hme::handle_norm(handles[r->process], r->alpha_s)};
-        off += r->nevt;
+      const int npar = hme::handle_npar(handles[process]);
+      for (size_t i = 0; i < b->parts.size(); ++i) {
+        const Part& pt = b->parts[i];
+        const auto& r = pt.r;
+        d->req[i] = ReqDesc{r->mom + pt.offset * npar * 4, r->out + pt.offset, pt.nevt, off,
+                            hme::handle_norm(handles[r->process], r->alpha_s)};
+        off += pt.nevt;
       }
       hipGraphExec_t ex = nullptr;
-      hipError_t e = graph_for(sl, head->process, bucket_for(total, cap), &ex);
+      hipError_t e = graph_for(sl, process, bucket_for(total, capacity(process)), &ex);
       // requests submitted with a producer stream: the gather reads their momenta only after
-      // the work queued on that stream before the submit
-      for (auto& r : b->reqs) {
-        if (!r->ready) continue;
-        if (e == hipSuccess) e = hipStreamWaitEvent(sl.stream, r->ready, 0);
-        (void)hipEventDestroy(r->ready);  // released once the event has completed
-        r->ready = nullptr;
+      // the work queued on that stream before the submit (each part's batch waits on it)
+      for (auto& pt : b->parts) {
+        if (!pt.r->ready || e != hipSuccess) continue;
+        e = hipStreamWaitEvent(sl.stream, pt.r->ready, 0);
       }
       if (e == hipSuccess) e = hipGraphLaunch(ex, sl.stream);
       if (e == hipSuccess) e = hipLaunchHostFunc(sl.stream, &Server::on_batch_done, b);
@@ -378,7 +443,7 @@ static int submit_impl(hme_server* srv, int process, double alpha_s, int64_t nev
   if (nevt > 0 && (!momenta_dev || !me2_dev)) return srv_fail(HME_E_ARG, "hme_submit: NULL momenta or me2");
   if ((reinterpret_cast<uintptr_t>(momenta_dev) | reinterpret_cast<uintptr_t>(me2_dev)) & 7u)
     return srv_fail(HME_E_ARG, "hme_submit: pointers must be 8-byte aligned");
-  if (nevt > s->capacity(process)) return srv_fail(HME_E_BUDGET, "hme_submit: request larger than a slot");
+  if (s->capacity(process) < 1) return srv_fail(HME_E_BUDGET, "hme_submit: a slot holds no event of this process");
   auto r = std::make_shared<Request>();
   r->t_submit = std::chrono::steady_clock::now();
   r->process = process;
@@ -412,7 +477,11 @@ static int submit_impl(hme_server* srv, int process, double alpha_s, int64_t nev
       r->t_done = r->t_submit;
       s->stats.completed++;
     } else {
-      s->pending.push_back(r);
+      const int64_t part = s->part_events(process);
+      for (int64_t o = 0; o < nevt; o += part) {
+        s->pending.push_back(Part{r, o, std::min(part, nevt - o)});
+        r->parts_left++;
+      }
     }
   }
   s->cv_sched.notify_one();
@@ -447,6 +516,15 @@ int hme_wait_timed(hme_server* srv, uint64_t req_id, double timeout_s, double* l
     return srv_fail(HME_E_TIMEOUT, "hme_wait: timed out");
   }
   s->requests.erase(req_id);
+  // the producer-stream event of hme_submit_after: every part's batch has waited on it by now
+  if (r->ready) {
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(s->device);
+    (void)hipEventDestroy(r->ready);
+    (void)hipSetDevice(prev);
+    r->ready = nullptr;
+  }
   if (latency_s) *latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
   if (r->status != HME_OK) return srv_fail(r->status, "hme_wait: " + r->error);
   return r->status;
@@ -486,6 +564,8 @@ int hme_server_destroy(hme_server* srv) {
     if (sl.h_desc) (void)hipHostFree(sl.h_desc);
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
   }
+  for (auto& kv : s->requests)  // requests never waited for
+    if (kv.second->ready) (void)hipEventDestroy(kv.second->ready);
   (void)hipSetDevice(prev);
   for (auto* h : s->handles)
     if (h) hme_destroy(h);
