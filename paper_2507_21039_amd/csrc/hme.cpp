@@ -58,7 +58,7 @@ static const ProcEntry kProcs[] = {
     {info_uueeggg, launch_me2_uueeggg, launch_hel_uueeggg, false, 1000.0},
 };
 
-// events per sub-batch of a process evaluated in pieces (workspace nslot * ngood * sizeof(cx) bytes each)
+// events per sub-batch of a process evaluated in pieces (workspace nslot * nhel * sizeof(cx) bytes each)
 constexpr int64_t kChunkSubBatch = 8192;
 constexpr int kNumProcs = sizeof(kProcs) / sizeof(kProcs[0]);
 
@@ -322,7 +322,7 @@ bool handle_chunked(const hme_handle* h) { return h->info.nchunk > 0; }
 // partial jamp per slot and good helicity, in the type of the amplitudes
 int64_t handle_ws_bytes_per_event(const hme_handle* h) {
   const int64_t real = h->precision == HME_MIXED_FAST ? (int64_t)sizeof(float) : (int64_t)sizeof(double);
-  return handle_chunked(h) ? (int64_t)h->info.nslot * (int64_t)h->goodhel.size() * 2 * real : 0;
+  return handle_chunked(h) ? (int64_t)h->info.nslot * (int64_t)h->info.nhel * 2 * real : 0;
 }
 
 hipError_t launch_for_handle(const hme_handle* h, int64_t nevt_grid, const int64_t* nevt_dev, const double* mom,

@@ -21,11 +21,13 @@ namespace hme {
 // at most a fixed number of flows in registers; a flow's partial sum leaves its register
 // after its last term in the piece, or earlier when the register is needed, and is
 // written to a slot of its own in a device workspace
-//     ws[event][slot][good helicity]   (cx<float>, events of one sub-batch)
-// so that the LPE lanes of an event, which hold consecutive helicities, write
-// consecutive addresses (plain coalesced stores; no read-modify-write, no atomics).  A
-// last kernel adds up each flow's slots, forms the colour sum and reduces over
-// helicities as me2_kernel does.  Single precision only.
+//     ws[event][slot][helicity column]   (cx<float> or cx<double>, events of one sub-batch)
+// with Proc::nhel columns of which the good helicities take the first ngood, so that the
+// LPE lanes of an event, which hold consecutive helicities, write consecutive addresses
+// (plain coalesced stores; no read-modify-write, no atomics) and every slot sits at a
+// compile-time offset from the event's column (the colour kernel's 789 loads then need no
+// address registers of their own).  A last kernel adds up each flow's slots, forms the
+// colour sum and reduces over helicities as me2_kernel does.
 
 // Events in a sub-batch: at most nevt (which sizes the grid); when a captured graph reads
 // the batch's event count from device memory, only those left after the sub-batch's
@@ -43,9 +45,57 @@ HME_FN int64_t sub_batch_events(int64_t nevt, const int64_t* nevt_dev, int64_t e
 // (float for HME_MIXED_FAST, double for HME_FP64 and HME_MIXED_PAPER).
 template <class T> struct WorkspaceSink {
   cx<T>* base;
-  int64_t stride;  // entries between consecutive slots (the number of good helicities)
+  int64_t stride;  // entries between consecutive slots (Proc::nhel, a compile-time constant)
   HME_FN void put(int slot, cx<T> v) const { base[slot * stride] = v; }
 };
+
+// One lane's helicity column of an event's workspace, read with buffer loads: the event's
+// slots in a buffer descriptor (wave-uniform base, bounds = the event's slots), the lane's
+// column as the vector offset and each slot's offset, a compile-time constant in the gather,
+// as the scalar offset.  The gather's 789 loads then take no address registers or address
+// arithmetic, which leaves the registers for loads in flight.
+template <class S> struct WsColumn {
+  __amdgpu_buffer_rsrc_t rsrc;
+  int lane_bytes;
+  // word 3 of a raw (untyped, unswizzled) buffer descriptor on the gfx9 family
+  static constexpr int kRawBufferFlags = 0x00020000;
+  template <class Proc> HME_FN static WsColumn make(const cx<S>* event_base, int column) {
+    constexpr int bytes = Proc::nslot * Proc::nhel * (int)sizeof(cx<S>);
+    return WsColumn{__builtin_amdgcn_make_buffer_rsrc(const_cast<cx<S>*>(event_base), 0, bytes, kRawBufferFlags),
+                    column * (int)sizeof(cx<S>)};
+  }
+  HME_FN cx<S> operator[](int64_t i) const {
+    const int off = (int)(i * (int64_t)sizeof(cx<S>));
+    // the words are copied out of the vector before reinterpretation (a bit cast of a vector
+    // element in place reads element 0 with this compiler)
+    if constexpr (sizeof(S) == 4) {
+      const auto v = __builtin_amdgcn_raw_buffer_load_b64(rsrc, lane_bytes, off, 0);
+      const unsigned re = v[0], im = v[1];
+      return cx<S>{__uint_as_float(re), __uint_as_float(im)};
+    } else {
+      const auto v = __builtin_amdgcn_raw_buffer_load_b128(rsrc, lane_bytes, off, 0);
+      const unsigned r0 = v[0], r1 = v[1], i0 = v[2], i1 = v[3];
+      return cx<S>{__hiloint2double((int)r1, (int)r0), __hiloint2double((int)i1, (int)i0)};
+    }
+  }
+};
+
+// The jamps of one helicity column k of an event's workspace w.  Double-precision slots (16 B)
+// are read through a buffer descriptor with constant slot offsets.  Single-precision slots are
+// read through a plain pointer with the stride hidden from the optimiser: with constant offsets
+// the compiler keeps a 64-bit address per load in flight and runs out of registers, while a
+// running pointer advanced by scalar strides keeps the gather's loads in flight (measured on the
+// compiled code: 25 against 541 waits for all loads of the colour kernel).
+template <class Proc, class T, class S>
+HME_FN void gather_column(const cx<S>* w, int k, cx<T> (&jamp)[Proc::ncol]) {
+  if constexpr (sizeof(S) == 8) {
+    Proc::template gather<T, S>(WsColumn<S>::template make<Proc>(w, k), Proc::nhel, jamp);
+  } else {
+    int64_t stride = Proc::nhel;
+    asm volatile("" : "+s"(stride));
+    Proc::template gather<T, S>(w + k, stride, jamp);
+  }
+}
 
 // Single-precision pieces are compiled for 2 waves per SIMD (at most 256 VGPRs): the generator's
 // budgets keep them within it or a few registers above, which the compiler then spills; one wave
@@ -78,9 +128,9 @@ __global__ void __launch_bounds__(256, piece_waves<T>())
   build_event_table<Proc, LPE>(p, prm, sub, msums + (threadIdx.x / LPE) * 8 * Proc::nsum, tab);
   __syncthreads();
   if (ev >= nevt) return;  // no barrier follows
-  cx<T>* w = ws + (size_t)ev * Proc::nslot * ngood;
+  cx<T>* w = ws + (size_t)ev * Proc::nslot * Proc::nhel;
   for (int k = sub; k < ngood; k += LPE) {
-    WorkspaceSink<T> sink{w + k, ngood};
+    WorkspaceSink<T> sink{w + k, Proc::nhel};
     Chunk::template amplitudes<T>(prm, (unsigned)goodhel[k], (tab_of<T>)tab, sink);
   }
 }
@@ -93,6 +143,7 @@ __global__ void __launch_bounds__(256)
     colour_kernel(const cx<S>* __restrict__ ws, double* __restrict__ out, int64_t nevt, int ngood,
                   double norm, int per_hel, const int64_t* __restrict__ nevt_dev, int64_t e0) {
   constexpr int EPW = 64 / LPE, EPB = 256 / LPE;
+  static_assert(LPE == 64, "one event per wavefront: the workspace descriptor is wave-uniform");
   const int lane = threadIdx.x & 63;
   nevt = sub_batch_events(nevt, nevt_dev, e0);
   if ((int64_t)blockIdx.x * EPB >= nevt) return;
@@ -100,11 +151,11 @@ __global__ void __launch_bounds__(256)
   const int64_t ev = ((int64_t)blockIdx.x * 4 + wib) * EPW + lane / LPE;
   const int sub = lane % LPE;
   const int64_t evc = ev < nevt ? ev : nevt - 1;
-  const cx<S>* w = ws + (size_t)evc * Proc::nslot * ngood;
+  const cx<S>* w = ws + (size_t)evc * Proc::nslot * Proc::nhel;
   double acc = 0.0;
   for (int k = sub; k < ngood; k += LPE) {
     cx<C> jamp[Proc::ncol];
-    Proc::template gather<C, S>(w + k, ngood, jamp);
+    gather_column<Proc, C, S>(w, k, jamp);
     const double v = (double)Proc::template colour_sum<C>(jamp);
     if (per_hel && ev < nevt) out[(size_t)ev * ngood + k] = v;
     acc += v;
@@ -139,7 +190,7 @@ __global__ void __launch_bounds__(256)
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t ev = (int64_t)blockIdx.x * 4 + wib;
   if (ev >= nevt) return;  // wave-uniform; no barrier follows
-  const cx<S>* w = ws + (size_t)ev * Proc::nslot * ngood;
+  const cx<S>* w = ws + (size_t)ev * Proc::nslot * Proc::nhel;
   double acc = 0.0;
   [[maybe_unused]] double mpass[Select ? NPASS : 1];
   if constexpr (Select) {
@@ -150,7 +201,7 @@ __global__ void __launch_bounds__(256)
     const int k = g + lane;
     const bool valid = k < ngood;
     cx<float> jamp[NCOL];
-    Proc::template gather<float, S>(w + (valid ? k : 0), ngood, jamp);
+    gather_column<Proc, float, S>(w, valid ? k : 0, jamp);
     if (!valid) {
 #pragma unroll
       for (int f = 0; f < NCOL; ++f) jamp[f] = {0.f, 0.f};
@@ -206,7 +257,7 @@ __global__ void __launch_bounds__(256)
 
 struct ChunkArgs {
   const double* mom;  // momenta of the sub-batch's first event
-  void* ws;           // workspace, nevt * nslot * ngood entries of cx<float> (f64 = 0) or cx<double>
+  void* ws;           // workspace, nevt * nslot * nhel entries of cx<float> (f64 = 0) or cx<double>
   int64_t nevt;       // events in the sub-batch
   const int* goodhel;
   int ngood;

@@ -37,6 +37,7 @@ FLOPS["vvv_vec_k"] = FLOPS["vvv_vec"] - 18
 FLOPS["ffv_psi_k"] = FLOPS["ffv_psi"] - 10
 FLOPS["ffv_psibar_k"] = FLOPS["ffv_psibar"] - 10
 FLOPS["vvv_amp_k"] = FLOPS["vvv_amp"] - 12
+GATHER_GROUP = 24  # workspace loads written ahead of their use in the gather
 VK_SIZE = {"vvv": 12, "psi": 5, "amp3": 12, "fd": 8}  # doubles per vertex kit
 VK_FLOPS = {"vvv": 24, "psi": 7, "amp3": 12, "fd": 16}  # per event, in the table
 FD_FLOPS = 2 * 14 + 4 * 2 * 4  # the gauge projection of a gluon current: two dots, four updates
@@ -604,15 +605,35 @@ struct {name}_c{c} {{
     assert all(abs(N[i][j]) < 32768 for i in range(ncol) for j in range(ncol))
     gather_code = ""
     if chunks:
-        gl_lines = []
+        # flows in groups of about GATHER_GROUP slots: a group's loads are written before its
+        # sums, so that many loads are in flight whatever order the compiler would pick
+        gl_lines, group, nload = [], [], 0
+
+        def flush():
+            if not group:
+                return
+            gl_lines.append("    {")
+            for _, sls in group:
+                gl_lines.extend(f"      const auto s{sl} = col[{sl} * stride];" for sl in sls)
+            for i, sls in group:
+                gl_lines.append(f"      jamp[{i}] = " + " + ".join(f"cast<T>(s{sl})" for sl in sls) + ";")
+            gl_lines.append("    }")
+            group.clear()
+
         for i, w in enumerate(basis):
-            terms = " + ".join(f"cast<T>(col[{sl} * stride])" for sl in sorted(partials[w]))
-            gl_lines.append(f"    jamp[{i}] = {terms};")
+            sls = sorted(partials[w])
+            if group and nload + len(sls) > GATHER_GROUP:
+                flush()
+                nload = 0
+            group.append((i, sls))
+            nload += len(sls)
+        flush()
         gather_code = (
-            "  // the jamps of one helicity from the workspace column `col` (slot s at col[s * stride]):\n"
-            "  // each flow is the sum of its partial slots, added in slot order\n"
-            "  template <class T, class S>\n"
-            f"  HME_FN static void gather(const cx<S>* col, int64_t stride, cx<T> (&jamp)[{ncol}]) {{\n"
+            "  // the jamps of one helicity from the workspace column `col` (slot s at col[s * stride];\n"
+            "  // col: a pointer to cx<S>, or an accessor with the same indexing): each flow is the sum of\n"
+            "  // its partial slots, added in slot order; the loads of a group of flows come first\n"
+            "  template <class T, class S, class Col>\n"
+            f"  HME_FN static void gather(const Col& col, int64_t stride, cx<T> (&jamp)[{ncol}]) {{\n"
             + "\n".join(gl_lines) + "\n  }\n\n")
         amp_section = (f"  // the amplitude terms are split into {len(chunk_out)} contiguous pieces of the schedule\n"
                        f"  // ({name}_c0 .. {name}_c{len(chunk_out) - 1}); each runs as its own kernel and adds\n"

@@ -168,9 +168,13 @@ def test_pieces_cover_every_term_once():
     assert nterms == 1890
     assert sorted(puts) == list(range(info["nslot"]))
     main = open(os.path.join(procs, "ggttggg.h")).read()
+    # the gather loads slot s into a temporary s<s> (col[s * stride]) and sums temporaries per flow
+    loads = {int(a): int(b) for a, b in re.findall(r"const auto s(\d+) = col\[(\d+) \* stride\];", main)}
+    assert all(a == b for a, b in loads.items())
+    assert sorted(loads) == list(range(info["nslot"]))
     gathered = {}
-    for flow, rhs in re.findall(r"jamp\[(\d+)\] = (cast<T>\(col.*);", main):
-        gathered[int(flow)] = [int(x) for x in re.findall(r"col\[(\d+) \* stride\]", rhs)]
+    for flow, rhs in re.findall(r"jamp\[(\d+)\] = (cast<T>\(s.*);", main):
+        gathered[int(flow)] = [int(x) for x in re.findall(r"cast<T>\(s(\d+)\)", rhs)]
     assert sorted(gathered) == list(range(120))
     assert sorted(x for v in gathered.values() for x in v) == list(range(info["nslot"]))
 
