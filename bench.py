@@ -24,23 +24,26 @@ PEAK_FP32_VALU = 157.3e12  # published FP32 vector peak (twice the FP64 rate)
 PEAK_HBM = 8.0e12
 
 # HBM traffic of one FP64 gg -> ttbar gg launch (1,048,576 events) from rocprofv3 counters
-# (profiles/me2_ggttgg_1M_traffic.md): FETCH_SIZE and WRITE_SIZE in KiB, each scaled by what the
-# counter reads for a plain 256 MiB device copy.  Valid only for the kernel sources it was taken
-# on (sha256 prefix of me2_kernels.h + colour_mfma.h + helas.h + procs/ggttgg.h); otherwise
-# traffic is null.
-TRAFFIC = {"source_sha": "f64fa9a3ee127763", "nevt": 1048576,
-           "fetch_kib": 198114.5, "write_kib": 8192.0, "fetch_factor": 262144 / 131088.875, "write_factor": 1.0}
+# (profiles/me2_ggttgg_1M_traffic.md): L2-to-memory read requests by size (TCC_EA0_RDREQ_32B/64B/
+# 128B) and WRITE_SIZE.  Calibrated on kernels of known traffic: a 256 MiB copy and a 256 MiB
+# read-only sum issue 2,097,152 requests of 128 B (exactly 256 MiB, factor 1.000; FETCH_SIZE, which
+# counts a 128 B request as 64 B on this part, reads half); a 256 MiB fill writes WRITE_SIZE =
+# 262,144 KiB (factor 1.000).  Valid only for the kernel sources it was taken on (sha256 prefix of
+# me2_kernels.h + colour_mfma.h + helas.h + procs/ggttgg.h); otherwise traffic is null.
+TRAFFIC = {"source_sha": "2c165627f28910db", "nevt": 1048576,
+           "rdreq_32b": 0, "rdreq_64b": 3166971, "rdreq_128b": 96, "fetch_size_kib": 197941.3125,
+           "write_kib": 8192.0, "write_factor": 1.0}
 
 # VALU and MFMA instruction counters of the same launches (profiles/me2_ggttgg_1M_valu_counters.md),
 # wave instructions summed over the device: FLOPs = 64 lanes x (2 FMA + ADD + MUL + TRANS) plus
 # 512 per MFMA "MOPS" unit (the counter's own scale).
 COUNTERS = {
-    "source_sha": "f64fa9a3ee127763", "nevt": 1048576,
-    "fp64": {"FMA_F64": 16571695104, "ADD_F64": 2621440000, "MUL_F64": 3951034368, "TRANS_F64": 45088768,
-             "VALU": 23765975040},
-    "mixed_fast": {"FMA_F32": 13015973888, "ADD_F32": 2454716416, "MUL_F32": 3052404736, "TRANS_F32": 0,
-                   "FMA_F64": 392167424, "ADD_F64": 30408704, "MUL_F64": 147849216, "TRANS_F64": 40894464,
-                   "MFMA_MOPS_BF16": 2684354560, "VALU": 20260585472},
+    "source_sha": "2c165627f28910db", "nevt": 1048576,
+    "fp64": {"FMA_F64": 12622753688, "ADD_F64": 3183477086, "MUL_F64": 3064986948, "TRANS_F64": 45088068,
+             "VALU": 19544400714},
+    "mixed_fast": {"FMA_F32": 11638145024, "ADD_F32": 2503999488, "MUL_F32": 2757754880, "TRANS_F32": 0,
+                   "FMA_F64": 326107136, "ADD_F64": 694157312, "MUL_F64": 223346688, "TRANS_F64": 45088768,
+                   "MFMA_MOPS_BF16": 2684354560, "VALU": 19425918976},
 }
 
 
@@ -70,9 +73,11 @@ def kernel_source_sha() -> str:
 
 
 def measured_traffic(nevt: int):
+    """HBM bytes per launch (read requests by size + calibrated WRITE_SIZE), or None."""
     if kernel_source_sha() != TRAFFIC["source_sha"] or nevt != TRAFFIC["nevt"]:
         return None
-    return 1024 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_factor"] + TRAFFIC["write_kib"] * TRAFFIC["write_factor"])
+    read = 32 * TRAFFIC["rdreq_32b"] + 64 * TRAFFIC["rdreq_64b"] + 128 * TRAFFIC["rdreq_128b"]
+    return read + 1024 * TRAFFIC["write_kib"] * TRAFFIC["write_factor"]
 
 
 def log(msg):
@@ -206,6 +211,42 @@ def e2e_leg(card, steps=5, warmup=2):
             "ms_rambo": per[0] * 1e3, "ms_me2": per[1] * 1e3, "ms_sum": per[2] * 1e3,
             "rambo_written_gbps": rambo_bytes / per[0] / 1e9,
             "sigma_pb": sigma, "sigma_err_pb": err, "points": n * (warmup + steps)}
+
+
+def pcie_leg(card, p, steps=5, warmup=2):
+    """gg -> ttbar gg FP64 with the batch handed over in host memory (pinned): momenta copied to
+    the device, |M|^2, |M|^2 copied back, all on one stream and timed there.  The library's
+    boundary takes device pointers; this is the rate a caller holding host buffers sees."""
+    import torch
+
+    import paper_2507_21039_amd as hme
+    from workloads import configs
+    n = p.shape[0]
+    host_in = torch.empty(p.shape, dtype=torch.float64, pin_memory=True)
+    host_in.numpy()[...] = p
+    host_out = torch.empty(n, dtype=torch.float64, pin_memory=True)
+    mom = torch.empty(p.shape, dtype=torch.float64, device="cuda")
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    t = np.zeros(3)
+    with hme.Handle(configs.GGTTGG, card, hme.FP64) as h:
+        for step in range(warmup + steps):
+            ev[0].record(stream)
+            mom.copy_(host_in, non_blocking=True)
+            ev[1].record(stream)
+            h.compute(mom, out, 0.118, stream)
+            ev[2].record(stream)
+            host_out.copy_(out, non_blocking=True)
+            ev[3].record(stream)
+            torch.cuda.synchronize()
+            if step >= warmup:
+                t += [ev[i].elapsed_time(ev[i + 1]) / 1e3 for i in range(3)]
+    per = t / steps
+    return {"value": n / per.sum(), "unit": "events/s", "nevt": n, "steps": steps,
+            "ms_h2d": per[0] * 1e3, "ms_me2": per[1] * 1e3, "ms_d2h": per[2] * 1e3,
+            "h2d_gbps": p.nbytes / per[0] / 1e9, "d2h_gbps": n * 8 / per[2] / 1e9,
+            "note": "not the headline value: the headline times |M|^2 on momenta already in HBM"}
 
 
 def select_leg(card, steps=3, warmup=1):
@@ -369,7 +410,16 @@ def served_leg(card, precision, nwarm=200, ntimed=3000, budget=32 << 30, nstream
         srv.close()
     timed = lat[nwarm:]
     span = arrival[-1] - arrival[nwarm]
+    by_proc = {}
+    for p in procs_avail:
+        sel = procs[nwarm:] == p
+        if sel.any():
+            by_proc[hme.PROCESS_NAMES[p]] = {"requests": int(sel.sum()),
+                                             "p50_ms": float(np.median(timed[sel]) * 1e3),
+                                             "p99_ms": float(np.quantile(timed[sel], 0.99) * 1e3),
+                                             "max_ms": float(timed[sel].max() * 1e3)}
     return {"p50_ms": float(np.median(timed) * 1e3), "p99_ms": float(np.quantile(timed, 0.99) * 1e3),
+            "by_process": by_proc,
             "mean_ms": float(timed.mean() * 1e3), "max_ms": float(timed.max() * 1e3),
             "requests": int(ntimed), "warmup_requests": int(nwarm),
             "offered_events_per_s": float(nevt[nwarm:].sum() / span), "offered_requests_per_s": float(ntimed / span),
@@ -486,7 +536,7 @@ def main():
                    "good_helicities": f64["ngoodhel"], "colour_flows": 24},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": measured_traffic(nevt),
-                     "traffic_unit": "bytes per launch (HBM, counter-based)",
+                     "traffic_unit": "bytes per launch (HBM: L2 read requests by size + WRITE_SIZE)",
                      "algorithmic_bytes": 200 * nevt, "flops_per_event": f64["flops_per_event"],
                      "counter_achieved": counter_achieved / 1e12 if counter_achieved else None,
                      "counter_frac": counter_achieved / PEAK_FP64_VALU if counter_achieved else None,
@@ -525,6 +575,10 @@ def main():
         log("[bench] end-to-end flat Monte Carlo (device RAMBO + FP64 |M|^2 + sum)")
         line["e2e"] = e2e_leg(card)
         log(f"[bench] e2e: {line['e2e']['value']:.4g} events/s, rambo {line['e2e']['ms_rambo']:.3f} ms")
+        log("[bench] host buffers (pinned H2D, FP64 |M|^2, D2H)")
+        line["e2e"]["host_buffers"] = pcie_leg(card, p)
+        log(f"[bench] host buffers: {line['e2e']['host_buffers']['value']:.4g} events/s, "
+            f"H2D {line['e2e']['host_buffers']['h2d_gbps']:.1f} GB/s")
     if not args.no_select:
         log("[bench] helicity and colour-flow choice")
         line["select"] = select_leg(card)
