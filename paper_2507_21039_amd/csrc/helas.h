@@ -187,20 +187,43 @@ HME_FN vw4<double> vxxxxx(const double* k, int lam, int nsv) {
 }
 
 // ------------------------------------------------------------------ fermion-vector vertices
-// Shorthands for a vector V: vp = V0 + V3, vm = V0 - V3, vt = V1 + i V2, vtb = V1 - i V2, so that
-// sigma.V = [[vm, -vtb], [-vt, vp]] and sigmabar.V = [[vp, vtb], [vt, vm]].
+// Light-cone components of a vector V: vp = V0 + V3, vm = V0 - V3, vt = V1 + i V2,
+// vtb = V1 - i V2, so that sigma.V = [[vm, -vtb], [-vt, vp]] and sigmabar.V = [[vp, vtb], [vt, vm]].
+// The fermion vertices use V only through these.  A vector built in the kernel is converted at
+// each use (vlc_of); the external gluons and the recycled currents also keep their light-cone
+// form in the per-event table, so that their uses in fermion vertices start from it.  An
+// external massless gluon has V0 = Im V3 = 0, so its vp = -vm is real (vlcx).
+template <class T> struct vlc {
+  cx<T> p, m, t, tb;
+};
+template <class T> struct vlcx {
+  T p;
+  cx<T> t, tb;
+};
+template <class T> HME_FN vlc<T> vlc_of(const vw4<T>& V) {
+  return {V.c[0] + V.c[3], V.c[0] - V.c[3], V.c[1] + mul_i(V.c[2]), V.c[1] - mul_i(V.c[2])};
+}
 
 // Amplitude fbar V-slash f (ALOHA-style "FFV1_0").
 // Grouped by the vector's components: vm (fb0 f2 + fb3 f1) + vp (fb1 f3 + fb2 f0)
 // + vtb (fb2 f1 - fb0 f3) + vt (fb3 f0 - fb1 f2).
+template <class T> struct ffv_bilinears {
+  cx<T> p1, p2, p3, p4;
+};
+template <class T> HME_FN ffv_bilinears<T> ffv_amp_bilinears(const sp4<T>& fb, const sp4<T>& f) {
+  return {cfma(fb.c[3], f.c[1], fb.c[0] * f.c[2]), cfma(fb.c[2], f.c[0], fb.c[1] * f.c[3]),
+          cfms(fb.c[0], f.c[3], fb.c[2] * f.c[1]), cfms(fb.c[1], f.c[2], fb.c[3] * f.c[0])};
+}
+template <class T> HME_FN cx<T> ffv_amp(const sp4<T>& fb, const sp4<T>& f, const vlc<T>& v) {
+  const ffv_bilinears<T> b = ffv_amp_bilinears(fb, f);
+  return cfma(v.t, b.p4, cfma(v.tb, b.p3, cfma(v.p, b.p2, v.m * b.p1)));
+}
+template <class T> HME_FN cx<T> ffv_amp(const sp4<T>& fb, const sp4<T>& f, const vlcx<T>& v) {
+  const ffv_bilinears<T> b = ffv_amp_bilinears(fb, f);
+  return cfma(v.t, b.p4, cfma(v.tb, b.p3, rfma(v.p, b.p2, (-v.p) * b.p1)));
+}
 template <class T> HME_FN cx<T> ffv_amp(const sp4<T>& fb, const sp4<T>& f, const vw4<T>& V) {
-  const cx<T> vp = V.c[0] + V.c[3], vm = V.c[0] - V.c[3];
-  const cx<T> vt = V.c[1] + mul_i(V.c[2]), vtb = V.c[1] - mul_i(V.c[2]);
-  const cx<T> p1 = cfma(fb.c[3], f.c[1], fb.c[0] * f.c[2]);
-  const cx<T> p2 = cfma(fb.c[2], f.c[0], fb.c[1] * f.c[3]);
-  const cx<T> p3 = cfms(fb.c[0], f.c[3], fb.c[2] * f.c[1]);
-  const cx<T> p4 = cfms(fb.c[1], f.c[2], fb.c[3] * f.c[0]);
-  return cfma(vt, p4, cfma(vtb, p3, cfma(vp, p2, vm * p1)));
+  return ffv_amp(fb, f, vlc_of(V));
 }
 
 // Same with chiral couplings gamma^mu (gL P_L + gR P_R).
@@ -390,6 +413,23 @@ template <class S> HME_FN void vector_kit(const double* k, int nsv, S* kit) {
   }
 }
 
+// The same states in light-cone form for the fermion vertices: for lam = +1 then lam = -1,
+// (vp, Re vt, Im vt, Re vtb, Im vtb) with vp = Re eps3 = -vm (eps0 = Im eps3 = 0), formed in
+// double from the kit above and rounded once.
+template <class S> HME_FN void vector_lc_kit(const double* k, int nsv, S* kit) {
+  double c[10];
+  vector_kit(k, nsv, c);
+  for (int h = 0; h < 2; ++h) {
+    const double* e = c + 5 * h;  // Re eps1, Re eps2, Re eps3, Im eps1, Im eps2
+    S* o = kit + 5 * h;
+    o[0] = S(e[2]);
+    o[1] = S(e[0] - e[4]);  // vt = eps1 + i eps2
+    o[2] = S(e[3] + e[1]);
+    o[3] = S(e[0] + e[4]);  // vtb = eps1 - i eps2
+    o[4] = S(e[3] - e[1]);
+  }
+}
+
 // Fermion states for lam = +1 then lam = -1, each 4 complex components as (re, im) pairs:
 // kind 1, ubar(p, lam) of an outgoing fermion (oxxxxx with nsf = +1); kind 2, v(p, lam) of an
 // outgoing antifermion (ixxxxx with nsf = -1); kind 3, vbar(p, lam) of an incoming antifermion
@@ -464,6 +504,11 @@ template <class T, class S> HME_FN sp4<T> ixxxxx_kit(const volatile HME_LDS S* k
   return spinor_from<T>(load_kit<T, 8>(kit + (lam > 0 ? 0 : 8)));
 }
 
+template <class T, class S> HME_FN vlcx<T> vxxxxx_lc_kit(const volatile HME_LDS S* kit, int lam) {
+  const kitv<T, 5> k = load_kit<T, 5>(kit + (lam > 0 ? 0 : 5));
+  return {k.v[0], {k.v[1], k.v[2]}, {k.v[3], k.v[4]}};
+}
+
 // Observer of the amplitude terms in the generated code: term(d, a) for each term a of diagram
 // d.  The default does nothing (and costs nothing).
 struct NoObserver {
@@ -486,6 +531,20 @@ template <class T, class S> HME_FN vw4<T> recycled_vw4(const volatile HME_LDS S*
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu) w.c[mu] = {k.v[2 * mu], k.v[2 * mu + 1]};
   return w;
+}
+template <class T, class S> HME_FN void store_lc(const vlc<T>& x, S* o) {
+  o[0] = x.p.r;
+  o[1] = x.p.i;
+  o[2] = x.m.r;
+  o[3] = x.m.i;
+  o[4] = x.t.r;
+  o[5] = x.t.i;
+  o[6] = x.tb.r;
+  o[7] = x.tb.i;
+}
+template <class T, class S> HME_FN vlc<T> recycled_vlc(const volatile HME_LDS S* p, int off) {
+  const kitv<T, 8> k = load_kit<T, 8>(p + off);
+  return {{k.v[0], k.v[1]}, {k.v[2], k.v[3]}, {k.v[4], k.v[5]}, {k.v[6], k.v[7]}};
 }
 template <class T, class S> HME_FN sp4<T> recycled_sp4(const volatile HME_LDS S* p, int off) {
   const kitv<T, 8> k = load_kit<T, 8>(p + off);
@@ -526,14 +585,10 @@ HME_FN cx<T> vvv_amp_k(const vw4<T>& a, const vw4<T>& b, const vw4<T>& c, const 
   return cfma(mdot(c, a), mdot(k.v + 8, b), cfma(mdot(b, c), mdot(k.v + 4, a), mdot(a, b) * mdot(k.v, c)));
 }
 
-// ffv_psi / ffv_psibar with k = den (K0 + K3, K0 - K3, K1, K2, m).
-template <class T> HME_FN sp4<T> ffv_psi_k(const sp4<T>& f, const vw4<T>& V, const kitv<T, 5>& k) {
-  const cx<T> vp = V.c[0] + V.c[3], vm = V.c[0] - V.c[3];
-  const cx<T> vt = V.c[1] + mul_i(V.c[2]), vtb = V.c[1] - mul_i(V.c[2]);
-  const cx<T> g0 = cfms(vtb, f.c[3], vm * f.c[2]);
-  const cx<T> g1 = cfms(vt, f.c[2], vp * f.c[3]);
-  const cx<T> g2 = cfma(vtb, f.c[1], vp * f.c[0]);
-  const cx<T> g3 = cfma(vm, f.c[1], vt * f.c[0]);
+// ffv_psi / ffv_psibar with k = den (K0 + K3, K0 - K3, K1, K2, m), from the products g / h of
+// V-slash and the spinor.
+template <class T> HME_FN sp4<T> psi_out(const cx<T>& g0, const cx<T>& g1, const cx<T>& g2, const cx<T>& g3,
+                                        const kitv<T, 5>& k) {
   const T kp = k.v[0], km = k.v[1], md = k.v[4];
   const cx<T> kt = {k.v[2], k.v[3]}, ktb = {k.v[2], -k.v[3]};
   sp4<T> o;
@@ -543,13 +598,20 @@ template <class T> HME_FN sp4<T> ffv_psi_k(const sp4<T>& f, const vw4<T>& V, con
   o.c[3] = cfma(kt, g0, rfma(md, g3, km * g1));
   return o;
 }
-template <class T> HME_FN sp4<T> ffv_psibar_k(const sp4<T>& fb, const vw4<T>& V, const kitv<T, 5>& k) {
-  const cx<T> vp = V.c[0] + V.c[3], vm = V.c[0] - V.c[3];
-  const cx<T> vt = V.c[1] + mul_i(V.c[2]), vtb = V.c[1] - mul_i(V.c[2]);
-  const cx<T> h0 = cfma(fb.c[3], vt, fb.c[2] * vp);
-  const cx<T> h1 = cfma(fb.c[3], vm, fb.c[2] * vtb);
-  const cx<T> h2 = cfms(fb.c[1], vt, fb.c[0] * vm);
-  const cx<T> h3 = cfms(fb.c[0], vtb, fb.c[1] * vp);
+template <class T> HME_FN sp4<T> ffv_psi_k(const sp4<T>& f, const vlc<T>& v, const kitv<T, 5>& k) {
+  return psi_out(cfms(v.tb, f.c[3], v.m * f.c[2]), cfms(v.t, f.c[2], v.p * f.c[3]),
+                 cfma(v.tb, f.c[1], v.p * f.c[0]), cfma(v.m, f.c[1], v.t * f.c[0]), k);
+}
+template <class T> HME_FN sp4<T> ffv_psi_k(const sp4<T>& f, const vlcx<T>& v, const kitv<T, 5>& k) {
+  return psi_out(cfms(v.tb, f.c[3], (-v.p) * f.c[2]), cfms(v.t, f.c[2], v.p * f.c[3]),
+                 cfma(v.tb, f.c[1], v.p * f.c[0]), rfma(-v.p, f.c[1], v.t * f.c[0]), k);
+}
+template <class T> HME_FN sp4<T> ffv_psi_k(const sp4<T>& f, const vw4<T>& V, const kitv<T, 5>& k) {
+  return ffv_psi_k(f, vlc_of(V), k);
+}
+
+template <class T> HME_FN sp4<T> psibar_out(const cx<T>& h0, const cx<T>& h1, const cx<T>& h2, const cx<T>& h3,
+                                           const kitv<T, 5>& k) {
   const T kp = k.v[0], km = k.v[1], md = k.v[4];
   const cx<T> kt = {k.v[2], k.v[3]}, ktb = {k.v[2], -k.v[3]};
   sp4<T> o;
@@ -558,6 +620,17 @@ template <class T> HME_FN sp4<T> ffv_psibar_k(const sp4<T>& fb, const vw4<T>& V,
   o.c[2] = cfms(kt, h1, rfma(md, h2, km * h0));
   o.c[3] = cfms(ktb, h0, rfma(md, h3, kp * h1));
   return o;
+}
+template <class T> HME_FN sp4<T> ffv_psibar_k(const sp4<T>& fb, const vlc<T>& v, const kitv<T, 5>& k) {
+  return psibar_out(cfma(fb.c[3], v.t, fb.c[2] * v.p), cfma(fb.c[3], v.m, fb.c[2] * v.tb),
+                    cfms(fb.c[1], v.t, fb.c[0] * v.m), cfms(fb.c[0], v.tb, fb.c[1] * v.p), k);
+}
+template <class T> HME_FN sp4<T> ffv_psibar_k(const sp4<T>& fb, const vlcx<T>& v, const kitv<T, 5>& k) {
+  return psibar_out(cfma(fb.c[3], v.t, v.p * fb.c[2]), rfma(-v.p, fb.c[3], fb.c[2] * v.tb),
+                    cfms(fb.c[1], v.t, (-v.p) * fb.c[0]), cfms(fb.c[0], v.tb, v.p * fb.c[1]), k);
+}
+template <class T> HME_FN sp4<T> ffv_psibar_k(const sp4<T>& fb, const vw4<T>& V, const kitv<T, 5>& k) {
+  return ffv_psibar_k(fb, vlc_of(V), k);
 }
 
 // ------------------------------------------------------------------ compensated per-event arithmetic

@@ -37,6 +37,14 @@ FLOPS["vvv_vec_k"] = FLOPS["vvv_vec"] - 18
 FLOPS["ffv_psi_k"] = FLOPS["ffv_psi"] - 10
 FLOPS["ffv_psibar_k"] = FLOPS["ffv_psibar"] - 10
 FLOPS["vvv_amp_k"] = FLOPS["vvv_amp"] - 12
+# fermion vertices whose vector comes in light-cone form from the table: no shorthands (8); an
+# external gluon's real vp = -vm also makes two complex products real ones (amplitude) or four
+# (currents)
+for _r in ("ffv_amp", "ffv_psi_k", "ffv_psibar_k"):
+    FLOPS[_r + ":lc"] = FLOPS[_r] - 8
+    FLOPS[_r + ":lcx"] = FLOPS[_r] - 8 - (8 if _r == "ffv_amp" else 16)
+LC_KIT_FLOPS = 8  # light-cone form of an external gluon's kit (both helicities), per event
+LC_REC_FLOPS = 8  # light-cone form of a recycled current (one helicity pair), per event
 GATHER_GROUP = 24  # workspace loads written ahead of their use in the gather
 VK_SIZE = {"vvv": 12, "psi": 5, "amp3": 12, "fd": 8}  # doubles per vertex kit
 VK_FLOPS = {"vvv": 24, "psi": 7, "amp3": 12, "fd": 16}  # per event, in the table
@@ -229,6 +237,8 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
             if key[0] != "E" and all(a[0] == "E" and g.nodes[a].kind in ("ext_v", "ext_o", "ext_i")
                                      for a in n.args) and len(n.args) == 2:
                 rec[key] = len(rec)
+    # the recycled currents (vectors) also keep their light-cone form, for the fermion vertices
+    rec_lc = {key: i for i, key in enumerate(k for k in rec if g.nodes[k].kind in ("vvv", "qq"))}
     # recycled wavefunctions: kind (0 three-gluon current, 1 spinor current, 2 barred spinor
     # current, 3 quark pair), the particles of the two external arguments, and the offset of
     # the vertex kit (kinds 0-2, in the vertex-kit region) or the index of the denominator (3);
@@ -252,7 +262,7 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
         if fd and n.kind in ("vvv", "qq"):
             vkit("fd", n.mask)
             fk = vkidx[("fd", n.mask, 0, 0, 1)]
-        rec_info.append(({"vvv": 0, "psi": 1, "psibar": 2, "qq": 3}[n.kind], pa, pb, kk, fk))
+        rec_info.append(({"vvv": 0, "psi": 1, "psibar": 2, "qq": 3}[n.kind], pa, pb, kk, fk, rec_lc.get(key, -1)))
 
     def pick_order(spec):
         if spec is None:
@@ -300,13 +310,15 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
         now = [0]
         computed_once = set()
 
-        def ext_expr(key, out_lines):
+        def ext_expr(key, out_lines, lc=False):
             """Build an external wavefunction from its kit into a fresh local, return the name."""
             nonlocal flops_exec
             k = key[1]
             kind = g.nodes[key].kind
             nm = f"e{k}_{len(out_lines)}"
-            if kind == "ext_w":
+            if kind == "ext_v" and lc:
+                out_lines.append(f"    const vlcx<T> {nm} = vxxxxx_lc_kit<T>(tab + KLOFF{k}, hel({k}));")
+            elif kind == "ext_w":
                 out_lines.append(f"    const vw4<T> {nm} = ew_from_kit<T>(tab + KOFFW, hel(0), hel(2), hel(3));")
             elif kind == "ext_v":
                 nsv = -1 if k < 2 else 1
@@ -318,17 +330,31 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
             flops_exec += KIT_FLOPS[kind]
             return nm
 
-        def arg(key, pre):
+        def arg(key, pre, lc=False):
+            """The expression of an argument; lc: the vector of a fermion vertex, taken in
+            light-cone form where the table holds it (external gluons, recycled currents)."""
             if key[0] == "E":
-                return ext_expr(key, pre)
+                return ext_expr(key, pre, lc)
             if key in rec:  # the lane's helicity pair of a recycled wavefunction
                 a, b = (k[1] for k in g.nodes[key].args)
                 typ = "sp4" if g.nodes[key].kind in ("psi", "psibar") else "vw4"
                 nm = f"r{rec[key]}_{len(pre)}"
-                pre.append(f"    const {typ}<T> {nm} = recycled_{typ}<T>(tab + ROFF + {32 * rec[key]}, "
-                           f"(hel({a}) > 0 ? 16 : 0) + (hel({b}) > 0 ? 8 : 0));")
+                pair = f"(hel({a}) > 0 ? 16 : 0) + (hel({b}) > 0 ? 8 : 0)"
+                if lc and typ == "vw4":
+                    pre.append(f"    const vlc<T> {nm} = recycled_vlc<T>(tab + RLOFF + {32 * rec_lc[key]}, {pair});")
+                else:
+                    pre.append(f"    const {typ}<T> {nm} = recycled_{typ}<T>(tab + ROFF + {32 * rec[key]}, {pair});")
                 return nm
             return live[key]
+
+        def lc_form(key):
+            """Which form a fermion vertex gets its vector in: ':lcx' (external gluon), ':lc'
+            (recycled current) or '' (a current of this kernel, converted at the use)."""
+            if key[0] == "E" and g.nodes[key].kind == "ext_v":
+                return ":lcx"
+            if key in rec and g.nodes[key].kind not in ("psi", "psibar"):
+                return ":lc"
+            return ""
 
         def need(key, pinned):
             nonlocal flops_exec, flops_dag
@@ -338,7 +364,8 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
             for a in n.args:
                 need(a, pinned | {key})
             pre = []
-            args = [arg(a, pre) for a in n.args]
+            fermion_vertex = n.kind in ("psi", "psibar")
+            args = [arg(a, pre, lc=fermion_vertex and i == 1) for i, a in enumerate(n.args)]
             version[key] = version.get(key, -1) + 1
             v = f"w{node_ids[key]}" + (f"_{version[key]}" if version[key] else "")
             if n.kind == "vvv":
@@ -365,7 +392,8 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
             lines.extend(pre)
             lines.append(f"    {name_rest.replace(v + ' =', v + ' =', 1)}")
             lines.append("  }")
-            f = FLOPS[NODE_FLOPS[n.kind]] + (FD_FLOPS if fd and n.kind in ("vvv", "vvvv", "qq") else 0)
+            f = (FLOPS[NODE_FLOPS[n.kind] + (lc_form(n.args[1]) if fermion_vertex else "")]
+                 + (FD_FLOPS if fd and n.kind in ("vvv", "vvvv", "qq") else 0))
             flops_exec += f
             if key not in computed_once:
                 flops_dag += f
@@ -406,10 +434,10 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
             for k in amp.args:
                 need(k, set(amp.args))
             pre = []
-            args = [arg(k, pre) for k in amp.args]
+            args = [arg(k, pre, lc=amp.kind == "ffv" and i == 2) for i, k in enumerate(amp.args)]
             if amp.kind == "ffv":
                 call = f"ffv_amp<T>({args[0]}, {args[1]}, {args[2]})"
-                f = FLOPS["ffv_amp"]
+                f = FLOPS["ffv_amp" + lc_form(amp.args[2])]
             elif amp.kind == "vvv":
                 a, b, q = amp.args
                 call = (f"vvv_amp_k<T>({args[0]}, {args[1]}, {args[2]}, "
@@ -454,7 +482,8 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
                     del live[x]
         flops_exec += 2 * jamp_terms
         ext_name = {"ext_v": "vxxxxx", "ext_o": "oxxxxx", "ext_i": "ixxxxx", "ext_w": "ewkit"}
-        flops_dag += 2 * jamp_terms + sum(EXT_FLOPS[ext_name[g.nodes[k].kind]] for k in g.nodes if k[0] == "E")
+        # (the external states come from the per-event kits: their flops are in the table's count)
+        flops_dag += 2 * jamp_terms
         assert not jslot
         if jbudget:
             return lines, flops_exec, flops_dag, jamp_terms, nflush[0]
@@ -489,19 +518,21 @@ def emit_qcd(name: str, g, label: str, budget=(4, 12), prefetch=("", "all"), chu
     off = 4 * nq + nd
     for k in ext:
         koff[k] = off
-        off += 10 if g.nodes[("E", k)].kind == "ext_v" else 16  # both helicities
+        # both helicities; a gluon's kit is followed by its light-cone form
+        off += 20 if g.nodes[("E", k)].kind == "ext_v" else 16
     if dy:
         koff["W"] = off
         off += 8 * EW_ITEMS
     voff = off
     roff = off + vk_off[0]  # recycled wavefunctions: 4 helicity pairs x 8 reals each
-    ntab = roff + 32 * len(rec)
+    rlcoff = roff + 32 * len(rec)  # light-cone forms of the recycled currents, the same layout
+    ntab = rlcoff + 32 * len(rec_lc)
 
     def finish(lines, pf):
-        lines = [l.replace("DOFF", str(4 * nq)).replace("VOFF", str(voff)).replace("ROFF", str(roff))
-                 for l in lines]
+        lines = [l.replace("DOFF", str(4 * nq)).replace("VOFF", str(voff)).replace("RLOFF", str(rlcoff))
+                 .replace("ROFF", str(roff)) for l in lines]
         for k in koff:
-            lines = [l.replace(f"KOFF{k}", str(koff[k])) for l in lines]
+            lines = [l.replace(f"KLOFF{k}", str(koff[k] + 10)).replace(f"KOFF{k}", str(koff[k])) for l in lines]
         return "\n".join(prefetch_units(lines, bool(pf), kits=(pf != "table")))
 
     body_d = finish(lines_d, prefetch[0])
@@ -550,9 +581,11 @@ struct {name}_c{c} {{
     kind_code = {"ext_v": 0, "ext_o": 3 if dy else 1, "ext_i": 4 if dy else 2}
     kits = [(koff[k], kind_code[g.nodes[("E", k)].kind], k) if k in koff else (0, -1, k) for k in range(npar)]
     flops_table = DEN_FLOPS * nd + 4 * nq + 40 * len(ext)
+    flops_table += LC_KIT_FLOPS * sum(1 for k in ext if g.nodes[("E", k)].kind == "ext_v")
     flops_table += 4 * sum(FLOPS[NODE_FLOPS[g.nodes[k].kind]] + (FD_FLOPS if fd and g.nodes[k].kind in ("vvv", "qq") else 0)
                            for k in rec)  # each helicity pair once
-    rec_rows = [(kind, pa, pb, koff[pa], koff[pb], kk, fk) for kind, pa, pb, kk, fk in rec_info]
+    flops_table += 4 * LC_REC_FLOPS * len(rec_lc)
+    rec_rows = [(kind, pa, pb, koff[pa], koff[pb], kk, fk, lc) for kind, pa, pb, kk, fk, lc in rec_info]
     nrec = len(rec)
     qmass = "0.0" if dy else "prm.mT"  # mass of the quark line
     row_end = 1 if dy else TOP  # particle of the barred spinor at the quark line's end
@@ -690,8 +723,11 @@ struct {name} {{
   static constexpr int gs_power = {2 * len(gl)};  // |M|^2 carries g_s^gs_power
   static constexpr double iden = {iden_dy(len(gl)) if dy else iden_qcd(len(gl) - 2)};  // spin and colour average, identical gluons
   static constexpr double colour_denom = {D};
-  static constexpr double flops_per_hel = {flops_dag + cs_flops};  // each wavefunction counted once
-  static constexpr double flops_per_hel_executed = {flops_exec_d + cs_flops};  // with recomputation (double)
+  // algorithmic flops per helicity: every call once (wavefunctions once), jamp additions and
+  // the colour sum counted as 4 ncol^2 (the dense quadratic form; the symmetric VALU form
+  // executes {cs_flops}); executed: with recomputation, the symmetric colour sum (double)
+  static constexpr double flops_per_hel = {flops_dag + 4 * ncol * ncol};
+  static constexpr double flops_per_hel_executed = {flops_exec_d + cs_flops};
   static constexpr double flops_per_event = {flops_table};  // helicity-independent table
 
   // Per-event table (LDS): {nq} momentum sums (incoming momenta of the particles in the mask,
@@ -732,6 +768,9 @@ struct {name} {{
   static constexpr int rec_ob[{max(nrec, 1)}] = {{{", ".join(str(x[4]) for x in rec_rows) or "0"}}};
   static constexpr int rec_k[{max(nrec, 1)}] = {{{", ".join(str(x[5]) for x in rec_rows) or "0"}}};
   static constexpr int rec_fd[{max(nrec, 1)}] = {{{", ".join(str(x[6]) for x in rec_rows) or "0"}}};  // gauge kit (kinds 0, 3)
+  // currents (kinds 0, 3): index of the light-cone copy at rlcoff + 32 i, same pair layout
+  static constexpr int rlcoff = {rlcoff};
+  static constexpr int rec_lc[{max(nrec, 1)}] = {{{", ".join(str(x[7]) for x in rec_rows) or "0"}}};
   static constexpr bool fd_gauge = {"true" if fd else "false"};  // Feynman-diagram gauge for internal gluons
 
   // item i < 4 nrec: recycled wavefunction i / 4 for the helicity pair i % 4 (bit 1: first
@@ -748,6 +787,7 @@ struct {name} {{
                                 load_kit<T, 12>(tab + voff + rec_k[r]));
         if constexpr (fd_gauge) x = fd_project<T>(x, load_kit<T, 8>(tab + voff + rec_fd[r]));
         store_wf(x, o);
+        store_lc(vlc_of(x), w + rlcoff + 32 * rec_lc[r] + 8 * (i & 3));
         break;
       }}
       case 1:
@@ -763,6 +803,7 @@ struct {name} {{
                               dv<T>(tab, {4 * nq} + rec_k[r]));
         if constexpr (fd_gauge) x = fd_project<T>(x, load_kit<T, 8>(tab + voff + rec_fd[r]));
         store_wf(x, o);
+        store_lc(vlc_of(x), w + rlcoff + 32 * rec_lc[r] + 8 * (i & 3));
         break;
       }}
     }}
@@ -875,7 +916,10 @@ struct {name} {{
 #pragma unroll
       for (int k = 0; k < {npar}; ++k) {{
         if (j - nq - nd != k) continue;
-        if (kit_kind[k] == 0) vector_kit(p[k], k < 2 ? -1 : 1, tab + kit_off[k]);
+        if (kit_kind[k] == 0) {{
+          vector_kit(p[k], k < 2 ? -1 : 1, tab + kit_off[k]);
+          vector_lc_kit(p[k], k < 2 ? -1 : 1, tab + kit_off[k] + 10);
+        }}
         else if (kit_kind[k] > 0) fermion_kit(p[k], {fmass}, kit_kind[k], tab + kit_off[k]);
       }}
       return;
@@ -906,9 +950,9 @@ struct {name} {{
 }}  // namespace hme
 """
     info = dict(name=name, npar=npar, ncol=ncol, ndiag=g.ndiag, namp=len(g.amps), nwf=len(g.nodes),
-                flops_per_hel=flops_dag + cs_flops, flops_per_hel_executed=flops_exec_d + cs_flops,
+                flops_per_hel=flops_dag + 4 * ncol * ncol, flops_per_hel_executed=flops_exec_d + cs_flops,
                 flops_per_hel_executed_f32=flops_exec_f + cs_flops,
-                flops_colour=cs_flops, flops_table=flops_table, colour_denom=D, numerators=N,
+                flops_colour=4 * ncol * ncol, flops_colour_symmetric=cs_flops, flops_table=flops_table, colour_denom=D, numerators=N,
                 jamp_terms=jamp_terms, budget=list(budget), prefetch=list(prefetch), ntab=ntab,
                 nchunk=len(chunk_headers), nslot=nslot if chunks else 0, jbudget=jbudget if chunks else 0,
                 chunk_headers=chunk_headers)
