@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <utility>
 
+#include "colour_blocked.h"
 #include "colour_mfma.h"
 #include "me2_kernels.h"
 
@@ -63,6 +64,20 @@ template <class S> struct WsColumn {
     constexpr int bytes = Proc::nslot * Proc::nhel * (int)sizeof(cx<S>);
     return WsColumn{__builtin_amdgcn_make_buffer_rsrc(const_cast<cx<S>*>(event_base), 0, bytes, kRawBufferFlags),
                     column * (int)sizeof(cx<S>)};
+  }
+  // writes entry i of the column (the same offsets as operator[])
+  HME_FN void put(int64_t i, cx<S> v) const {
+    const int off = (int)(i * (int64_t)sizeof(cx<S>));
+    if constexpr (sizeof(S) == 4) {
+      typedef unsigned u32x2 __attribute__((vector_size(8)));
+      const u32x2 d = {__float_as_uint(v.r), __float_as_uint(v.i)};
+      __builtin_amdgcn_raw_buffer_store_b64(d, rsrc, lane_bytes, off, 0);
+    } else {
+      typedef unsigned u32x4 __attribute__((vector_size(16)));
+      const u32x4 d = {(unsigned)__double2loint(v.r), (unsigned)__double2hiint(v.r),
+                       (unsigned)__double2loint(v.i), (unsigned)__double2hiint(v.i)};
+      __builtin_amdgcn_raw_buffer_store_b128(d, rsrc, lane_bytes, off, 0);
+    }
   }
   HME_FN cx<S> operator[](int64_t i) const {
     const int off = (int)(i * (int64_t)sizeof(cx<S>));
@@ -163,6 +178,43 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
   for (int off = LPE / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
   if (!per_hel && sub == 0 && ev < nevt) out[ev] = acc * norm;
+}
+
+// FP64 colour sum in two kernels.  The 120 double jamps of a helicity need 480 registers, so
+// the gather form spills; instead fold_kernel adds each flow's slots (in slot order, the same
+// sums as the gather) and writes the result over the flow's first slot, with a few groups of
+// loads live at a time, and colour_blocked_kernel, a launch later, reads those 120 values back
+// in blocks for the symmetric colour sum.  Each lane folds and reads only its own helicity
+// column, and no slot is read after it is written within a kernel.
+template <class Proc>
+__global__ void __launch_bounds__(256)
+    fold_kernel(cx<double>* ws, int64_t nevt, int ngood, const int64_t* __restrict__ nevt_dev, int64_t e0) {
+  const int lane = threadIdx.x & 63;
+  nevt = sub_batch_events(nevt, nevt_dev, e0);
+  const int64_t ev = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (ev >= nevt) return;  // wave-uniform; no barrier follows
+  cx<double>* w = ws + (size_t)ev * Proc::nslot * Proc::nhel;
+  for (int k = lane; k < ngood; k += 64) Proc::template fold<double>(WsColumn<double>::template make<Proc>(w, k), Proc::nhel);
+}
+
+template <class Proc>
+__global__ void __launch_bounds__(256)
+    colour_blocked_kernel(const cx<double>* __restrict__ ws, double* __restrict__ out, int64_t nevt, int ngood,
+                          double norm, int per_hel, const int64_t* __restrict__ nevt_dev, int64_t e0) {
+  const int lane = threadIdx.x & 63;
+  nevt = sub_batch_events(nevt, nevt_dev, e0);
+  const int64_t ev = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (ev >= nevt) return;  // wave-uniform; no barrier follows
+  const cx<double>* w = ws + (size_t)ev * Proc::nslot * Proc::nhel;
+  double acc = 0.0;
+  for (int k = lane; k < ngood; k += 64) {
+    const double v = colour_sum_blocked<Proc, kColourBlock>(WsColumn<double>::template make<Proc>(w, k));
+    if (per_hel) out[(size_t)ev * ngood + k] = v;
+    acc += v;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (!per_hel && lane == 0) out[ev] = acc * norm;
 }
 
 // Select: also picks one helicity and one colour flow per event (the rule of
@@ -301,6 +353,12 @@ hipError_t launch_colour(const cx<S>* ws, double* out, int64_t nevt, int ngood, 
     else
       colour_mfma_kernel<Proc, false, S><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(ws, out, nevt, ngood, norm,
                                                                                        per_hel, nevt_dev, e0, goodhel, sel);
+  } else if constexpr (sizeof(S) == 8 && sizeof(C) == 8) {
+    static_assert(LPE == 64, "one event per wavefront");
+    // (the fold writes the workspace in place)
+    fold_kernel<Proc><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(const_cast<cx<S>*>(ws), nevt, ngood, nevt_dev, e0);
+    colour_blocked_kernel<Proc><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(ws, out, nevt, ngood, norm, per_hel,
+                                                                             nevt_dev, e0);
   } else {
     colour_kernel<Proc, LPE, S, C><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(ws, out, nevt, ngood, norm, per_hel,
                                                                                  nevt_dev, e0);

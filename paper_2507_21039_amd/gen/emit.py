@@ -640,17 +640,21 @@ struct {name}_c{c} {{
     if chunks:
         # flows in groups of about GATHER_GROUP slots: a group's loads are written before its
         # sums, so that many loads are in flight whatever order the compiler would pick
-        gl_lines, group, nload = [], [], 0
+        gl_lines, fold_lines, group, nload = [], [], [], 0
 
         def flush():
             if not group:
                 return
-            gl_lines.append("    {")
-            for _, sls in group:
-                gl_lines.extend(f"      const auto s{sl} = col[{sl} * stride];" for sl in sls)
+            for out in (gl_lines, fold_lines):
+                out.append("    {")
+                for _, sls in group:
+                    out.extend(f"      const auto s{sl} = col[{sl} * stride];" for sl in sls)
             for i, sls in group:
-                gl_lines.append(f"      jamp[{i}] = " + " + ".join(f"cast<T>(s{sl})" for sl in sls) + ";")
+                total = " + ".join(f"cast<T>(s{sl})" for sl in sls)
+                gl_lines.append(f"      jamp[{i}] = {total};")
+                fold_lines.append(f"      col.put({sls[0]} * stride, {total});")
             gl_lines.append("    }")
+            fold_lines.append("    }")
             group.clear()
 
         for i, w in enumerate(basis):
@@ -661,13 +665,20 @@ struct {name}_c{c} {{
             group.append((i, sls))
             nload += len(sls)
         flush()
+        jslot = [sorted(partials[w])[0] for w in basis]
         gather_code = (
             "  // the jamps of one helicity from the workspace column `col` (slot s at col[s * stride];\n"
             "  // col: a pointer to cx<S>, or an accessor with the same indexing): each flow is the sum of\n"
             "  // its partial slots, added in slot order; the loads of a group of flows come first\n"
             "  template <class T, class S, class Col>\n"
             f"  HME_FN static void gather(const Col& col, int64_t stride, cx<T> (&jamp)[{ncol}]) {{\n"
-            + "\n".join(gl_lines) + "\n  }\n\n")
+            + "\n".join(gl_lines) + "\n  }\n\n"
+            "  // the same sums, each written over its flow's first slot (jslot): the column then holds\n"
+            "  // the jamps at those slots (col: an accessor with put; no slot is read after it is written)\n"
+            f"  static constexpr short jslot[{ncol}] = {{{', '.join(map(str, jslot))}}};\n"
+            "  template <class T, class Col>\n"
+            "  HME_FN static void fold(const Col& col, int64_t stride) {\n"
+            + "\n".join(fold_lines) + "\n  }\n\n")
         amp_section = (f"  // the amplitude terms are split into {len(chunk_out)} contiguous pieces of the schedule\n"
                        f"  // ({name}_c0 .. {name}_c{len(chunk_out) - 1}); each runs as its own kernel and adds\n"
                        f"  // its terms to the jamps kept in a device workspace between kernels\n"

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <string>
 
+#include "../../paper_2507_21039_amd/csrc/colour_blocked.h"
 #include "../../paper_2507_21039_amd/csrc/params.h"
 #include "../../paper_2507_21039_amd/csrc/procs/ggttggg_c0.h"
 #include "../../paper_2507_21039_amd/csrc/procs/ggttggg_c1.h"
@@ -23,6 +24,19 @@
 namespace {
 using P = hme::P_ggttggg;
 static_assert(P::nchunk == 12, "update the piece list");
+
+// one helicity's slots as a column the fold can write (stride 1)
+template <class T> struct HostColumn {
+  hme::cx<T>* slots;
+  hme::cx<T> operator[](int64_t i) const { return slots[i]; }
+  void put(int64_t i, hme::cx<T> v) const { slots[i] = v; }
+};
+
+// the same slots read at the device layout's offsets (entry s at s * nhel)
+struct StrideNhel {
+  const hme::cx<double>* slots;
+  hme::cx<double> operator[](int64_t i) const { return slots[i / P::nhel]; }
+};
 
 // the pieces' partial jamps, one slot each, for one helicity; every slot written once
 template <class T> struct SlotSink {
@@ -75,9 +89,15 @@ void run(const hme::ProcParams& prm, double alpha_s, int64_t nevt, const double*
       add_piece<hme::P_ggttggg_c11, T>(prm, h, t, sink);
       for (bool x : written)
         if (!x) throw "slot never written";
-      hme::cx<T> jamp[P::ncol];
-      P::template gather<T, T>(slots, 1, jamp);
-      acc += (double)P::template colour_sum<T>(jamp) * norm;
+      if constexpr (sizeof(T) == 8) {
+        // the FP64 path of the GPU: fold in place, then the blocked colour sum
+        P::template fold<T>(HostColumn<T>{slots}, 1);
+        acc += hme::colour_sum_blocked<P, hme::kColourBlock>(StrideNhel{slots}) * norm;
+      } else {
+        hme::cx<T> jamp[P::ncol];
+        P::template gather<T, T>(slots, 1, jamp);
+        acc += (double)P::template colour_sum<T>(jamp) * norm;
+      }
     }
     out[e] = acc;
   }
