@@ -1,7 +1,7 @@
 """hme_compute_noalloc (the entry point that allocates nothing) against hme_compute, through
 the C ABI: bitwise the same |M|^2 on two calls in a row, the second with a smaller batch, for
-the process whose kernels use the workspace (gg -> ttbar ggg, sub-batches of the 256 MiB
-scratch) and for one that uses none (gg -> ttbar gg)."""
+the process whose kernels use the workspace (gg -> ttbar ggg in single and double precision,
+sub-batches of the 256 MiB scratch) and for one that uses none (gg -> ttbar gg)."""
 import numpy as np
 import pytest
 
@@ -29,6 +29,8 @@ def _both(h, p):
 
 @pytest.mark.parametrize("key,proc,prec,sizes", [
     ("ggttggg", hme.GGTTGGG, hme.MIXED_FAST, (1000, 333)),
+    # double workspace: 160-event sub-batches of the scratch array, FP64 colour sum by fold
+    ("ggttggg", hme.GGTTGGG, hme.FP64, (400, 97)),
     ("ggttgg", hme.GGTTGG, hme.FP64, (3001, 129)),
 ])
 def test_noalloc_equals_compute(card, key, proc, prec, sizes):
