@@ -117,7 +117,8 @@ int hme_compute(hme_handle* h, double alpha_s, int64_t nevt, const double* momen
  * results and errors, that allocates nothing.  The jamp workspace of HME_GGTTGGG comes from a
  * 256 MiB device array inside the library (one per device, held until the process ends,
  * its address looked up once per device by hme_create) instead of hipMallocAsync: batches
- * run in sub-batches of as many events as it holds (320 at 0.81 MB per event).  A process
+ * run in sub-batches of as many events as it holds (320 at 0.81 MB per event, 160 in the
+ * double-precision modes).  A process
  * whose workspace for 4 events exceeds 256 MiB is rejected with HME_E_BUDGET.  Other
  * processes use no workspace and run exactly as in hme_compute.  Every call on a device
  * shares that device's array: calls that overlap in time on one device (different streams,

@@ -34,10 +34,10 @@ DEPS = {
     "rambo.hip": ["../../include/hme.h"],
     **{f"proc_{p}.hip": _KERNEL_DEPS + [f"procs/{p}.h"] for p in _PROCS},
     **{f"proc_{p}_fd.hip": _KERNEL_DEPS + [f"procs/{p}_fd.h"] for p in _FD},
-    **{f"procs/{p}_c{c}.hip": _KERNEL_DEPS + ["piece_kernels.h", f"procs/{p}.h", f"procs/{p}_c{c}.h"]
+    **{f"procs/{p}_c{c}.hip": _KERNEL_DEPS + ["piece_kernels.h", "colour_blocked.h", f"procs/{p}.h", f"procs/{p}_c{c}.h"]
        for p, n in PIECES.items() for c in range(n)},
 }
-DEPS["proc_ggttggg.hip"] = DEPS["proc_ggttggg.hip"] + ["piece_kernels.h", "procs/ggttggg_chunks.h"]
+DEPS["proc_ggttggg.hip"] = DEPS["proc_ggttggg.hip"] + ["piece_kernels.h", "colour_blocked.h", "procs/ggttggg_chunks.h"]
 
 
 def hipcc() -> str:
