@@ -140,7 +140,8 @@ def hostlib7():
         pytest.skip("hipcc not available")
     src = os.path.join(HERE, "hostcheck", "hostcheck7.hip")
     procs = os.path.join(HERE, "..", "paper_2507_21039_amd", "csrc", "procs")
-    deps = [src] + [os.path.join(procs, f) for f in os.listdir(procs) if f.startswith("ggttggg")]
+    deps = [src] + [os.path.join(procs, f) for f in os.listdir(procs) if f.startswith("ggttggg")] + [
+        os.path.join(procs, "..", f) for f in ("colour_blocked.h", "helas.h", "params.h", "process.h")]
     if not os.path.exists(HOSTLIB7) or os.path.getmtime(HOSTLIB7) < max(os.path.getmtime(d) for d in deps):
         os.makedirs(os.path.dirname(HOSTLIB7), exist_ok=True)
         subprocess.run(["/opt/rocm/bin/hipcc", "-O1", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
