@@ -108,8 +108,8 @@ int hme_create(int process, const hme_sm_card* card, int precision, int device, 
  * hme_info.workspace_bytes_per_event (partial-jamp slots x helicities x the size of a
  * complex jamp: 789 x 128 x 8 bytes = 0.81 MB per event at HME_MIXED_FAST, twice that in the
  * double-precision modes), allocated and released on `hip_stream` in stream order (HME_E_OOM if
- * that fails); larger batches run as consecutive sub-batches of S events, S = 8192 at
- * HME_MIXED_FAST and 4096 at HME_FP64 and HME_MIXED_PAPER (8 GiB of workspace at most). */
+ * that fails); larger batches run as consecutive sub-batches of S = 16384 events (13 GB of
+ * workspace at HME_MIXED_FAST, 26 GB in the double-precision modes). */
 int hme_compute(hme_handle* h, double alpha_s, int64_t nevt, const double* momenta, double* me2, void* hip_stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight

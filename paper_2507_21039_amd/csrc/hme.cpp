@@ -58,8 +58,13 @@ static const ProcEntry kProcs[] = {
     {info_uueeggg, launch_me2_uueeggg, launch_hel_uueeggg, false, 1000.0},
 };
 
-// events per sub-batch of a process evaluated in pieces (workspace nslot * nhel * sizeof(cx) bytes each)
-constexpr int64_t kChunkSubBatch = 8192;
+// events per sub-batch of a process evaluated in pieces (workspace nslot * nhel * sizeof(cx) bytes
+// each: 13 GB in single, 26 GB in double precision).  Measured per 65,536 events of g g -> t tbar
+// g g g: FP64 152 / 132.5 ms and MIXED_PAPER 134.3 / 115.3 ms with sub-batches of 4,096 / 16,384
+// events (the double pieces run at 1 wave/SIMD, and the fold at 4 waves/SIMD on 4,096 events
+// did not fill the machine), MIXED_FAST 61.1 / 60.9 ms with 8,192 / 16,384.
+constexpr int64_t kChunkSubBatch = 16384;
+constexpr int64_t kChunkWorkspaceCap = int64_t(32) << 30;  // bytes
 constexpr int kNumProcs = sizeof(kProcs) / sizeof(kProcs[0]);
 
 }  // namespace hme
@@ -353,8 +358,8 @@ static int compute_impl(const char* who, hme_handle* h, double norm, int64_t nev
   hipError_t e;
   if (hme::handle_chunked(h)) {
     // jamp workspace, allocated and released in stream order
-    // at most 8192 events and 8 GiB per sub-batch (4096 events in double precision)
-    const int64_t cap = std::min<int64_t>(hme::kChunkSubBatch, (int64_t(8) << 30) / hme::handle_ws_bytes_per_event(h));
+    // at most kChunkSubBatch events and kChunkWorkspaceCap bytes per sub-batch
+    const int64_t cap = std::min<int64_t>(hme::kChunkSubBatch, hme::kChunkWorkspaceCap / hme::handle_ws_bytes_per_event(h));
     ws_events = nevt < cap ? nevt : cap;
     const size_t bytes = (size_t)ws_events * (size_t)hme::handle_ws_bytes_per_event(h);
     if ((e = hipMallocAsync(&ws, bytes, stream)) != hipSuccess)

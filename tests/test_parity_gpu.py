@@ -31,6 +31,7 @@ torch = pytest.importorskip("torch")
 FP64_TOL = 1e-12
 MIXED_TOL = 1e-5
 AS = 0.118
+SUB = 16384  # events per sub-batch of gg -> ttbar ggg in hme_compute (the library's kChunkSubBatch)
 
 CASES = [("eemumu", hme.EEMUMU, 16384), ("ggtt", hme.GGTT, 20011), ("ggttg", hme.GGTTG, 6007),
          ("ggttgg", hme.GGTTGG, 2003)]
@@ -290,7 +291,7 @@ def test_ggttggg_double_precision_modes(card, prec):
     """FP64 (double pieces and workspace, colour sum in double) and MIXED_PAPER (double pieces,
     single-precision colour sum on the matrix cores) on 2,048 events against the stored oracle
     values, with the FP64 gate (the long double oracle deciding) and the 1e-5 mixed gate; across
-    the 4,096-event sub-batch boundary the values are bitwise those of smaller calls."""
+    the sub-batch boundary the values are bitwise those of smaller calls."""
     print(f"[gpu] ggttggg precision={prec}", flush=True)
     p = configs.WORKLOADS["ggttggg"].momenta(2048)
     ref = golden_values("ggttggg_2048", p)
@@ -303,9 +304,9 @@ def test_ggttggg_double_precision_modes(card, prec):
             print(f"  {narb} events arbitrated")
         else:
             assert rel.max() <= MIXED_TOL
-        q = configs.WORKLOADS["ggttggg"].momenta(4096 + 300, first_event=9000)
+        q = configs.WORKLOADS["ggttggg"].momenta(SUB + 300, first_event=9000)
         whole = run(h, q)
-        for a, b in [(0, 64), (4090, 4100), (4095, 4396)]:
+        for a, b in [(0, 64), (SUB - 6, SUB + 4), (SUB - 1, SUB + 300)]:
             assert np.array_equal(run(h, q[a:b]), whole[a:b]), (a, b)
 
 
@@ -331,16 +332,16 @@ def test_ggttggg_mixed_fast_accuracy(h7, card):
 
 
 def test_ggttggg_sub_batches_and_edges(h7, card):
-    """Across the 8192-event sub-batch boundary and at ragged sizes, per-event values are bitwise
-    those of smaller calls; a few events on both sides of the boundary against the oracle."""
-    n = 8192 + 700
+    """Across the sub-batch boundary and at ragged sizes, per-event values are bitwise those of
+    smaller calls; a few events on both sides of the boundary against the oracle."""
+    n = SUB + 700
     p = configs.WORKLOADS["ggttggg"].momenta(n)
     print(f"[gpu] ggttggg sub-batches n={n}", flush=True)
     whole = run(h7, p)
     assert np.all(np.isfinite(whole)) and np.all(whole > 0)
-    for a, b in [(0, 1), (1, 64), (8188, 8198), (8191, n)]:
+    for a, b in [(0, 1), (1, 64), (SUB - 4, SUB + 6), (SUB - 1, n)]:
         assert np.array_equal(run(h7, p[a:b]), whole[a:b]), (a, b)
-    idx = np.array([0, 1, 8190, 8191, 8192, 8193, n - 1])
+    idx = np.array([0, 1, SUB - 2, SUB - 1, SUB, SUB + 1, n - 1])
     ref = oracle.me2(configs.GGTTGGG, p[idx], card, AS)
     assert np.abs(whole[idx] / ref - 1).max() <= 1e-3
 

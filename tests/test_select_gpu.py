@@ -26,6 +26,7 @@ CASES = [("eemumu", hme.EEMUMU, 3001), ("ggtt", hme.GGTT, 3001), ("ggttg", hme.G
          ("ggttgg", hme.GGTTGG, 257)]
 TOL = {hme.FP64: 1e-10, hme.MIXED_PAPER: 1e-5, hme.MIXED_FAST: 1e-3}
 AS = 0.118
+SUB = 16384  # events per sub-batch of gg -> ttbar ggg in hme_compute (the library's kChunkSubBatch)
 
 
 @pytest.fixture(scope="module")
@@ -128,10 +129,10 @@ def test_selection_full_size_sampled(card):
 
 
 def test_selection_ggttggg_across_sub_batches(card):
-    """gg -> ttbar ggg (pieces, single precision): 8192 + 300 events, so the second sub-batch
-    starts at event 8192; events on both sides of the boundary are checked."""
+    """gg -> ttbar ggg (pieces, single precision): SUB + 300 events, so the second sub-batch
+    starts at event SUB; events on both sides of the boundary are checked."""
     w = configs.WORKLOADS["ggttggg"]
-    nevt = 8192 + 300
+    nevt = SUB + 300
     p = w.momenta(nevt)
     rng = np.random.default_rng(23)
     r_hel, r_col = rng.random(nevt), rng.random(nevt)
@@ -147,7 +148,7 @@ def test_selection_ggttggg_across_sub_batches(card):
     pos = {int(g): i for i, g in enumerate(good)}
     tol = TOL[hme.MIXED_FAST]
     same_h = same_c = 0
-    idx = list(range(0, 30)) + list(range(8170, 8222)) + [nevt - 1]
+    idx = list(range(0, 30)) + list(range(SUB - 22, SUB + 30)) + [nevt - 1]
     for e in idx:
         mh = oracle.me2_hel(hme.GGTTGGG, p[e], card, AS)[good]
         Wc = np.zeros(120)
