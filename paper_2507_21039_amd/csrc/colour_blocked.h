@@ -65,7 +65,7 @@ template <class Proc, int B, class Col> HME_FN double colour_sum_blocked(const C
   return acc;
 }
 
-// flows per block of the FP64 colour sum: two blocks of double jamps, 160 registers, keep the
+// flows per block of the FP64 colour sum: two blocks of 20 double jamps (160 registers) keep the
 // kernel at 2 waves/SIMD (measured per 65,536 events of g g -> t tbar g g g: blocks of 12, 20
 // and 24 flows 152.7, 151.9 and 161.4 ms; 16 compiles to re-reads of every jamp at each use)
 constexpr int kColourBlock = 20;
